@@ -1,0 +1,474 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+high-precision evaluation of a definition, a library quadrature routine, adaptive
+integration, the continuum solution of a single-mode problem, convergence orders,
+and the exactness and Lipschitz properties the paper proves for parareal.
+"""
+import json
+import math
+import os
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.special as sp
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+
+
+# ------------------------------------------------------------------ L1 weights
+
+def _b_decimal(x: Decimal, alpha: Decimal) -> Decimal:
+    getcontext().prec = 60
+    e = 1 - alpha
+    if x == 0:
+        return Decimal(1)
+    return (x + 1) ** e - x ** e
+
+
+def test_weights_golden_alpha_half(orc):
+    g = GOLDEN["l1_weights_alpha_half"]
+    for j, v in g["values"].items():
+        assert orc.bweight(float(j), 0.5) == pytest.approx(v, rel=1e-15, abs=0)
+
+
+@pytest.mark.parametrize("alpha", [0.2, 0.3, 0.5, 0.7, 0.95])
+def test_weights_high_precision(orc, alpha):
+    """b_x = (x+1)^(1-a) - x^(1-a) (Section 2.1) at integer and hybrid x = m + r/S."""
+    a = Decimal(repr(alpha))
+    xs = [0, 1, 2, 3, 7, 63, 64, 100, 4095, 4096]
+    S = 16
+    xs_h = [(m * S + r) / S for m in (0, 1, 5, 63) for r in (1, 3, 8, 15, 16)]
+    for x in xs + xs_h:
+        ref = float(_b_decimal(Decimal(repr(float(x))), a))
+        got = orc.bweight(float(x), alpha)
+        assert got == pytest.approx(ref, rel=2e-15, abs=0), (x, got, ref)
+
+
+def test_weights_alpha_one(orc):
+    """At alpha = 1 the L1 weights are b_0 = 1 and b_x = 0 for x > 0 (backward Euler)."""
+    assert orc.bweight(0.0, 1.0) == 1.0
+    for x in (1.0, 0.5, 2.25, 4096.0):
+        assert orc.bweight(x, 1.0) == 0.0
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.6, 1.0])
+def test_weights_monotone_and_telescoping(orc, alpha):
+    """b_j decreases in j, and b_n + sum_{i=1}^n (b_{n-i} - b_{n-i+1}) = b_0 = 1 (the sum
+    used in the Lipschitz proof of Section 3.1)."""
+    b = [orc.bweight(float(j), alpha) for j in range(50)]
+    assert all(b[j] >= b[j + 1] for j in range(49))
+    for n in (1, 5, 49):
+        s = b[n] + sum(b[n - i] - b[n - i + 1] for i in range(1, n + 1))
+        assert s == pytest.approx(1.0, abs=1e-14)
+
+
+# ------------------------------------------------------------------ quadrature
+
+@pytest.mark.parametrize("Q", [1, 2, 3, 8, 33, 64, 384])
+def test_gauss_legendre_vs_library(orc, Q):
+    x, w = orc.gauss_legendre01(Q)
+    xr, wr = np.polynomial.legendre.leggauss(Q)
+    order = np.argsort(xr)
+    assert np.max(np.abs(x - (xr[order] + 1) / 2)) < 1e-15
+    assert np.max(np.abs(w - wr[order] / 2)) < 4e-16 * max(1, Q / 16)
+    assert abs(w.sum() - 1) < 1e-14
+
+
+def test_gauss_legendre_golden_and_exactness(orc):
+    g = GOLDEN["gauss_legendre_3pt_01"]
+    x, w = orc.gauss_legendre01(3)
+    assert np.allclose(x, g["x"], rtol=0, atol=4e-16)
+    assert np.allclose(w, g["w"], rtol=0, atol=4e-16)
+    for Q in (4, 12):
+        x, w = orc.gauss_legendre01(Q)
+        for p in range(2 * Q):
+            assert abs(np.dot(w, x ** p) - 1.0 / (p + 1)) < 1e-14
+
+
+# -------------------------------------------------------------------- Galerkin
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_constant_D_stiffness_is_diagonal(orc, dim):
+    """For constant D the sine basis diagonalises the bilinear form a(D;u,v) of
+    Section 2.1: K = D diag((k pi)^2), 2D: D diag(pi^2 (k1^2 + k2^2)).  With Q = 4M + 8
+    points the Gauss rule integrates cos(j pi x), j <= 2M, to rounding."""
+    M = 8 if dim == 1 else 5
+    p = orc.problem(dim=dim, modes=M, quad=4 * M + 8, d_sel=0, d_param=1.7)
+    Md = orc.nmodes(p)
+    K, F = orc.galerkin(p, np.zeros(Md), 0.0, 0.0)
+    if dim == 1:
+        lam = 1.7 * (np.arange(1, M + 1) * math.pi) ** 2
+    else:
+        k = np.arange(1, M + 1)
+        lam = 1.7 * math.pi ** 2 * (k[:, None] ** 2 + k[None, :] ** 2).reshape(-1)
+    assert np.max(np.abs(K - np.diag(lam))) < 1e-12 * lam.max()
+    assert np.all(F == 0)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_load_vector_closed_form(orc, dim):
+    """f = sin(pi x) e^{-t} (2D: times sin(pi y)) projects onto the first mode only:
+    (f, sqrt2 sin(pi x)) = e^{-t}/sqrt2 ; 2D: (f, 2 sin sin) = e^{-t}/2."""
+    M = 6 if dim == 1 else 4
+    p = orc.problem(dim=dim, modes=M, quad=4 * M + 8, d_sel=0, d_param=1.0, f_sel=4)
+    Md = orc.nmodes(p)
+    t = 0.37
+    _, F = orc.galerkin(p, np.zeros(Md), t, t)
+    ref = np.zeros(Md)
+    ref[0] = math.exp(-t) / (math.sqrt(2) if dim == 1 else 2.0)
+    assert np.max(np.abs(F - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("d_sel,f_sel", [(1, 2), (2, 3), (3, 2), (4, 4)])
+def test_nonlinear_assembly_vs_adaptive_integration(orc, d_sel, f_sel):
+    """K_kl = int D(x,t,u) phi_k' phi_l' dx and F_k = int f(x,t,u) phi_k dx with
+    u = sum c_k phi_k, checked against scipy's adaptive integrator (the quadrature
+    error of a 64-point Gauss rule on this smooth integrand is far below the tolerance)."""
+    M = 4
+    p = orc.problem(modes=M, quad=64, d_sel=d_sel, f_sel=f_sel, d_param=1.0)
+    c = np.array([0.3, -0.2, 0.1, 0.05])
+    t = 0.25
+
+    def u(x):
+        return sum(c[k] * math.sqrt(2) * math.sin((k + 1) * math.pi * x) for k in range(M))
+
+    def Dx(x):
+        uu = u(x)
+        return {1: 1 + 0.5 * math.sin(uu) ** 2, 2: 1 + 1 / (1 + uu * uu),
+                3: 1 + 0.5 * math.exp(-uu * uu), 4: 1 + uu}[d_sel]
+
+    def fx(x):
+        uu = u(x)
+        return {2: 0.1 * uu * (1 - uu), 3: math.sin(uu), 4: math.sin(math.pi * x) * math.exp(-t)}[f_sel]
+
+    def dphi(k, x):
+        return math.sqrt(2) * k * math.pi * math.cos(k * math.pi * x)
+
+    K, F = orc.galerkin(p, c, t, t)
+    for k in range(M):
+        Fk = si.quad(lambda x: fx(x) * math.sqrt(2) * math.sin((k + 1) * math.pi * x), 0, 1,
+                     epsabs=1e-14, epsrel=1e-14, limit=200)[0]
+        assert abs(F[k] - Fk) < 1e-12
+        for l in range(M):
+            Kkl = si.quad(lambda x: Dx(x) * dphi(k + 1, x) * dphi(l + 1, x), 0, 1,
+                          epsabs=1e-13, epsrel=1e-14, limit=200)[0]
+            assert abs(K[k, l] - Kkl) < 1e-10 * max(1.0, abs(Kkl)), (k, l, K[k, l], Kkl)
+    assert np.allclose(K, K.T, rtol=0, atol=1e-12)
+
+
+def test_step_system_is_spd(orc):
+    """I + tau K is symmetric positive definite (Section 2.1: the system is uniquely
+    solvable)."""
+    p = orc.problem(modes=12, quad=18, d_sel=2, f_sel=2)
+    rng = np.random.default_rng(3)
+    c = rng.normal(size=12) * 0.3
+    K, _ = orc.galerkin(p, c, 0.1, 0.1)
+    A = np.eye(12) + 0.01 * K
+    assert np.allclose(A, A.T, atol=1e-13)
+    assert np.linalg.eigvalsh(A).min() > 1.0 - 1e-12
+
+
+# ------------------------------------------------------------ closed-form solves
+
+def _mode1(dim):
+    return 1 / math.sqrt(2) if dim == 1 else 0.5
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("history", [0, 1])
+def test_alpha_one_backward_euler_closed_form(orc, dim, history):
+    """At alpha = 1 every L1 weight beyond b_0 vanishes and both the hybrid and the full
+    scheme reduce to backward Euler: the first mode of u0 = sin(pi x) (2D: sin sin) is
+    u0_1 (1 + lambda dt)^(-m) with lambda = dim pi^2 D."""
+    M = 4 if dim == 1 else 3
+    D = 0.8
+    p = orc.problem(dim=dim, modes=M, quad=4 * M + 8, steps=24, slices=4, alpha=1.0, d_sel=0,
+                    d_param=D, history=history)
+    Md = orc.nmodes(p)
+    u0 = np.zeros(Md)
+    u0[0] = _mode1(dim)
+    U, traj = orc.solve_serial(p, u0, want_traj=True)
+    dt = 1.0 / 24
+    lam = dim * math.pi ** 2 * D
+    m = np.arange(25)
+    ref = u0[0] * (1 + lam * dt) ** (-m)
+    assert np.max(np.abs(traj[:, 0] - ref) / ref) < 1e-13
+    assert np.max(np.abs(traj[:, 1:])) < 1e-15
+
+
+def test_alpha_half_mittag_leffler_limit(orc):
+    """Full uniform L1 with constant D = 1, f = 0, u0 = sin(pi x): the first mode tends to
+    u0_1 E_{1/2}(-pi^2 sqrt(t)) (continuum single-mode solution; golden value at t=1);
+    the error at t = 1 is first order in dt."""
+    g = GOLDEN["mittag_leffler_half"]
+    assert sp.erfcx(g["z"]) == pytest.approx(g["value"], rel=1e-13)
+    errs = []
+    for N in (64, 128, 256):
+        p = orc.problem(modes=1, quad=8, steps=N, slices=1, alpha=0.5, d_sel=0, d_param=1.0,
+                        history=1)
+        U = orc.solve_serial(p, np.array([1 / math.sqrt(2)]))
+        errs.append(abs(U[-1, 0] * math.sqrt(2) - g["value"]))
+    assert errs[-1] < 2e-3
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 1.6 < e0 / e1 < 2.4, errs
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.7])
+@pytest.mark.parametrize("history", [0, 1])
+def test_mittag_leffler_general_alpha(orc, alpha, history):
+    """Single mode, small lambda: E_alpha(-lambda t^alpha) by its power series (no
+    cancellation for lambda t^alpha < 1); the L1 solution converges to it as dt -> 0.
+    The hybrid scheme is refined with S = N/P fixed: its coarse-grid history carries an
+    O(dT) interpolation error (the hybrid-L1 truncation bound of Section 3.1), so it only
+    converges when the coarse grid is refined too."""
+    D = 0.05
+    lam = D * math.pi ** 2
+
+    def ml(z):
+        return sum((-z) ** k / sp.gamma(alpha * k + 1) for k in range(80))
+
+    ref = ml(lam)
+    errs = []
+    for N in (32, 64, 128):
+        p = orc.problem(modes=1, quad=8, steps=N, slices=N // 8, alpha=alpha, d_sel=0,
+                        d_param=D, history=history)
+        U = orc.solve_serial(p, np.array([1 / math.sqrt(2)]))
+        errs.append(abs(U[-1, 0] * math.sqrt(2) - ref))
+    assert errs[-1] < 2e-3
+    rates = [math.log2(e0 / e1) for e0, e1 in zip(errs, errs[1:])]
+    assert all(0.8 < r < 1.3 for r in rates), (errs, rates)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.8])
+def test_manufactured_nonlinear_order_one(orc, alpha):
+    """Manufactured solution U = (1 + t^alpha) sin(pi x) with D = 1 + sin(u)^2/2: the lagged
+    (semi-implicit) scheme converges at T with order about one (the lag is an O(dt)
+    consistency error; the solution is not C^2 in time, cf. the regularity model of
+    Section 3.1).  The exact solution is a single sine mode, so the error is temporal."""
+    errs = []
+    for N in (32, 64, 128):
+        p = orc.problem(modes=6, quad=24, steps=N, slices=4, alpha=alpha, d_sel=1, f_sel=1,
+                        history=0)
+        u0 = np.zeros(6)
+        u0[0] = 1 / math.sqrt(2)
+        U = orc.solve_serial(p, u0)
+        ex = np.zeros(6)
+        ex[0] = 2.0 / math.sqrt(2)
+        errs.append(np.linalg.norm(U[-1] - ex))
+    rates = [math.log2(e0 / e1) for e0, e1 in zip(errs, errs[1:])]
+    assert errs[-1] < 5e-3
+    assert all(0.75 < r < 1.4 for r in rates), (errs, rates)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
+def test_l1_operator_order_two_minus_alpha(orc, alpha):
+    """With no diffusion (test hook D = 0) and the source at the new time level, the scheme
+    is the L1 approximation of d^alpha y = f(t) with y = (1 + t^2) sin(pi x):
+    for C^2 data the L1 discretisation is of order 2 - alpha (remark after the hybrid-L1
+    truncation bound, Section 3.1)."""
+    errs = []
+    for N in (16, 32, 64, 128):
+        p = orc.problem(modes=2, quad=8, steps=N, slices=1, alpha=alpha, d_sel=-1, d_param=0.0,
+                        f_sel=5, history=1, source_time=1)
+        U = orc.solve_serial(p, np.array([1 / math.sqrt(2), 0.0]))
+        errs.append(abs(U[-1, 0] - 2 / math.sqrt(2)))
+    rates = [math.log2(e0 / e1) for e0, e1 in zip(errs, errs[1:])]
+    assert abs(rates[-1] - (2 - alpha)) < 0.08, rates
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.6])
+def test_smooth_mms_with_diffusion_order(orc, alpha):
+    """Constant D, smooth manufactured solution (1 + t^2) sin(pi x), source at the new time
+    level: the full L1-Galerkin scheme converges with order close to 2 - alpha."""
+    errs = []
+    for N in (32, 64, 128):
+        p = orc.problem(modes=3, quad=8, steps=N, slices=1, alpha=alpha, d_sel=0, d_param=0.5,
+                        f_sel=5, history=1, source_time=1)
+        U = orc.solve_serial(p, np.array([1 / math.sqrt(2), 0.0, 0.0]))
+        errs.append(abs(U[-1, 0] - 2 / math.sqrt(2)))
+    rates = [math.log2(e0 / e1) for e0, e1 in zip(errs, errs[1:])]
+    assert rates[-1] > (2 - alpha) - 0.25, (errs, rates)
+
+
+def test_hybrid_and_full_converge_to_same_limit(orc):
+    """The hybrid fine operator (coarse history) and the full uniform L1 scheme are two
+    discretisations of the same Caputo derivative: their gap shrinks (first order) as dt and
+    dT go to zero together (S fixed)."""
+    gaps = []
+    for N in (64, 128, 256):
+        base = dict(modes=4, quad=8, steps=N, slices=N // 8, alpha=0.5, d_sel=2, f_sel=2)
+        u0 = np.array([0.5, -0.2, 0.1, 0.05])
+        Uh = orc.solve_serial(orc.problem(history=0, **base), u0)
+        Uf = orc.solve_serial(orc.problem(history=1, **base), u0)
+        gaps.append(np.linalg.norm(Uh[-1] - Uf[-1]) / np.linalg.norm(Uf[-1]))
+    assert all(1.7 < g0 / g1 < 2.6 for g0, g1 in zip(gaps, gaps[1:])), gaps
+
+
+# -------------------------------------------------------------------- invariants
+
+def test_no_diffusion_no_source_is_stationary(orc):
+    """With D = 0 and f = 0 every propagator returns its input for a constant history."""
+    p = orc.problem(modes=3, quad=6, steps=12, slices=3, alpha=0.4, d_sel=-1, d_param=0.0)
+    u0 = np.array([0.3, -0.1, 0.7])
+    U = orc.solve_serial(p, u0)
+    assert np.max(np.abs(U - u0)) < 1e-15
+    Up, k, _, _ = orc.solve_parareal(p, u0, 3)
+    assert np.max(np.abs(Up - u0)) < 1e-15
+
+
+def test_alpha_one_hybrid_equals_full_bitwise(orc):
+    base = dict(modes=5, quad=8, steps=20, slices=5, alpha=1.0, d_sel=2, f_sel=2)
+    u0 = np.array([0.4, -0.3, 0.2, 0.1, -0.05])
+    Uh = orc.solve_serial(orc.problem(history=0, **base), u0)
+    Uf = orc.solve_serial(orc.problem(history=1, **base), u0)
+    assert np.array_equal(Uh, Uf)
+
+
+def test_single_slice_hybrid_equals_full_bitwise(orc):
+    """P = 1: the hybrid fine propagator has no coarse history and is the full L1 scheme."""
+    base = dict(modes=5, quad=8, steps=16, slices=1, alpha=0.6, d_sel=1, f_sel=3)
+    u0 = np.array([0.4, -0.3, 0.2, 0.1, -0.05])
+    Uh = orc.solve_serial(orc.problem(history=0, **base), u0)
+    Uf = orc.solve_serial(orc.problem(history=1, **base), u0)
+    assert np.array_equal(Uh, Uf)
+
+
+def test_coarse_history_difference_form_matches_expanded_form(orc):
+    """The coarse propagator's history b_n C_0 + sum (b_{n-i} - b_{n-i+1}) C_i (Section 2.1)
+    equals the difference form C_n - sum b_{n+1-i} (C_i - C_{i-1}) to rounding."""
+    p = orc.problem(modes=4, quad=8, steps=32, slices=8, alpha=0.35, d_sel=2, f_sel=2)
+    rng = np.random.default_rng(7)
+    C = rng.normal(size=(7, 4)) * 0.3
+    n = 6
+    b = lambda j: orc.bweight(float(j), p.alpha)
+    hist = b(n) * C[0] + sum((b(n - i) - b(n - i + 1)) * C[i] for i in range(1, n + 1))
+    tau_c = (1.0 / 8) ** p.alpha * math.gamma(2 - p.alpha)
+    tn = 1.0 * n * 4 / 32
+    ref = orc.step(p, C[n], tn, tn, hist, tau_c)
+    got = orc.coarse_G(p, n, C)
+    assert np.max(np.abs(got - ref)) < 1e-14
+
+
+# ----------------------------------------------------------------------- parareal
+
+@pytest.mark.parametrize("alpha", [0.3, 0.7, 1.0])
+def test_parareal_exactness(orc, alpha):
+    """After k sweeps the first k+1 slice ends equal the serial (fine) solution bitwise, and
+    after P sweeps all of them do (finite termination, Section 3.2; fixed point Section 2.2)."""
+    P = 5
+    p = orc.problem(modes=5, quad=8, steps=P * 3, slices=P, alpha=alpha, d_sel=2, f_sel=2)
+    u0 = np.array([0.5, -0.3, 0.2, 0.1, -0.05])
+    Us = orc.solve_serial(p, u0)
+    U, k, incr, its = orc.solve_parareal(p, u0, P, tol=0.0, want_iterates=True)
+    assert k == P
+    assert np.array_equal(U, Us)
+    for kk in range(P + 1):
+        assert np.array_equal(its[kk][: kk + 1], Us[: kk + 1]), kk
+
+
+def test_parareal_single_fine_step_converges_in_one_sweep(orc):
+    """S = 1 makes the fine propagator identical to the coarse one: one sweep reproduces the
+    serial solution and the coarse prediction already equals it."""
+    p = orc.problem(modes=4, quad=8, steps=6, slices=6, alpha=0.45, d_sel=3, f_sel=3)
+    u0 = np.array([0.5, -0.3, 0.2, 0.1])
+    Us = orc.solve_serial(p, u0)
+    U, k, incr, its = orc.solve_parareal(p, u0, 3, tol=0.0, want_iterates=True)
+    assert np.array_equal(its[0], Us)
+    assert np.array_equal(U, Us)
+    assert np.all(incr == 0.0)
+
+
+def test_parareal_single_slice_is_serial(orc):
+    p = orc.problem(modes=4, quad=8, steps=12, slices=1, alpha=0.45, d_sel=1, f_sel=2)
+    u0 = np.array([0.5, -0.3, 0.2, 0.1])
+    U, k, _, _ = orc.solve_parareal(p, u0, 1)
+    assert k == 1
+    assert np.array_equal(U, orc.solve_serial(p, u0))
+
+
+def test_parareal_converges_geometrically(orc):
+    """Errors against the serial solution decrease over the sweeps (Theorem of Section 3.2;
+    the paper observes convergence in a few iterations)."""
+    P = 16
+    p = orc.problem(modes=6, quad=9, steps=P * 4, slices=P, alpha=0.5, d_sel=2, f_sel=2)
+    rng = np.random.default_rng(0)
+    u0 = rng.normal(size=6) * (np.arange(1, 7) ** -1.5)
+    Us = orc.solve_serial(p, u0)
+    _, k, incr, its = orc.solve_parareal(p, u0, 8, tol=0.0, want_iterates=True)
+    errs = [np.linalg.norm(it - Us) / np.linalg.norm(Us) for it in its]
+    assert errs[-1] < 1e-3 * errs[0]
+    assert all(e1 <= e0 * 1.0001 for e0, e1 in zip(errs, errs[1:]))
+
+
+def test_parareal_tolerance_stop(orc):
+    P = 8
+    p = orc.problem(modes=4, quad=6, steps=P * 4, slices=P, alpha=0.5, d_sel=2, f_sel=2)
+    u0 = np.array([0.5, -0.3, 0.2, 0.1])
+    _, k, incr, _ = orc.solve_parareal(p, u0, P, tol=1e-6)
+    assert incr[-1] <= 1e-6 or k == P
+    assert all(i > 1e-6 for i in incr[:-1])
+
+
+def test_coarse_propagator_lipschitz_linear_case(orc):
+    """Proposition (Lipschitz, Section 3.1) with linear diffusion (C = L_f = 0):
+    ||G_n(V) - G_n(W)|| <= max_i ||V_i - W_i|| (L2 norm = coefficient 2-norm)."""
+    p = orc.problem(modes=6, quad=12, steps=40, slices=10, alpha=0.4, d_sel=0, d_param=0.7,
+                    f_sel=4)
+    rng = np.random.default_rng(11)
+    for n in (0, 1, 4, 9):
+        V = rng.normal(size=(n + 1, 6))
+        W = V + rng.normal(size=(n + 1, 6)) * 0.1
+        lhs = np.linalg.norm(orc.coarse_G(p, n, V) - orc.coarse_G(p, n, W))
+        rhs = max(np.linalg.norm(V[i] - W[i]) for i in range(n + 1))
+        assert lhs <= rhs * (1 + 1e-12)
+
+
+def test_fine_propagator_lipschitz_linear_case(orc):
+    """Proposition (Lipschitz, Section 3.1), fine propagator, C = L_f = 0: one fine step
+    moves the difference by at most max_{i<r}||Z1_i - Z2_i|| + sqrt(2 b_{r/S}) S^-a E with
+    E = max_j ||V_j - W_j||; over S steps ||F_n(V) - F_n(W)|| <= E (1 + sum_r sqrt(2 b_{r/S}) S^-a)."""
+    S, P, a = 4, 6, 0.4
+    p = orc.problem(modes=5, quad=10, steps=S * P, slices=P, alpha=a, d_sel=0, d_param=0.7,
+                    f_sel=4)
+    rng = np.random.default_rng(5)
+    bound_fac = 1 + sum(math.sqrt(2 * orc.bweight(r / S, a)) * S ** -a for r in range(1, S + 1))
+    for n in (1, 3, 5):
+        V = rng.normal(size=(n + 1, 5))
+        W = V + rng.normal(size=(n + 1, 5)) * 0.1
+        E = max(np.linalg.norm(V[i] - W[i]) for i in range(n + 1))
+        lhs = np.linalg.norm(orc.fine_F(p, n, V) - orc.fine_F(p, n, W))
+        assert lhs <= E * bound_fac
+
+
+def test_validation_rejects_bad_problems(orc):
+    good = dict(modes=4, quad=8, steps=8, slices=4, alpha=0.5, d_sel=0, d_param=1.0)
+    assert orc.validate(orc.problem(**good))
+    bad = [dict(alpha=0.0), dict(alpha=1.5), dict(T=0.0), dict(steps=10), dict(quad=3),
+           dict(d_sel=9), dict(d_param=0.0), dict(f_sel=7), dict(dim=3),
+           dict(source_time=1, f_sel=2)]
+    for b in bad:
+        kw = dict(good)
+        kw.update(b)
+        assert not orc.validate(orc.problem(**kw)), b
+
+
+@pytest.mark.parametrize("S", [1, 3, 5])
+def test_parareal_linear_scalar_binomial_closed_form(orc, S):
+    """alpha = 1, constant D, f = 0, one sine mode: G and F are the scalar linear maps
+    g = 1/(1 + lam dT) and f = (1 + lam dt)^-S, and the parareal correction of Section 2.2
+    gives the truncated binomial expansion of (g + (f - g))^n:
+        U^k_n = sum_{j=0}^{min(k,n)} C(n,j) (f-g)^j g^(n-j) u0."""
+    P, D = 7, 0.6
+    lam = D * math.pi ** 2
+    p = orc.problem(modes=1, quad=16, steps=P * S, slices=P, alpha=1.0, d_sel=0, d_param=D)
+    u0 = 1 / math.sqrt(2)
+    _, k, _, its = orc.solve_parareal(p, np.array([u0]), P, tol=0.0, want_iterates=True)
+    g = 1.0 / (1.0 + lam / P)
+    fm = (1.0 + lam / (P * S)) ** (-S)
+    for kk in range(k + 1):
+        for n in range(P + 1):
+            ref = sum(math.comb(n, j) * (fm - g) ** j * g ** (n - j) for j in range(min(kk, n) + 1)) * u0
+            assert its[kk][n, 0] == pytest.approx(ref, rel=1e-13, abs=1e-17), (kk, n)
