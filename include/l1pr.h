@@ -1,0 +1,138 @@
+/*
+ * l1pr — parareal-in-time, L1-in-time, sine-Galerkin-in-space solver for the
+ * quasilinear Caputo subdiffusion equation
+ *
+ *     d^alpha_t u = div( D(x,t,u) grad u ) + f(x,t,u)   on (0,1)^dim,  u = 0 on the boundary,
+ *     u(x,0) = u0(x),
+ *
+ * for MI355X (gfx950).  Method: arXiv 2510.11023, "Parareal in time and spectral in space
+ * fast L1 quasilinear subdiffusion solver" (Caballero, Plociniczak, Sadarangani).
+ *
+ * Space.  Orthonormal sine basis phi_k(x) = sqrt(2) sin(k pi x), k = 1..M (2D: the tensor
+ * product 2 sin(k1 pi x) sin(k2 pi y), coefficient index (k1-1)*M + (k2-1)), so the Galerkin
+ * mass matrix is the identity.  The stiffness K_kl = sum_q w_q D(x_q,t,u_q) phi_k'(x_q) phi_l'(x_q)
+ * and the load F_k = sum_q w_q f(x_q,t,u_q) phi_k(x_q) use Gauss-Legendre quadrature on (0,1)
+ * with Q points per direction (the weak form of Section 2.1 with quadrature).
+ *
+ * Time.  Uniform coarse grid T_n = n T/P (P parareal slices) and fine grid of N = P*S steps.
+ *   - coarse propagator G (Section 2.1, semi-implicit sequential L1 scheme, step T/P):
+ *       (I + tau_c K(C_n)) C_{n+1} = C_n - sum_{i=1}^{n} b_{n+1-i} (C_i - C_{i-1}) + tau_c F(C_n)
+ *   - fine propagator F (Section 2.2, hybrid L1: fine grid in the current slice, coarse grid
+ *     for the history), for r = 1..S starting at c_0 = C_n:
+ *       (I + tau K(c_{r-1})) c_r = c_{r-1} - sum_{j=1}^{r-1} b_{r-j} (c_j - c_{j-1})
+ *                                 - S^-alpha sum_{i=1}^{n} b_{n-i+r/S} (C_i - C_{i-1}) + tau F(c_{r-1})
+ *   with b_x = (x+1)^(1-alpha) - x^(1-alpha), b_0 = 1, tau = dt^alpha Gamma(2-alpha),
+ *   tau_c = dT^alpha Gamma(2-alpha); D and f lagged to the previous level.
+ *   - parareal (Section 2.2 and its flowchart): coarse initial sweep, then per sweep k the
+ *     fine propagator on all slices at once and the sequential correction
+ *       U^{k+1}_{n+1} = F_n(U^k_0..U^k_n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_n(U^k_0..U^k_n)).
+ *     After k sweeps the first k+1 slice ends equal the serial solution exactly, so at most
+ *     P sweeps reproduce it bit for bit.
+ *
+ * Conventions of every entry point.
+ *   - Pointers marked "device" point to device memory of the current HIP device; the caller
+ *     owns every buffer (the library allocates nothing and never frees caller memory).
+ *   - Vectors of coefficients are float64, contiguous, with Md = M (1D) or M*M (2D)
+ *     entries, ordered by mode number.
+ *   - Every call is asynchronous and stream-ordered on `stream` (a hipStream_t passed as a
+ *     void*; NULL means the default stream), except where a host-side stop test is asked for
+ *     (parareal with tol > 0), which synchronises the stream once per sweep.
+ *   - Problems are validated on the host before anything is launched; an invalid problem
+ *     returns L1PR_EINVAL and touches nothing.
+ *   - No C++ exception crosses this boundary.
+ */
+#ifndef L1PR_H
+#define L1PR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  L1PR_OK = 0,
+  L1PR_EINVAL = -1,     /* invalid problem or argument */
+  L1PR_ENOMEM = -2,     /* workspace smaller than l1pr_workspace_bytes() */
+  L1PR_EHIP = -3,       /* HIP runtime error */
+  L1PR_ENOTCONV = -4,   /* parareal stopped at max_iter < P without meeting tol; U holds the last iterate */
+  L1PR_ENONFINITE = -5  /* a parareal increment was NaN or infinite (tol > 0 only) */
+} l1pr_status;
+
+/* Diffusion selectors D(x,t,u). */
+enum { L1PR_D_CONST = 0,      /* d_param (> 0)                 */
+       L1PR_D_SIN2 = 1,       /* 1 + sin(u)^2 / 2              */
+       L1PR_D_RATIONAL = 2,   /* 1 + 1/(1 + u^2)               */
+       L1PR_D_GAUSS = 3,      /* 1 + exp(-u^2) / 2             */
+       L1PR_D_LINEAR = 4 };   /* 1 + u (the paper's model problem, Section 4.2) */
+
+/* Source selectors f(x,t,u).  s(x) = sin(pi x) (2D: sin(pi x) sin(pi y)). */
+enum { L1PR_F_ZERO = 0,
+       L1PR_F_MMS_SIN2 = 1,   /* manufactured: U = (1 + t^alpha) s is exact for D = L1PR_D_SIN2 */
+       L1PR_F_LOGISTIC = 2,   /* 0.1 u (1 - u)                 */
+       L1PR_F_SIN = 3,        /* sin(u)                        */
+       L1PR_F_PAPER = 4,      /* s(x) exp(-t) (Section 4.2)    */
+       L1PR_F_MMS_SMOOTH = 5  /* manufactured: U = (1 + t^2) s is exact for constant D = d_param */ };
+
+typedef struct {
+  int32_t dim;          /* 1 or 2 */
+  int32_t modes;        /* M per direction, >= 1 */
+  int32_t quad;         /* Q per direction, >= M */
+  int32_t steps;        /* N fine steps, N % P == 0 */
+  int32_t slices;       /* P parareal slices (coarse steps) */
+  double  alpha;        /* fractional order in (0, 1] (used when no per-instance alpha is given) */
+  double  T;            /* final time > 0 */
+  int32_t d_sel;        /* L1PR_D_*  */
+  double  d_param;      /* constant D for L1PR_D_CONST (> 0); the D of L1PR_F_MMS_SMOOTH */
+  int32_t f_sel;        /* L1PR_F_*  */
+  int32_t history;      /* 0: hybrid fine propagator (the paper's; parareal's fixed point)
+                           1: full uniform L1 over all N steps (serial only) */
+  int32_t source_time;  /* 0: f lagged to the previous level (the paper)
+                           1: f at the new time level (only for u-independent f) */
+} l1pr_problem;
+
+/* Operation codes for l1pr_workspace_bytes. */
+enum { L1PR_OP_SERIAL = 0, L1PR_OP_PARAREAL = 1 };
+
+/* Bytes of device workspace that an operation needs for `batch` instances. */
+size_t l1pr_workspace_bytes(const l1pr_problem* p, int32_t batch, int32_t op);
+
+/* Returns L1PR_OK if the problem is valid, L1PR_EINVAL otherwise (host only). */
+l1pr_status l1pr_validate(const l1pr_problem* p);
+
+/* Serial solve of `batch` independent instances: the fine solution C_{n+1} = F_n(C_0..C_n)
+ * (history = 0; the fixed point of parareal, Section 2.2) or the full uniform L1 scheme
+ * (history = 1).
+ *   alpha : host [batch] per-instance fractional orders, or NULL to use p->alpha for all.
+ *   u0    : device [batch][Md]           initial coefficients.
+ *   U     : device [batch][P+1][Md]      output slice ends C_0..C_P.
+ *   traj  : device [batch][N+1][Md]      output fine trajectory, or NULL.
+ *   ws    : device workspace of ws_bytes >= l1pr_workspace_bytes(p, batch, L1PR_OP_SERIAL). */
+l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double* alpha,
+                              const double* u0, double* U, double* traj,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Parareal solve of `batch` instances (hybrid history only), Section 2.2.
+ *   max_iter : number of fine sweeps allowed, 0 <= max_iter <= P.
+ *   tol      : > 0 stops after the sweep whose relative increment
+ *              max_b ||U^{k+1}_b - U^k_b|| / ||U^{k+1}_b|| (Frobenius over all P+1 slice ends)
+ *              is <= tol (one stream synchronisation per sweep); <= 0 runs exactly
+ *              min(max_iter, P) sweeps with no synchronisation.
+ *   U        : device [batch][P+1][Md]   output: the last iterate.
+ *   U_iters  : device [max_iter+1][batch][P+1][Md] every iterate (0 = coarse prediction), or NULL.
+ *   incr     : device [batch][max_iter] relative increment of each sweep, or NULL.
+ *   iters    : host int32, number of sweeps done, or NULL.
+ * Returns L1PR_ENOTCONV if tol > 0 was not met within max_iter < P sweeps. */
+l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const double* alpha,
+                                const double* u0, double* U, int32_t max_iter, double tol,
+                                double* U_iters, double* incr, int32_t* iters,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* l1pr_status_string(l1pr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,78 @@
+"""ctypes binding of libl1pr.so (include/l1pr.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  PyTorch
+supplies device memory and the current stream.  The library must be built
+(``python -m paper_2510_11023_amd.build``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libl1pr.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
+OP_SERIAL, OP_PARAREAL = 0, 1
+
+
+class Problem(ctypes.Structure):
+    """Mirror of l1pr_problem."""
+
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("modes", ctypes.c_int32),
+        ("quad", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("slices", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("T", ctypes.c_double),
+        ("d_sel", ctypes.c_int32),
+        ("d_param", ctypes.c_double),
+        ("f_sel", ctypes.c_int32),
+        ("history", ctypes.c_int32),
+        ("source_time", ctypes.c_int32),
+    ]
+
+
+class L1prError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_2510_11023_amd.build); there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        pp = ctypes.POINTER(Problem)
+        L.l1pr_workspace_bytes.argtypes = [pp, ctypes.c_int32, ctypes.c_int32]
+        L.l1pr_workspace_bytes.restype = ctypes.c_size_t
+        L.l1pr_validate.argtypes = [pp]
+        L.l1pr_validate.restype = ctypes.c_int
+        L.l1pr_solve_serial.argtypes = [pp, ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.l1pr_solve_serial.restype = ctypes.c_int
+        L.l1pr_solve_parareal.argtypes = [pp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
+                                          ctypes.c_double, vp, vp, ctypes.POINTER(ctypes.c_int32),
+                                          vp, ctypes.c_size_t, vp]
+        L.l1pr_solve_parareal.restype = ctypes.c_int
+        L.l1pr_status_string.argtypes = [ctypes.c_int]
+        L.l1pr_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().l1pr_status_string(int(status)).decode()
+
+
+EXPORTED = ["l1pr_workspace_bytes", "l1pr_validate", "l1pr_solve_serial", "l1pr_solve_parareal",
+            "l1pr_status_string"]

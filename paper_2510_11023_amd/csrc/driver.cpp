@@ -1,0 +1,395 @@
+// Host orchestration and the C-ABI of libl1pr.
+//
+// serial (hybrid):  for n = 0..P-1, r = 1..S: one step over the B instances (units = B).
+// serial (full):    for m = 0..N-1: one full-history step over the B instances.
+// parareal:         coarse initial sweep (P steps, units = B); then per sweep the fine
+//                   propagator of all B*P (instance, slice) units in lockstep (S steps,
+//                   units = B*P) followed by the sequential correction sweep (P steps,
+//                   units = B) and the increment reduction (Section 2.2, flowchart).
+// Everything is enqueued on the caller's stream; nothing is allocated.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "l1pr_internal.h"
+
+namespace l1pr {
+
+size_t solve_lds_bytes(int Mp);
+
+namespace {
+
+constexpr int kMaxMp1D = 400;
+
+struct Layout {
+  size_t total = 0;
+  size_t xq, wq, phi, phiT, dphi, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
+};
+
+size_t take(size_t& cur, size_t bytes) {
+  const size_t off = cur;
+  cur += (bytes + 255) / 256 * 256;
+  return off;
+}
+
+bool valid(const l1pr_problem* p) {
+  if (!p) return false;
+  if (p->dim != 1) return false;  // the GPU path covers 1D
+  if (p->modes < 1 || p->quad < p->modes) return false;
+  if (roundup(p->modes, 16) > kMaxMp1D) return false;
+  if (p->steps < 1 || p->slices < 1 || p->steps % p->slices != 0) return false;
+  if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return false;
+  if (!(p->T > 0.0) || !std::isfinite(p->T)) return false;
+  if (p->d_sel < L1PR_D_CONST || p->d_sel > L1PR_D_LINEAR) return false;
+  if (p->d_sel == L1PR_D_CONST && !(p->d_param > 0.0)) return false;
+  if (p->f_sel < L1PR_F_ZERO || p->f_sel > L1PR_F_MMS_SMOOTH) return false;
+  if (p->history != 0 && p->history != 1) return false;
+  if (p->source_time != 0 && p->source_time != 1) return false;
+  if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
+  return true;
+}
+
+void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
+  tb.dim = p->dim;
+  tb.M = p->modes;
+  tb.Q = p->quad;
+  tb.Mp = roundup(p->modes, 16);
+  tb.Qp = roundup(p->quad, 16);
+  tb.N = p->steps;
+  tb.P = p->slices;
+  tb.S = p->steps / p->slices;
+  tb.B = B;
+  tb.LB = p->history == 1 ? p->steps + 1 : std::max(tb.S, tb.P) + 1;
+  tb.d_sel = p->d_sel;
+  tb.f_sel = p->f_sel;
+  tb.source_time = p->source_time;
+  tb.d_param = p->d_param;
+  tb.T = p->T;
+  const size_t D = sizeof(double);
+  const size_t Mp = tb.Mp, Qp = tb.Qp, P = tb.P, S = tb.S, N = tb.N;
+  size_t cur = 0;
+  L.xq = take(cur, D * Qp);
+  L.wq = take(cur, D * Qp);
+  L.phi = take(cur, D * Qp * Mp);
+  L.phiT = take(cur, D * Qp * Mp);
+  L.dphi = take(cur, D * Qp * Mp);
+  L.inst = take(cur, D * B * NSCAL);
+  L.bw = take(cur, D * B * tb.LB);
+  L.bhyb = take(cur, D * B * P * S);
+  L.alpha = take(cur, D * B);
+  L.Z0 = take(cur, D * B * (P + 1) * Mp);
+  const bool para = (op == L1PR_OP_PARAREAL);
+  L.Z1 = para ? take(cur, D * B * (P + 1) * Mp) : 0;
+  L.Gold = para ? take(cur, D * B * P * Mp) : 0;
+  size_t units;
+  if (para) {
+    units = (size_t)B * P;
+    L.traj = take(cur, D * units * (S + 1) * Mp);
+  } else {
+    units = B;
+    L.traj = take(cur, D * B * ((p->history == 1 ? N : S) + 1) * Mp);
+  }
+  L.d = take(cur, D * units * Qp);
+  L.rhs = take(cur, D * units * Mp);
+  L.A = take(cur, D * units * Mp * Mp);
+  L.incrk = take(cur, D * B);
+  L.total = cur;
+}
+
+struct Ctx {
+  Tables tb;
+  Layout L;
+  char* ws;
+  hipStream_t s;
+  double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+};
+
+#define L1PR_TRY(expr)                          \
+  do {                                          \
+    if ((expr) != hipSuccess) return L1PR_EHIP; \
+  } while (0)
+
+l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, void* ws,
+                  size_t ws_bytes, void* stream, Ctx& c) {
+  if (!valid(p) || B < 1 || !ws) return L1PR_EINVAL;
+  if (op == L1PR_OP_PARAREAL && p->history != 0) return L1PR_EINVAL;
+  std::vector<double> al(B, p->alpha);
+  if (alpha) {
+    for (int b = 0; b < B; ++b) {
+      if (!(alpha[b] > 0.0 && alpha[b] <= 1.0)) return L1PR_EINVAL;
+      al[b] = alpha[b];
+    }
+  }
+  make_layout(p, B, op, c.L, c.tb);
+  if (ws_bytes < c.L.total) return L1PR_ENOMEM;
+  c.ws = static_cast<char*>(ws);
+  c.s = static_cast<hipStream_t>(stream);
+  Tables& tb = c.tb;
+  tb.xq = c.ptr(c.L.xq);
+  tb.wq = c.ptr(c.L.wq);
+  tb.phi = c.ptr(c.L.phi);
+  tb.phiT = c.ptr(c.L.phiT);
+  tb.dphi = c.ptr(c.L.dphi);
+  tb.inst = c.ptr(c.L.inst);
+  tb.bw = c.ptr(c.L.bw);
+  tb.bhyb = c.ptr(c.L.bhyb);
+  if (alpha)  // pageable source: the copy is staged before the call returns
+    L1PR_TRY(hipMemcpyAsync(c.ptr(c.L.alpha), al.data(), sizeof(double) * B, hipMemcpyHostToDevice, c.s));
+  else
+    L1PR_TRY(launch_fill(c.ptr(c.L.alpha), B, p->alpha, c.s));
+  L1PR_TRY(launch_tables(tb, c.ptr(c.L.xq), c.ptr(c.L.wq), c.ptr(c.L.phi), c.ptr(c.L.phiT),
+                         c.ptr(c.L.dphi), c.ptr(c.L.inst), c.ptr(c.L.bw), c.ptr(c.L.bhyb),
+                         c.ptr(c.L.alpha), c.s));
+  return L1PR_OK;
+}
+
+// eval + assemble + solve for `units` units
+l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
+  L1PR_TRY(launch_eval(c.tb, a, units, c.s));
+  L1PR_TRY(launch_assemble(c.tb, a, units, c.s));
+  L1PR_TRY(launch_solve(c.tb, a, e, units, c.s));
+  return L1PR_OK;
+}
+
+StepArgs base_args(const Ctx& c) {
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.d = c.ptr(c.L.d);
+  a.rhs = c.ptr(c.L.rhs);
+  a.A = c.ptr(c.L.A);
+  return a;
+}
+
+l1pr_status serial_hybrid(const Ctx& c, const double* u0, double* U, double* traj_out) {
+  const Tables& tb = c.tb;
+  const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp, M = tb.M;
+  const long vecP = (long)(P + 1) * Mp, slotS = (long)(S + 1) * Mp;
+  double* Z = c.ptr(c.L.Z0);
+  double* traj = c.ptr(c.L.traj);
+  L1PR_TRY(launch_pack(u0, M, B, M, Z, Mp, vecP, c.s));
+  if (traj_out) L1PR_TRY(launch_unpack(Z, Mp, vecP, traj_out, M, (long)(tb.N + 1) * M, 1, B, c.s));
+  for (int n = 0; n < P; ++n) {
+    L1PR_TRY(launch_copy_rows(Z + (long)n * Mp, vecP, traj, slotS, 1, Mp, B, c.s));
+    for (int r = 1; r <= S; ++r) {
+      StepArgs a = base_args(c);
+      a.mode = MODE_FINE;
+      a.r = r;
+      a.nP = 1;
+      a.n_lo = n;
+      a.traj = traj;
+      a.trajP = 1;
+      a.trajN0 = n;
+      a.Z = Z;
+      Epilogue e{};
+      e.kind = (r == S) ? EPI_STORE2 : EPI_STORE;
+      e.out = traj + (long)r * Mp;
+      e.out_stride = slotS;
+      e.gold = Z + (long)(n + 1) * Mp;
+      e.gold_stride = vecP;
+      l1pr_status st = run_step(c, a, e, B);
+      if (st != L1PR_OK) return st;
+    }
+    if (traj_out)
+      L1PR_TRY(launch_unpack(traj + Mp, Mp, slotS, traj_out + ((long)n * S + 1) * M, M,
+                             (long)(tb.N + 1) * M, S, B, c.s));
+  }
+  L1PR_TRY(launch_unpack(Z, Mp, vecP, U, M, (long)(P + 1) * M, P + 1, B, c.s));
+  return L1PR_OK;
+}
+
+l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_out) {
+  const Tables& tb = c.tb;
+  const int B = tb.B, P = tb.P, S = tb.S, N = tb.N, Mp = tb.Mp, M = tb.M;
+  const long trajN = (long)(N + 1) * Mp;
+  double* traj = c.ptr(c.L.traj);
+  L1PR_TRY(launch_pack(u0, M, B, M, traj, Mp, trajN, c.s));
+  for (int m = 0; m < N; ++m) {
+    StepArgs a = base_args(c);
+    a.mode = MODE_FULL;
+    a.m = m;
+    a.traj = traj;
+    Epilogue e{};
+    e.kind = EPI_STORE;
+    e.out = traj + (long)(m + 1) * Mp;
+    e.out_stride = trajN;
+    l1pr_status st = run_step(c, a, e, B);
+    if (st != L1PR_OK) return st;
+  }
+  for (int n = 0; n <= P; ++n)
+    L1PR_TRY(launch_unpack(traj + (long)n * S * Mp, Mp, trajN, U + (long)n * M, M,
+                           (long)(P + 1) * M, 1, B, c.s));
+  if (traj_out) L1PR_TRY(launch_unpack(traj, Mp, trajN, traj_out, M, (long)(N + 1) * M, N + 1, B, c.s));
+  return L1PR_OK;
+}
+
+// One coarse step G_n over all instances; `e` decides what is stored.
+l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e) {
+  StepArgs a = base_args(c);
+  a.mode = MODE_COARSE;
+  a.n = n;
+  a.Z = Z;
+  return run_step(c, a, e, c.tb.B);
+}
+
+l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, double tol,
+                     double* U_iters, double* incr, int* iters_out) {
+  const Tables& tb = c.tb;
+  const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp, M = tb.M;
+  const long vecP = (long)(P + 1) * Mp, slotS = (long)(S + 1) * Mp;
+  double* Zk = c.ptr(c.L.Z0);
+  double* Zk1 = c.ptr(c.L.Z1);
+  double* Gold = c.ptr(c.L.Gold);
+  double* traj = c.ptr(c.L.traj);
+  double* incrk = c.ptr(c.L.incrk);
+  const long iterStride = (long)B * (P + 1) * M;
+
+  // coarse initial sweep: U^0_{n+1} = G_n(U^0_0..U^0_n), G_old(n) = the same value
+  L1PR_TRY(launch_pack(u0, M, B, M, Zk, Mp, vecP, c.s));
+  for (int n = 0; n < P; ++n) {
+    Epilogue e{};
+    e.kind = EPI_STORE2;
+    e.out = Zk + (long)(n + 1) * Mp;
+    e.out_stride = vecP;
+    e.gold = Gold + (long)n * Mp;
+    e.gold_stride = (long)P * Mp;
+    l1pr_status st = coarse_step(c, Zk, n, e);
+    if (st != L1PR_OK) return st;
+  }
+  if (U_iters) L1PR_TRY(launch_unpack(Zk, Mp, vecP, U_iters, M, (long)(P + 1) * M, P + 1, B, c.s));
+
+  int done = 0;
+  bool met = false;
+  std::vector<double> h_incr(B);
+  for (int k = 0; k < max_iter; ++k) {
+    // parallel stage: F_old(n) = F_n(U^k_0..U^k_n) for all (b, n)
+    L1PR_TRY(launch_fill_slot0(tb, Zk, traj, B, P, c.s));
+    for (int r = 1; r <= S; ++r) {
+      StepArgs a = base_args(c);
+      a.mode = MODE_FINE;
+      a.r = r;
+      a.nP = P;
+      a.n_lo = 0;
+      a.traj = traj;
+      a.trajP = P;
+      a.trajN0 = 0;
+      a.Z = Zk;
+      Epilogue e{};
+      e.kind = EPI_STORE;
+      e.out = traj + (long)r * Mp;
+      e.out_stride = slotS;
+      l1pr_status st = run_step(c, a, e, B * P);
+      if (st != L1PR_OK) return st;
+    }
+    // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n))
+    L1PR_TRY(launch_pack(u0, M, B, M, Zk1, Mp, vecP, c.s));
+    for (int n = 0; n < P; ++n) {
+      Epilogue e{};
+      e.kind = EPI_CORRECT;
+      e.out = Zk1 + (long)(n + 1) * Mp;
+      e.out_stride = vecP;
+      e.gold = Gold + (long)n * Mp;
+      e.gold_stride = (long)P * Mp;
+      e.fold = traj + ((long)n * (S + 1) + S) * Mp;
+      e.fold_stride = (long)P * slotS;
+      l1pr_status st = coarse_step(c, Zk1, n, e);
+      if (st != L1PR_OK) return st;
+    }
+    L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, c.s));
+    if (U_iters)
+      L1PR_TRY(launch_unpack(Zk1, Mp, vecP, U_iters + (long)(k + 1) * iterStride, M,
+                             (long)(P + 1) * M, P + 1, B, c.s));
+    std::swap(Zk, Zk1);
+    done = k + 1;
+    if (done >= P) {
+      met = true;
+      break;
+    }
+    if (tol > 0.0) {
+      L1PR_TRY(hipMemcpyAsync(h_incr.data(), incrk, sizeof(double) * B, hipMemcpyDeviceToHost, c.s));
+      L1PR_TRY(hipStreamSynchronize(c.s));
+      double mx = 0.0;
+      for (double v : h_incr) {
+        if (!std::isfinite(v)) {
+          if (iters_out) *iters_out = done;
+          return L1PR_ENONFINITE;
+        }
+        mx = std::max(mx, v);
+      }
+      if (mx <= tol) {
+        met = true;
+        break;
+      }
+    }
+  }
+  L1PR_TRY(launch_unpack(Zk, Mp, vecP, U, M, (long)(P + 1) * M, P + 1, B, c.s));
+  if (iters_out) *iters_out = done;
+  if (tol > 0.0 && !met) return L1PR_ENOTCONV;
+  return L1PR_OK;
+}
+
+}  // namespace
+}  // namespace l1pr
+
+using namespace l1pr;
+
+extern "C" {
+
+l1pr_status l1pr_validate(const l1pr_problem* p) { return valid(p) ? L1PR_OK : L1PR_EINVAL; }
+
+size_t l1pr_workspace_bytes(const l1pr_problem* p, int32_t batch, int32_t op) {
+  if (!valid(p) || batch < 1 || (op != L1PR_OP_SERIAL && op != L1PR_OP_PARAREAL)) return 0;
+  Layout L;
+  Tables tb;
+  make_layout(p, batch, op, L, tb);
+  return L.total;
+}
+
+l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double* alpha,
+                              const double* u0, double* U, double* traj, void* ws,
+                              size_t ws_bytes, void* stream) {
+  try {
+    if (!u0 || !U) return L1PR_EINVAL;
+    Ctx c;
+    l1pr_status st = setup(p, batch, L1PR_OP_SERIAL, alpha, ws, ws_bytes, stream, c);
+    if (st != L1PR_OK) return st;
+    return p->history == 1 ? serial_full(c, u0, U, traj) : serial_hybrid(c, u0, U, traj);
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
+l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const double* alpha,
+                                const double* u0, double* U, int32_t max_iter, double tol,
+                                double* U_iters, double* incr, int32_t* iters, void* ws,
+                                size_t ws_bytes, void* stream) {
+  try {
+    if (!u0 || !U || !p) return L1PR_EINVAL;
+    if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
+    Ctx c;
+    l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
+    if (st != L1PR_OK) return st;
+    int it = 0;
+    st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it);
+    if (iters) *iters = it;
+    return st;
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
+const char* l1pr_status_string(l1pr_status s) {
+  switch (s) {
+    case L1PR_OK: return "ok";
+    case L1PR_EINVAL: return "invalid problem or argument";
+    case L1PR_ENOMEM: return "workspace too small";
+    case L1PR_EHIP: return "HIP runtime error";
+    case L1PR_ENOTCONV: return "parareal did not meet the tolerance within max_iter sweeps";
+    case L1PR_ENONFINITE: return "non-finite parareal increment";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

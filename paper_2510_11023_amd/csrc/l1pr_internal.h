@@ -1,0 +1,158 @@
+// Internal definitions shared by the HIP sources of libl1pr (not part of the C-ABI).
+//
+// Data layout in device memory (all float64 unless stated):
+//   - coefficient vectors are padded from M to Mp = roundup(M, 16) entries (the padded
+//     basis functions are identically zero, so padded entries stay exactly 0);
+//   - quadrature is padded from Q to Qp = roundup(Q, 16) nodes with zero weight;
+//   - phi [Qp][Mp]  = sqrt2 sin(k pi x_q),  phiT [Mp][Qp] its transpose,
+//     dphi[Qp][Mp]  = sqrt2 k pi cos(k pi x_q);
+//   - per-instance tables: scalars inst[b][NSCAL], L1 weights bw[b][LB] = b_j,
+//     hybrid weights bhyb[b][m*S + r-1] = b_{m + r/S};
+//   - slice ends Z[b][P+1][Mp]; fine trajectories traj[slot][S+1][Mp];
+//   - per-unit step buffers d[u][Qp] (w_q D), rhs[u][Mp], A[u][Mp][Mp] (row-major, the
+//     lower triangle is what the factorisation reads).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "l1pr.h"
+
+namespace l1pr {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// per-instance scalar slots
+enum { IS_ALPHA = 0, IS_TAU, IS_TAUC, IS_SFAC, IS_G1A, IS_G3A, NSCAL = 8 };
+
+// kinds of step
+enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
+
+// epilogue kinds of the solve kernel
+enum { EPI_STORE = 0, EPI_STORE2 = 1, EPI_CORRECT = 2 };
+
+struct Tables {
+  int dim, M, Q, Mp, Qp, N, P, S, B, LB;
+  int d_sel, f_sel, source_time;
+  double d_param, T;
+  const double* xq;
+  const double* wq;
+  const double* phi;
+  const double* phiT;
+  const double* dphi;
+  const double* inst;
+  const double* bw;
+  const double* bhyb;
+};
+
+// What one step-launch computes for each of its units.
+struct StepArgs {
+  int mode;
+  int r;        // MODE_FINE: fine step 1..S
+  int n;        // MODE_COARSE: slice
+  int nP, n_lo; // MODE_FINE: unit u -> instance u / nP, slice n_lo + u % nP
+  int m;        // MODE_FULL: the step computes c_{m+1}
+  double* traj; // MODE_FINE: slots [B*trajP][S+1][Mp]; MODE_FULL: [B][N+1][Mp]
+  int trajP, trajN0;
+  const double* Z;  // slice-end sequence [B][P+1][Mp]
+  double* d;        // [units][Qp]
+  double* rhs;      // [units][Mp]
+  double* A;        // [units][Mp][Mp]
+};
+
+struct Epilogue {
+  int kind;
+  double* out;
+  long out_stride;   // doubles between consecutive units
+  double* gold;
+  long gold_stride;
+  const double* fold;
+  long fold_stride;
+};
+
+__host__ __device__ inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+// L1 weight b_x = (x+1)^(1-a) - x^(1-a), b_0 = 1; written as x^(1-a) (exp((1-a) log(1+1/x)) - 1)
+// so that large x loses no digits to cancellation.
+__device__ inline double l1_weight(double x, double a) {
+  if (x == 0.0) return 1.0;
+  const double e = 1.0 - a;
+  return pow(x, e) * expm1(e * log1p(1.0 / x));
+}
+
+// Diffusion coefficient by selector.
+__device__ inline double coef_D(int sel, double dparam, double u) {
+  switch (sel) {
+    case L1PR_D_CONST: return dparam;
+    case L1PR_D_SIN2: { const double s = sin(u); return 1.0 + 0.5 * s * s; }
+    case L1PR_D_RATIONAL: return 1.0 + 1.0 / (1.0 + u * u);
+    case L1PR_D_GAUSS: return 1.0 + 0.5 * exp(-u * u);
+    case L1PR_D_LINEAR: return 1.0 + u;
+  }
+  return 0.0;
+}
+
+// Source by selector at (x, y, t) with state u (y unused in 1D).
+__device__ inline double coef_f(const Tables& tb, const double* inst, double x, double y,
+                                double t, double u) {
+  const double a = inst[IS_ALPHA];
+  switch (tb.f_sel) {
+    case L1PR_F_ZERO: return 0.0;
+    case L1PR_F_MMS_SIN2: {
+      // U = (1 + t^a) s,  f = Gamma(1+a) s - D(U) lap U - D'(U) |grad U|^2, D = 1 + sin^2/2
+      const double At = 1.0 + pow(t, a);
+      const double sx = sin(kPi * x), cx = cos(kPi * x);
+      double s, grad2;
+      if (tb.dim == 1) {
+        s = sx;
+        grad2 = At * At * kPi * kPi * cx * cx;
+      } else {
+        const double sy = sin(kPi * y), cy = cos(kPi * y);
+        s = sx * sy;
+        grad2 = At * At * kPi * kPi * (cx * cx * sy * sy + sx * sx * cy * cy);
+      }
+      const double U = At * s;
+      const double sU = sin(U);
+      const double DU = 1.0 + 0.5 * sU * sU;
+      return inst[IS_G1A] * s + DU * (tb.dim * kPi * kPi * U) - 0.5 * sin(2.0 * U) * grad2;
+    }
+    case L1PR_F_LOGISTIC: return 0.1 * u * (1.0 - u);
+    case L1PR_F_SIN: return sin(u);
+    case L1PR_F_PAPER: {
+      double s = sin(kPi * x);
+      if (tb.dim == 2) s *= sin(kPi * y);
+      return s * exp(-t);
+    }
+    case L1PR_F_MMS_SMOOTH: {
+      double s = sin(kPi * x);
+      if (tb.dim == 2) s *= sin(kPi * y);
+      return (2.0 * pow(t, 2.0 - a) / inst[IS_G3A] + tb.dim * tb.d_param * kPi * kPi * (1.0 + t * t)) * s;
+    }
+  }
+  return 0.0;
+}
+
+// fine time level t_m = T m / N
+__device__ inline double t_level(const Tables& tb, long m) { return (tb.T * (double)m) / (double)tb.N; }
+
+// ---- launchers (implemented in the .hip files) ----
+hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
+                         double* dphi, double* inst, double* bw, double* bhyb,
+                         const double* alpha_dev, hipStream_t s);
+hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
+hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
+hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
+hipError_t launch_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                        hipStream_t s);
+hipError_t launch_pack(const double* src, int M, int B, long src_stride, double* dst, int Mp,
+                       long dst_stride, hipStream_t s);
+hipError_t launch_copy_rows(const double* src, long src_unit_stride, double* dst,
+                            long dst_unit_stride, int rows, int Mp, int units, hipStream_t s);
+hipError_t launch_fill_slot0(const Tables& tb, const double* Z, double* traj, int B, int P,
+                             hipStream_t s);
+hipError_t launch_unpack(const double* src, int Mp, long src_stride, double* dst, int M,
+                         long dst_stride, int rows_per_unit, int units, hipStream_t s);
+hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
+                            double* incr_out, int incr_stride, int k, double* incr_k,
+                            hipStream_t s);
+
+}  // namespace l1pr

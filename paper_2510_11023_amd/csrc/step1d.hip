@@ -1,0 +1,480 @@
+// One semi-implicit L1-Galerkin step for many units at once (1D sine basis).
+//
+// A "unit" is one system to solve at this step: an (instance, slice) pair of the fine
+// sweep, an instance of the coarse sweep, or an instance of the full-history sweep.
+// Each step is three launches over all units:
+//   k_eval1d     u_q = sum_k phi_k(x_q) c_k at the lagged state, d_q = w_q D(x_q,t,u_q),
+//                g_q = w_q f(x_q,t,u_q), the load F = phi^T g, the L1 history sums and the
+//                right-hand side rhs = hist + tau F            (Sections 2.1 and 2.2)
+//   k_assemble1d A = I + tau dphi^T diag(d) dphi, lower tiles only, FP64 MFMA 16x16x4
+//   k_solve1d    A = L L^T (blocked right-looking Cholesky, MFMA trailing updates),
+//                forward and backward substitution, then the epilogue that stores the new
+//                state (or applies the parareal correction F_old + (G_new - G_old)).
+// The arithmetic of a unit never depends on the other units of the launch, so a unit's
+// result is bit-for-bit the same in a serial sweep and in a parareal sweep.
+#include "l1pr_internal.h"
+
+namespace l1pr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct UnitView {
+  int b, n;
+  const double* y;   // sequence whose last entry is the lagged state
+  int L;             // index of that last entry
+  const double* z;   // coarse sequence for the hybrid history (MODE_FINE) or nullptr
+  int nz;
+  long m_prev;       // fine index of the lagged time level
+  long m_src;        // fine index of the new time level (source_time = 1)
+  int tau_slot;      // IS_TAU or IS_TAUC
+  long slot;         // trajectory slot (MODE_FINE)
+};
+
+__device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int u) {
+  UnitView v;
+  const long vecP = (long)(tb.P + 1) * tb.Mp;
+  if (a.mode == MODE_FINE) {
+    v.b = u / a.nP;
+    v.n = a.n_lo + u % a.nP;
+    v.slot = (long)v.b * a.trajP + (v.n - a.trajN0);
+    v.y = a.traj + v.slot * (long)(tb.S + 1) * tb.Mp;
+    v.L = a.r - 1;
+    v.z = a.Z + v.b * vecP;
+    v.nz = v.n;
+    v.m_prev = (long)v.n * tb.S + a.r - 1;
+    v.m_src = v.m_prev + 1;
+    v.tau_slot = IS_TAU;
+  } else if (a.mode == MODE_COARSE) {
+    v.b = u;
+    v.n = a.n;
+    v.slot = u;
+    v.y = a.Z + v.b * vecP;
+    v.L = a.n;
+    v.z = nullptr;
+    v.nz = 0;
+    v.m_prev = (long)a.n * tb.S;
+    v.m_src = (long)(a.n + 1) * tb.S;
+    v.tau_slot = IS_TAUC;
+  } else {
+    v.b = u;
+    v.n = 0;
+    v.slot = u;
+    v.y = a.traj + (long)v.b * (tb.N + 1) * tb.Mp;
+    v.L = a.m;
+    v.z = nullptr;
+    v.nz = 0;
+    v.m_prev = a.m;
+    v.m_src = a.m + 1;
+    v.tau_slot = IS_TAU;
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------------------ eval
+__global__ __launch_bounds__(256) void k_eval1d(Tables tb, StepArgs a) {
+  extern __shared__ double sm[];
+  const int u = blockIdx.x, tid = threadIdx.x;
+  const int Mp = tb.Mp, Qp = tb.Qp;
+  double* sc = sm;       // lagged state c [Mp]
+  double* sg = sm + Mp;  // w_q f_q       [Qp]
+  const UnitView v = decode_unit(tb, a, u);
+  const double* ins = tb.inst + (long)v.b * NSCAL;
+  const double tD = t_level(tb, v.m_prev);
+  const double tf = tb.source_time ? t_level(tb, v.m_src) : tD;
+
+  for (int k = tid; k < Mp; k += blockDim.x) sc[k] = v.y[(long)v.L * Mp + k];
+  __syncthreads();
+
+  double* dout = a.d + (long)u * Qp;
+  for (int q = tid; q < Qp; q += blockDim.x) {
+    double uq = 0.0;
+    for (int k = 0; k < Mp; ++k) uq += tb.phiT[(long)k * Qp + q] * sc[k];
+    const double x = tb.xq[q], w = tb.wq[q];
+    dout[q] = w * coef_D(tb.d_sel, tb.d_param, uq);
+    sg[q] = w * coef_f(tb, ins, x, 0.0, tf, uq);
+  }
+  __syncthreads();
+
+  const double tau = ins[v.tau_slot];
+  const double* bw = tb.bw + (long)v.b * tb.LB;
+  const double* bh = tb.bhyb ? tb.bhyb + (long)v.b * tb.P * tb.S : nullptr;
+  for (int k = tid; k < Mp; k += blockDim.x) {
+    double F = 0.0;
+    for (int q = 0; q < Qp; ++q) F += tb.phi[(long)q * Mp + k] * sg[q];
+    // in-sequence L1 history: y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1})
+    double acc = 0.0;
+    for (int i = 1; i <= v.L; ++i)
+      acc += bw[v.L + 1 - i] * (v.y[(long)i * Mp + k] - v.y[(long)(i - 1) * Mp + k]);
+    double h = v.y[(long)v.L * Mp + k] - acc;
+    if (a.mode == MODE_FINE) {
+      // coarse-grid history of the hybrid operator: S^-a sum_{i=1}^{n} b_{n-i+r/S} (C_i - C_{i-1})
+      double acc2 = 0.0;
+      for (int i = 1; i <= v.nz; ++i)
+        acc2 += bh[(long)(v.nz - i) * tb.S + (a.r - 1)] *
+                (v.z[(long)i * Mp + k] - v.z[(long)(i - 1) * Mp + k]);
+      h = h - ins[IS_SFAC] * acc2;
+    }
+    a.rhs[(long)u * Mp + k] = h + tau * F;
+  }
+}
+
+// -------------------------------------------------------------------------- assemble
+// Tile (I, J), I >= J, of TB x TB entries of A = I + tau dphi^T diag(d) dphi.  Quadrature
+// points stream through LDS in chunks of 16; each wave owns TPW x TPW MFMA 16x16 tiles.
+// MFMA f64 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16]; the
+// accumulator holds D[l/16 + 4v][l%16] in element v.
+template <int TB>
+__global__ __launch_bounds__(256) void k_assemble1d(Tables tb, StepArgs a) {
+  constexpr int NW = (TB == 16) ? 1 : 4;
+  constexpr int TPW = (TB == 64) ? 2 : 1;
+  constexpr int QC = 16;
+  __shared__ double sA[QC][TB + 1];
+  __shared__ double sB[QC][TB + 1];
+  const int t = blockIdx.x, u = blockIdx.y;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = (NW == 4) ? (wave >> 1) : 0, wj = (NW == 4) ? (wave & 1) : 0;
+  const int Mp = tb.Mp, Qp = tb.Qp;
+  const double* d = a.d + (long)u * Qp;
+
+  d4 acc[TPW][TPW];
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TPW; ++tj) acc[ti][tj] = d4{0.0, 0.0, 0.0, 0.0};
+
+  for (int q0 = 0; q0 < Qp; q0 += QC) {
+    for (int e = threadIdx.x; e < QC * TB; e += NW * 64) {
+      const int qq = e / TB, c = e % TB;
+      const double* row = tb.dphi + (long)(q0 + qq) * Mp;
+      sA[qq][c] = row[I * TB + c];
+      sB[qq][c] = d[q0 + qq] * row[J * TB + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < QC / 4; ++kk) {
+      const int kq = kk * 4 + (lane >> 4);
+      double af[TPW], bf[TPW];
+#pragma unroll
+      for (int ti = 0; ti < TPW; ++ti) af[ti] = sA[kq][wi * 16 * TPW + ti * 16 + (lane & 15)];
+#pragma unroll
+      for (int tj = 0; tj < TPW; ++tj) bf[tj] = sB[kq][wj * 16 * TPW + tj * 16 + (lane & 15)];
+#pragma unroll
+      for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TPW; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ti], bf[tj], acc[ti][tj], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  const int b = (a.mode == MODE_FINE) ? u / a.nP : u;
+  const double tau = tb.inst[(long)b * NSCAL + ((a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU)];
+  double* A = a.A + (long)u * Mp * Mp;
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TPW; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = I * TB + wi * 16 * TPW + ti * 16 + (lane >> 4) + 4 * e;
+        const int col = J * TB + wj * 16 * TPW + tj * 16 + (lane & 15);
+        A[(long)row * Mp + col] = tau * acc[ti][tj][e] + (row == col ? 1.0 : 0.0);
+      }
+}
+
+// ----------------------------------------------------------------------------- solve
+// One work-group (4 waves) per unit.  Right-looking Cholesky by 16-column blocks:
+//   (1) wave 0 factors the 16x16 diagonal block in registers (one row per lane, values
+//       exchanged by shuffles) and solves its part of L y = rhs;
+//   (2) every thread takes one row of the panel below it: L_ij = A_ij L_jj^-T, and updates
+//       its entry of the right-hand side;
+//   (3) the trailing lower tiles are updated, A_IK -= L_Ij L_Kj^T, by MFMA 16x16x4 with the
+//       panel staged in LDS.
+// Then L^T x = y by 16-row blocks.  The lower triangle of A is overwritten by L.
+__global__ __launch_bounds__(256) void k_solve1d(Tables tb, StepArgs a, Epilogue ep) {
+  extern __shared__ double sm[];
+  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Mp = tb.Mp, nt = Mp / 16;
+  double* A = a.A + (long)u * Mp * Mp;
+  double* sb = sm;               // rhs -> y -> x   [Mp]
+  double* sL = sb + Mp;          // diagonal block  [16][17]
+  double* sP = sL + 16 * 17;     // panel           [Mp][17]
+  double* sred = sP + Mp * 17;   // partial sums    [256]
+
+  for (int k = tid; k < Mp; k += blockDim.x) sb[k] = a.rhs[(long)u * Mp + k];
+  __syncthreads();
+
+  for (int j = 0; j < nt; ++j) {
+    const int j0 = 16 * j;
+    if (wave == 0) {
+      const int r = lane & 15;
+      double v[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) v[s] = (s <= r) ? A[(long)(j0 + r) * Mp + j0 + s] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const double dcc = __shfl(v[c], c, 16);
+        const double dd = sqrt(dcc);
+        const double inv = 1.0 / dd;
+        if (r == c) v[c] = dd;
+        else if (r > c) v[c] = v[c] * inv;
+#pragma unroll
+        for (int s = c + 1; s < 16; ++s) {
+          const double lsc = __shfl(v[c], s, 16);
+          if (r >= s) v[s] -= v[c] * lsc;
+        }
+      }
+      // y_j = L_jj^{-1} b_j
+      double yv = sb[j0 + r];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const double yc = __shfl(yv / v[c], c, 16);
+        if (r == c) yv = yc;
+        else if (r > c) yv -= v[c] * yc;
+      }
+      if (lane < 16) {
+        sb[j0 + r] = yv;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) sL[r * 17 + s] = (s <= r) ? v[s] : 0.0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+          if (s <= r) A[(long)(j0 + r) * Mp + j0 + s] = v[s];
+      }
+    }
+    __syncthreads();
+
+    const int rows = Mp - j0 - 16;
+    for (int t = tid; t < rows; t += blockDim.x) {
+      const int i = j0 + 16 + t;
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) x[c] = A[(long)i * Mp + j0 + c];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double s = x[c];
+#pragma unroll
+        for (int p = 0; p < c; ++p) s -= x[p] * sL[c * 17 + p];
+        x[c] = s / sL[c * 17 + c];
+      }
+      double bi = sb[i];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        A[(long)i * Mp + j0 + c] = x[c];
+        sP[t * 17 + c] = x[c];
+        bi -= x[c] * sb[j0 + c];
+      }
+      sb[i] = bi;
+    }
+    __syncthreads();
+
+    const int ntr = nt - j - 1;
+    const int ntiles = ntr * (ntr + 1) / 2;
+    for (int tt = wave; tt < ntiles; tt += 4) {
+      int I = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+      while ((I + 1) * (I + 2) / 2 <= tt) ++I;
+      while (I * (I + 1) / 2 > tt) --I;
+      const int K = tt - I * (I + 1) / 2;
+      const int gi = (j + 1 + I) * 16, gk = (j + 1 + K) * 16;
+      d4 acc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = A[(long)(gi + (lane >> 4) + 4 * e) * Mp + gk + (lane & 15)];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kc = 4 * kk + (lane >> 4);
+        const double aop = -sP[(I * 16 + (lane & 15)) * 17 + kc];
+        const double bop = sP[(K * 16 + (lane & 15)) * 17 + kc];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) A[(long)(gi + (lane >> 4) + 4 * e) * Mp + gk + (lane & 15)] = acc[e];
+    }
+    __syncthreads();
+  }
+
+  // L^T x = y, last block first
+  for (int j = nt - 1; j >= 0; --j) {
+    const int j0 = 16 * j;
+    {
+      const int c = tid & 15, part = tid >> 4;
+      double acc = 0.0;
+      for (int i = j0 + 16 + part; i < Mp; i += 16) acc += A[(long)i * Mp + j0 + c] * sb[i];
+      sred[part * 16 + c] = acc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const int r = lane & 15;
+      double s = sb[j0 + r];
+      for (int p = 0; p < 16; ++p) s -= sred[p * 16 + r];
+#pragma unroll
+      for (int cc = 15; cc >= 0; --cc) {
+        const double lcc = A[(long)(j0 + cc) * Mp + j0 + cc];
+        const double xc = __shfl(s / lcc, cc, 16);
+        if (r == cc) s = xc;
+        else if (r < cc) s -= A[(long)(j0 + cc) * Mp + j0 + r] * xc;
+      }
+      if (lane < 16) sb[j0 + r] = s;
+    }
+    __syncthreads();
+  }
+
+  // epilogue
+  long slot = u;
+  if (a.mode == MODE_FINE) {
+    const int b = u / a.nP, n = a.n_lo + u % a.nP;
+    slot = (long)b * a.trajP + (n - a.trajN0);
+  }
+  for (int k = tid; k < Mp; k += blockDim.x) {
+    const double x = sb[k];
+    if (ep.kind == EPI_CORRECT) {
+      const double go = ep.gold[(long)u * ep.gold_stride + k];
+      ep.out[(long)u * ep.out_stride + k] = ep.fold[(long)u * ep.fold_stride + k] + (x - go);
+      ep.gold[(long)u * ep.gold_stride + k] = x;
+    } else {
+      ep.out[slot * ep.out_stride + k] = x;
+      if (ep.kind == EPI_STORE2) ep.gold[(long)u * ep.gold_stride + k] = x;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------ launchers
+hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s) {
+  const size_t lds = sizeof(double) * (tb.Mp + tb.Qp);
+  k_eval1d<<<units, 256, lds, s>>>(tb, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s) {
+  int TB = (tb.Mp % 64 == 0) ? 64 : ((tb.Mp % 32 == 0) ? 32 : 16);
+  const int nt = tb.Mp / TB;
+  dim3 grid(nt * (nt + 1) / 2, units);
+  if (TB == 64) k_assemble1d<64><<<grid, 256, 0, s>>>(tb, a);
+  else if (TB == 32) k_assemble1d<32><<<grid, 256, 0, s>>>(tb, a);
+  else k_assemble1d<16><<<grid, 64, 0, s>>>(tb, a);
+  return hipGetLastError();
+}
+
+size_t solve_lds_bytes(int Mp) { return sizeof(double) * (Mp + 16 * 17 + (size_t)Mp * 17 + 256); }
+
+hipError_t launch_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                        hipStream_t s) {
+  k_solve1d<<<units, 256, solve_lds_bytes(tb.Mp), s>>>(tb, a, e);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- small kernels
+__global__ void k_pack(const double* src, int M, int B, long src_stride, double* dst, int Mp,
+                       long dst_stride) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)B * Mp) return;
+  const int b = (int)(idx / Mp), k = (int)(idx % Mp);
+  dst[b * dst_stride + k] = (k < M) ? src[b * src_stride + k] : 0.0;
+}
+
+hipError_t launch_pack(const double* src, int M, int B, long src_stride, double* dst, int Mp,
+                       long dst_stride, hipStream_t s) {
+  const long n = (long)B * Mp;
+  k_pack<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, M, B, src_stride, dst, Mp, dst_stride);
+  return hipGetLastError();
+}
+
+// dst[u][row][k] = src[u][row][k] for row < rows, k < Mp
+__global__ void k_copy_rows(const double* src, long sstr, double* dst, long dstr, int rows, int Mp,
+                            int units) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)rows * Mp;
+  if (idx >= per * units) return;
+  const long u = idx / per, e = idx % per;
+  dst[u * dstr + e] = src[u * sstr + e];
+}
+
+hipError_t launch_copy_rows(const double* src, long src_unit_stride, double* dst,
+                            long dst_unit_stride, int rows, int Mp, int units, hipStream_t s) {
+  const long n = (long)rows * Mp * units;
+  if (n == 0) return hipSuccess;
+  k_copy_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, src_unit_stride, dst,
+                                                          dst_unit_stride, rows, Mp, units);
+  return hipGetLastError();
+}
+
+// traj[b*P + n][0] = Z[b][n] for all b < B, n < P
+__global__ void k_fill_slot0(const double* Z, double* traj, int B, int P, int S, int Mp) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)B * P * Mp) return;
+  const long slot = idx / Mp;
+  const int k = (int)(idx % Mp);
+  const long b = slot / P, n = slot % P;
+  traj[slot * (long)(S + 1) * Mp + k] = Z[(b * (P + 1) + n) * Mp + k];
+}
+
+hipError_t launch_fill_slot0(const Tables& tb, const double* Z, double* traj, int B, int P,
+                             hipStream_t s) {
+  const long n = (long)B * P * tb.Mp;
+  k_fill_slot0<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(Z, traj, B, P, tb.S, tb.Mp);
+  return hipGetLastError();
+}
+
+// dst[u][row][k<M] = src[u][row][k] (drops the padding)
+__global__ void k_unpack(const double* src, int Mp, long sstr, double* dst, int M, long dstr,
+                         int rows, int units) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)rows * M;
+  if (idx >= per * units) return;
+  const long u = idx / per, e = idx % per;
+  const long row = e / M, k = e % M;
+  dst[u * dstr + row * M + k] = src[u * sstr + row * Mp + k];
+}
+
+hipError_t launch_unpack(const double* src, int Mp, long src_stride, double* dst, int M,
+                         long dst_stride, int rows_per_unit, int units, hipStream_t s) {
+  const long n = (long)rows_per_unit * M * units;
+  if (n == 0) return hipSuccess;
+  k_unpack<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, Mp, src_stride, dst, M, dst_stride,
+                                                       rows_per_unit, units);
+  return hipGetLastError();
+}
+
+// Relative increment ||Znew_b - Zold_b|| / ||Znew_b|| per instance, fixed-order tree
+// reduction (one work-group per instance).
+__global__ __launch_bounds__(256) void k_increment(const double* Znew, const double* Zold, int rows,
+                                                   int Mp, double* incr_out, int incr_stride, int k,
+                                                   double* incr_k) {
+  __shared__ double sd[256], su[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const long per = (long)rows * Mp;
+  const double* a = Znew + b * per;
+  const double* o = Zold + b * per;
+  double dn = 0.0, un = 0.0;
+  for (long e = tid; e < per; e += 256) {
+    const double d = a[e] - o[e];
+    dn += d * d;
+    un += a[e] * a[e];
+  }
+  sd[tid] = dn;
+  su[tid] = un;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      sd[tid] += sd[tid + w];
+      su[tid] += su[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double rel = su[0] > 0.0 ? sqrt(sd[0]) / sqrt(su[0]) : sqrt(sd[0]);
+    if (incr_out) incr_out[(long)b * incr_stride + k] = rel;
+    incr_k[b] = rel;
+  }
+}
+
+hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
+                            double* incr_out, int incr_stride, int k, double* incr_k,
+                            hipStream_t s) {
+  k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k);
+  return hipGetLastError();
+}
+
+}  // namespace l1pr

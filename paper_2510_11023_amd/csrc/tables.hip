@@ -1,0 +1,128 @@
+// Tables of the method, computed on the device once per call:
+//   - Gauss-Legendre nodes and weights on (0,1) (padded with zero-weight nodes);
+//   - sine basis values and derivatives at the nodes, phi, phiT and dphi;
+//   - per instance: alpha, tau = dt^a Gamma(2-a), tau_c = dT^a Gamma(2-a), S^-a,
+//     Gamma(1+a), Gamma(3-a), the L1 weights b_j (L1 scheme, Section 2.1) and the hybrid
+//     weights b_{m+r/S} of the fine operator (Section 2.2).
+#include "l1pr_internal.h"
+
+namespace l1pr {
+
+// One thread per node.  The i-th root of the Legendre polynomial P_Q (descending in i on
+// (-1,1)) is refined by Newton steps on the three-term recurrence, starting from the
+// classical cosine estimate; the node maps to x = (1 - z)/2 so nodes ascend on (0,1).
+__global__ void k_gauss_legendre(int Q, int Qp, double* xq, double* wq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Qp) return;
+  if (i >= Q) {  // padding node: weight 0
+    xq[i] = 0.5;
+    wq[i] = 0.0;
+    return;
+  }
+  double z = cos(kPi * (4.0 * i + 3.0) / (4.0 * Q + 2.0));
+  double deriv = 1.0;
+  for (int it = 0; it < 12; ++it) {
+    // P_0 = 1, P_1 = z, (j) P_j = (2j-1) z P_{j-1} - (j-1) P_{j-2}
+    double pm = 1.0, pc = z;
+    for (int j = 2; j <= Q; ++j) {
+      const double pn = ((2 * j - 1) * z * pc - (j - 1) * pm) / j;
+      pm = pc;
+      pc = pn;
+    }
+    deriv = Q * (pm - z * pc) / (1.0 - z * z);
+    z -= pc / deriv;
+  }
+  double pm = 1.0, pc = z;
+  for (int j = 2; j <= Q; ++j) {
+    const double pn = ((2 * j - 1) * z * pc - (j - 1) * pm) / j;
+    pm = pc;
+    pc = pn;
+  }
+  deriv = Q * (pm - z * pc) / (1.0 - z * z);
+  xq[i] = 0.5 * (1.0 - z);
+  wq[i] = 1.0 / ((1.0 - z * z) * deriv * deriv);
+}
+
+// phi[q][k] = sqrt2 sin((k+1) pi x_q), dphi[q][k] = sqrt2 (k+1) pi cos((k+1) pi x_q),
+// zero outside k < M, q < Q.
+__global__ void k_basis(int M, int Q, int Mp, int Qp, const double* xq, double* phi,
+                        double* phiT, double* dphi) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)Qp * Mp) return;
+  const int q = (int)(idx / Mp), k = (int)(idx % Mp);
+  double v = 0.0, dv = 0.0;
+  if (k < M && q < Q) {
+    const double kp = (k + 1) * kPi;
+    const double arg = kp * xq[q];
+    v = sqrt(2.0) * sin(arg);
+    dv = sqrt(2.0) * kp * cos(arg);
+  }
+  phi[(long)q * Mp + k] = v;
+  phiT[(long)k * Qp + q] = v;
+  dphi[(long)q * Mp + k] = dv;
+}
+
+__global__ void k_inst_scalars(int B, int N, int P, int S, double T, const double* alpha,
+                               double* inst) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double a = alpha[b];
+  const double g2 = tgamma(2.0 - a);
+  double* o = inst + (long)b * NSCAL;
+  o[IS_ALPHA] = a;
+  o[IS_TAU] = pow(T / (double)N, a) * g2;
+  o[IS_TAUC] = pow(T / (double)P, a) * g2;
+  o[IS_SFAC] = pow((double)S, -a);
+  o[IS_G1A] = tgamma(1.0 + a);
+  o[IS_G3A] = tgamma(3.0 - a);
+  o[6] = 0.0;
+  o[7] = 0.0;
+}
+
+// bw[b][j] = b_j for j < LB
+__global__ void k_weights(int B, int LB, const double* alpha, double* bw) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)B * LB) return;
+  const int b = (int)(idx / LB), j = (int)(idx % LB);
+  bw[idx] = l1_weight((double)j, alpha[b]);
+}
+
+// bhyb[b][m*S + r-1] = b_{m + r/S}, m < P, 1 <= r <= S, with m + r/S formed as (m S + r)/S.
+__global__ void k_hybrid_weights(int B, int P, int S, const double* alpha, double* bhyb) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)P * S;
+  if (idx >= (long)B * per) return;
+  const int b = (int)(idx / per);
+  const long rem = idx % per;
+  const int m = (int)(rem / S), r = (int)(rem % S) + 1;
+  const double x = (double)((long)m * S + r) / (double)S;
+  bhyb[idx] = l1_weight(x, alpha[b]);
+}
+
+__global__ void k_fill(double* x, long n, double v) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+hipError_t launch_fill(double* x, long n, double v, hipStream_t s) {
+  if (n > 0) k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
+                         double* dphi, double* inst, double* bw, double* bhyb,
+                         const double* alpha_dev, hipStream_t s) {
+  const int T = 256;
+  k_gauss_legendre<<<(tb.Qp + T - 1) / T, T, 0, s>>>(tb.Q, tb.Qp, xq, wq);
+  const long nb = (long)tb.Qp * tb.Mp;
+  k_basis<<<(unsigned)((nb + T - 1) / T), T, 0, s>>>(tb.M, tb.Q, tb.Mp, tb.Qp, xq, phi, phiT, dphi);
+  k_inst_scalars<<<(tb.B + T - 1) / T, T, 0, s>>>(tb.B, tb.N, tb.P, tb.S, tb.T, alpha_dev, inst);
+  const long nw = (long)tb.B * tb.LB;
+  k_weights<<<(unsigned)((nw + T - 1) / T), T, 0, s>>>(tb.B, tb.LB, alpha_dev, bw);
+  const long nh = (long)tb.B * tb.P * tb.S;
+  if (bhyb && nh > 0)
+    k_hybrid_weights<<<(unsigned)((nh + T - 1) / T), T, 0, s>>>(tb.B, tb.P, tb.S, alpha_dev, bhyb);
+  return hipGetLastError();
+}
+
+}  // namespace l1pr

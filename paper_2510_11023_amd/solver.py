@@ -1,0 +1,114 @@
+"""Python entry points with the C-ABI's names: ``solve_serial`` and ``solve_parareal``.
+
+Tensors are torch float64 CUDA (HIP) tensors; the work is enqueued on the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import Problem
+
+
+def make_problem(dim=1, modes=32, quad=64, steps=256, slices=8, alpha=0.5, T=1.0, d_sel=0,
+                 d_param=1.0, f_sel=0, history=0, source_time=0) -> Problem:
+    return Problem(dim, modes, quad, steps, slices, alpha, T, d_sel, d_param, f_sel, history,
+                   source_time)
+
+
+def nmodes(p: Problem) -> int:
+    return p.modes if p.dim == 1 else p.modes * p.modes
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _alpha_arg(alpha, B):
+    if alpha is None:
+        return None, None
+    arr = (ctypes.c_double * B)(*[float(a) for a in alpha])
+    return arr, ctypes.cast(arr, ctypes.c_void_p)
+
+
+def _check_u0(p: Problem, u0: torch.Tensor):
+    if not (u0.is_cuda and u0.dtype == torch.float64 and u0.is_contiguous()):
+        raise ValueError("u0 must be a contiguous float64 device tensor")
+    if u0.dim() != 2 or u0.shape[1] != nmodes(p):
+        raise ValueError(f"u0 must have shape [batch, {nmodes(p)}]")
+
+
+def workspace_bytes(p: Problem, batch: int, op: int) -> int:
+    return int(_lib.lib().l1pr_workspace_bytes(ctypes.byref(p), batch, op))
+
+
+def _workspace(p, B, op, device):
+    n = workspace_bytes(p, B, op)
+    if n == 0:
+        raise _lib.L1prError(_lib.EINVAL, "workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=device), n
+
+
+def solve_serial(p: Problem, u0: torch.Tensor, alpha=None, want_traj: bool = False,
+                 workspace: torch.Tensor | None = None):
+    """Serial solve of u0.shape[0] instances.  Returns (U [B,P+1,Md], traj [B,N+1,Md] or None)."""
+    _check_u0(p, u0)
+    B = u0.shape[0]
+    Md = nmodes(p)
+    U = torch.empty((B, p.slices + 1, Md), dtype=torch.float64, device=u0.device)
+    traj = torch.empty((B, p.steps + 1, Md), dtype=torch.float64, device=u0.device) if want_traj else None
+    if workspace is None:
+        workspace, n = _workspace(p, B, _lib.OP_SERIAL, u0.device)
+    else:
+        n = workspace.numel() * workspace.element_size()
+    keep, aptr = _alpha_arg(alpha, B)
+    st = _lib.lib().l1pr_solve_serial(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U), _ptr(traj),
+                                      _ptr(workspace), n, _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_solve_serial")
+    return U, traj
+
+
+@dataclass
+class PararealResult:
+    U: torch.Tensor
+    iters: int
+    status: int
+    incr: torch.Tensor | None
+    iterates: torch.Tensor | None
+
+
+def solve_parareal(p: Problem, u0: torch.Tensor, max_iter: int, tol: float = 0.0, alpha=None,
+                   want_iterates: bool = False, want_incr: bool = True,
+                   workspace: torch.Tensor | None = None, allow_notconv: bool = True):
+    """Parareal solve.  Returns a PararealResult; iterates is [iters+1, B, P+1, Md]."""
+    _check_u0(p, u0)
+    B = u0.shape[0]
+    Md = nmodes(p)
+    dev = u0.device
+    U = torch.empty((B, p.slices + 1, Md), dtype=torch.float64, device=dev)
+    its = torch.empty((max_iter + 1, B, p.slices + 1, Md), dtype=torch.float64, device=dev) \
+        if want_iterates else None
+    incr = torch.zeros((B, max(max_iter, 1)), dtype=torch.float64, device=dev) if want_incr else None
+    if workspace is None:
+        workspace, n = _workspace(p, B, _lib.OP_PARAREAL, dev)
+    else:
+        n = workspace.numel() * workspace.element_size()
+    keep, aptr = _alpha_arg(alpha, B)
+    it = ctypes.c_int32(0)
+    st = _lib.lib().l1pr_solve_parareal(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U), int(max_iter),
+                                        float(tol), _ptr(its), _ptr(incr), ctypes.byref(it),
+                                        _ptr(workspace), n, _stream())
+    if st != _lib.OK and not (allow_notconv and st == _lib.ENOTCONV):
+        raise _lib.L1prError(st, "l1pr_solve_parareal")
+    k = it.value
+    return PararealResult(U=U, iters=k, status=st,
+                          incr=None if incr is None else incr[:, :k],
+                          iterates=None if its is None else its[: k + 1])

@@ -1,0 +1,65 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that include/l1pr.h
+declares, and its host-only entry points (validation, workspace sizing, status strings)
+behave.  No compute call is made here (no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "l1pr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(l1pr_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2510_11023_amd import _lib, build
+
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert {"l1pr_solve_serial", "l1pr_solve_parareal"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_host_entry_points(L):
+    from paper_2510_11023_amd import make_problem, workloads as W
+
+    p = make_problem(**W.C2)
+    assert L.l1pr_validate(ctypes.byref(p)) == 0
+    ser = L.l1pr_workspace_bytes(ctypes.byref(p), 32, 0)
+    par = L.l1pr_workspace_bytes(ctypes.byref(p), 32, 1)
+    # the parareal workspace holds B*P systems of M^2 doubles
+    assert par > 32 * 64 * 256 * 256 * 8 > ser > 0
+    bad = make_problem(**W.with_(W.C2, steps=4095))
+    assert L.l1pr_validate(ctypes.byref(bad)) == -1
+    assert L.l1pr_workspace_bytes(ctypes.byref(bad), 32, 1) == 0
+    assert L.l1pr_workspace_bytes(ctypes.byref(p), 0, 1) == 0
+    for s in (0, -1, -2, -3, -4, -5):
+        assert L.l1pr_status_string(s)
+    # invalid problems are rejected before any device work
+    u = ctypes.c_void_p(1)
+    assert L.l1pr_solve_serial(ctypes.byref(bad), 1, None, u, u, None, u, 1 << 30, None) == -1
+    assert L.l1pr_solve_parareal(ctypes.byref(p), 1, None, u, u, 65, 0.0, None, None, None, u,
+                                 1 << 30, None) == -1
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The package never imports the oracle, and the binding raises if the library is missing."""
+    pkg = os.path.join(ROOT, "paper_2510_11023_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            txt = open(os.path.join(pkg, fn)).read()
+            assert "import oracle" not in txt and "from oracle" not in txt, fn
+    txt = open(os.path.join(pkg, "_lib.py")).read()
+    assert "raise ImportError" in txt
