@@ -129,6 +129,23 @@ l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const doub
                                 double* U_iters, double* incr, int32_t* iters,
                                 void* ws, size_t ws_bytes, void* stream);
 
+/* Kernel-launch profiling (for benchmarks).  After l1pr_profile_start(), every step kernel
+ * that the solvers enqueue is bracketed by two HIP events recorded on its stream.
+ * l1pr_profile_stop() turns recording off, waits for the recorded events, and aggregates
+ * the elapsed times by "kernel/mode/units" (kernel = eval | assemble | solve, mode =
+ * fine | coarse | full, units = systems per launch).  It writes up to max_out entries to
+ * `out` (host memory owned by the caller) and returns the number of distinct entries, or
+ * -1 on a HIP error.  The events are created on first use and kept by the library for
+ * reuse; nothing else is allocated. */
+typedef struct {
+  char    name[64];
+  int64_t launches;
+  double  total_ms;
+} l1pr_kernel_stat;
+
+void    l1pr_profile_start(void);
+int32_t l1pr_profile_stop(l1pr_kernel_stat* out, int32_t max_out);
+
 /* Static description of a status code. */
 const char* l1pr_status_string(l1pr_status s);
 

@@ -35,6 +35,13 @@ class Problem(ctypes.Structure):
     ]
 
 
+class KernelStat(ctypes.Structure):
+    """Mirror of l1pr_kernel_stat."""
+
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 class L1prError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -64,6 +71,10 @@ def lib():
                                           ctypes.c_double, vp, vp, ctypes.POINTER(ctypes.c_int32),
                                           vp, ctypes.c_size_t, vp]
         L.l1pr_solve_parareal.restype = ctypes.c_int
+        L.l1pr_profile_start.argtypes = []
+        L.l1pr_profile_start.restype = None
+        L.l1pr_profile_stop.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32]
+        L.l1pr_profile_stop.restype = ctypes.c_int32
         L.l1pr_status_string.argtypes = [ctypes.c_int]
         L.l1pr_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -74,5 +85,15 @@ def status_string(status: int) -> str:
     return lib().l1pr_status_string(int(status)).decode()
 
 
-EXPORTED = ["l1pr_workspace_bytes", "l1pr_validate", "l1pr_solve_serial", "l1pr_solve_parareal",
-            "l1pr_status_string"]
+def profile_start():
+    lib().l1pr_profile_start()
+
+
+def profile_stop():
+    """Returns {"kernel/mode/units": (launches, total_ms)} for the launches since profile_start()."""
+    cap = 512
+    buf = (KernelStat * cap)()
+    n = lib().l1pr_profile_stop(buf, cap)
+    if n < 0:
+        raise L1prError(EHIP, "l1pr_profile_stop")
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms) for i in range(min(n, cap))}

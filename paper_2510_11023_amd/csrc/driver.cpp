@@ -11,7 +11,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "l1pr_internal.h"
@@ -146,11 +150,56 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   return L1PR_OK;
 }
 
+// Optional per-launch timing with HIP events recorded on the launch stream around each
+// step kernel (l1pr_profile_start / l1pr_profile_stop).  Events come from a pool that
+// persists across calls, so steady-state timing creates no events.
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { std::string name; size_t ev; };
+  std::vector<Rec> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+
+const char* mode_name(int mode) {
+  return mode == MODE_FINE ? "fine" : (mode == MODE_COARSE ? "coarse" : "full");
+}
+
+template <class F>
+hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s, F&& launch) {
+  Profiler& p = prof();
+  if (!p.on) return launch();
+  std::lock_guard<std::mutex> g(p.mu);
+  const size_t i0 = p.used;
+  hipEvent_t e0 = p.next(), e1 = p.next();
+  if (!e0 || !e1) return hipErrorOutOfMemory;
+  hipError_t r = hipEventRecord(e0, s);
+  if (r == hipSuccess) r = launch();
+  if (r == hipSuccess) r = hipEventRecord(e1, s);
+  char name[64];
+  std::snprintf(name, sizeof(name), "%s/%s/%d", kernel, mode_name(a.mode), units);
+  p.recs.push_back({name, i0});
+  return r;
+}
+
 // eval + assemble + solve for `units` units
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
-  L1PR_TRY(launch_eval(c.tb, a, units, c.s));
-  L1PR_TRY(launch_assemble(c.tb, a, units, c.s));
-  L1PR_TRY(launch_solve(c.tb, a, e, units, c.s));
+  L1PR_TRY(timed("eval", a, units, c.s, [&] { return launch_eval(c.tb, a, units, c.s); }));
+  L1PR_TRY(timed("assemble", a, units, c.s, [&] { return launch_assemble(c.tb, a, units, c.s); }));
+  L1PR_TRY(timed("solve", a, units, c.s, [&] { return launch_solve(c.tb, a, e, units, c.s); }));
   return L1PR_OK;
 }
 
@@ -378,6 +427,42 @@ l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const doub
   } catch (...) {
     return L1PR_EHIP;
   }
+}
+
+void l1pr_profile_start(void) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.on = true;
+  p.used = 0;
+  p.recs.clear();
+}
+
+int32_t l1pr_profile_stop(l1pr_kernel_stat* out, int32_t max_out) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.on = false;
+  std::map<std::string, std::pair<int64_t, double>> agg;
+  for (const auto& r : p.recs) {
+    if (hipEventSynchronize(p.pool[r.ev + 1]) != hipSuccess) return -1;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.pool[r.ev], p.pool[r.ev + 1]) != hipSuccess) return -1;
+    auto& a = agg[r.name];
+    a.first += 1;
+    a.second += ms;
+  }
+  p.recs.clear();
+  p.used = 0;
+  int32_t n = 0;
+  for (const auto& kv : agg) {
+    if (out && n < max_out) {
+      std::memset(&out[n], 0, sizeof(l1pr_kernel_stat));
+      std::snprintf(out[n].name, sizeof(out[n].name), "%s", kv.first.c_str());
+      out[n].launches = kv.second.first;
+      out[n].total_ms = kv.second.second;
+    }
+    ++n;
+  }
+  return n;
 }
 
 const char* l1pr_status_string(l1pr_status s) {
