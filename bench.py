@@ -13,11 +13,17 @@ from the GPU serial solution (itself parity-checked against the CPU oracle by th
 and the parareal iterates.  Metric: useful mode-steps/s = sum_b M N / time-to-1e-8.
 
 The JSON line also carries:
-  roofline      the dominant kernel (stiffness assembly of the fine sweep, FP64 MFMA):
-                algorithmic flops per launch = units * Q * M (M + 1) (the M(M+1)/2 distinct
-                entries of the symmetric stiffness matrix, 2Q flops each), divided by its
-                average launch time measured with HIP events on the launch stream over the
-                timed region; peak = 78.6 TFLOP/s (MI355X dense FP64 matrix).
+  roofline      the dominant kernel: the fine-sweep step kernel (2048 units per launch;
+                evaluation, cosine-moment stiffness, register-resident Cholesky, solves).
+                Algorithmic flops per unit = M^3/3 + M^2/2 + M/6 (Cholesky) + 2 M^2
+                (two triangular solves) + 4 M Q (u_q and the load vector) + 2 (2M+1) Q
+                (cosine moments); divided by the average launch time measured with HIP
+                events on the launch stream over the timed region; peak = 78.6 TFLOP/s
+                (MI355X dense FP64 matrix).
+  gemm_assembly the same step with the stiffness formed as the quadrature GEMM
+                dphi^T diag(w D) dphi on FP64 MFMA (assembly = 1), timed for one step; its
+                assembly kernel's roofline counts Q M (M+1) flops per unit (the M(M+1)/2
+                distinct entries of the symmetric stiffness, 2Q flops each).
   cpu_baseline  the CPU oracle (plain serial C) timed on this host's cores on a bounded
                 sample: the first slice (64 fine steps) of 16 instances of the alpha = 0.3
                 batch, one instance per thread.
@@ -96,6 +102,7 @@ def main():
     u0_np = W.u0_batch_1d(M, range(B))
     u0 = torch.tensor(u0_np, dtype=torch.float64, device=dev)
     probs = {a: l1.make_problem(**W.with_(base, alpha=a)) for a in alphas}
+    probs_gemm = {a: l1.make_problem(assembly=1, **W.with_(base, alpha=a)) for a in alphas}
     p0 = probs[alphas[0]]
     ws_par = torch.empty(l1.workspace_bytes(p0, B, 1), dtype=torch.uint8, device=dev)
     ws_ser = torch.empty(l1.workspace_bytes(p0, B, 0), dtype=torch.uint8, device=dev)
@@ -137,10 +144,10 @@ def main():
         errs[a] = e
         log(f"parareal alpha={a}: k*={kstar[a]} errors " + " ".join(f"{v:.1e}" for v in e[: kstar[a] + 1]))
 
-    def step():
+    def step(pr=probs):
         out = {}
         for a in alphas:
-            out[a] = l1.solve_parareal(probs[a], u0, kstar[a], tol=0.0, want_incr=False,
+            out[a] = l1.solve_parareal(pr[a], u0, kstar[a], tol=0.0, want_incr=False,
                                        workspace=ws_par).U
         return out
 
@@ -166,20 +173,46 @@ def main():
     executed = sum(kstar[a] for a in alphas) * B * M * N
     serial_total = sum(t_serial.values())
 
-    # dominant kernel: fine-sweep stiffness assembly
-    key = f"assemble/fine/{B * P}"
+    # dominant kernel: the fine-sweep step kernel
+    units = B * P
+    key = f"step/fine/{units}"
     n_l, tot_l = stats.get(key, (0, 0.0))
     roofline = None
     if n_l:
         avg_s = tot_l / n_l / 1e3
-        flops = B * P * Q * M * (M + 1)
+        per_unit = M ** 3 / 3 + M ** 2 / 2 + M / 6 + 2 * M ** 2 + 4 * M * Q + 2 * (2 * M + 1) * Q
+        flops = units * per_unit
         achieved = flops / avg_s / 1e12
-        roofline = {"bound": "mfma", "kernel": "k_assemble1d<64> (fine sweep, 2048 units)",
+        roofline = {"bound": "mfma", "kernel": "k_step1d_reg<moments> (fine sweep, 2048 units)",
                     "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
-                    "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops,
+                    "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": int(flops),
                     "traffic": None}
     share = {k: round(v[1] / sum(x[1] for x in stats.values()), 4) for k, v in stats.items()}
+
+    # the same step with the quadrature-GEMM stiffness (assembly = 1)
+    step(probs_gemm)
+    torch.cuda.synchronize()
+    _lib.profile_start()
+    t0 = time.perf_counter()
+    out_g = step(probs_gemm)
+    torch.cuda.synchronize()
+    t_gemm = time.perf_counter() - t0
+    stats_g = _lib.profile_stop()
+    n_a, tot_a = stats_g.get(f"assemble/fine/{units}", (0, 0.0))
+    gemm = {"ms_per_step": t_gemm * 1e3,
+            "achieved_rel_err": {str(a): rel_err_max(out_g[a], Us[a]) for a in alphas}}
+    if n_a:
+        avg_a = tot_a / n_a / 1e3
+        fl = units * Q * M * (M + 1)
+        gemm["assemble_roofline"] = {
+            "bound": "mfma", "kernel": "k_assemble1d<64> (fine sweep, 2048 units)",
+            "achieved": round(fl / avg_a / 1e12, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(fl / avg_a / 1e12 / PEAK_FP64_MFMA_TFLOPS, 4),
+            "avg_launch_ms": round(avg_a * 1e3, 4), "flops_per_launch": fl}
+    for k in sorted(stats_g):
+        n, tot = stats_g[k]
+        log(f"  gemm {k:27s} launches {n:7d}  avg {tot / n * 1e3:9.1f} us  total {tot:9.1f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -214,6 +247,7 @@ def main():
         "executed_mode_steps_per_s": executed / (ms_per_step / 1e3),
         "kernel_time_share": share,
         "roofline": roofline,
+        "gemm_assembly": gemm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

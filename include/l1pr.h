@@ -90,6 +90,12 @@ typedef struct {
                            1: full uniform L1 over all N steps (serial only) */
   int32_t source_time;  /* 0: f lagged to the previous level (the paper)
                            1: f at the new time level (only for u-independent f) */
+  int32_t assembly;     /* how the stiffness sum_q w_q D_q phi_k'(x_q) phi_l'(x_q) is formed:
+                           0: cosine moments, K_kl = k l pi^2 (m_|k-l| + m_{k+l}) with
+                              m_j = sum_q w_q D_q cos(j pi x_q) (product-to-sum identity of the
+                              sine basis; the same quadrature sum, 2M+1 moments instead of
+                              M^2 dot products), M <= 256; larger M uses 1
+                           1: quadrature GEMM dphi^T diag(w D) dphi on FP64 MFMA */
 } l1pr_problem;
 
 /* Operation codes for l1pr_workspace_bytes. */

@@ -32,6 +32,7 @@ class Problem(ctypes.Structure):
         ("f_sel", ctypes.c_int32),
         ("history", ctypes.c_int32),
         ("source_time", ctypes.c_int32),
+        ("assembly", ctypes.c_int32),
     ]
 
 

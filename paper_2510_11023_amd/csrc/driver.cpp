@@ -30,7 +30,8 @@ constexpr int kMaxMp1D = 400;
 
 struct Layout {
   size_t total = 0;
-  size_t xq, wq, phi, phiT, dphi, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
+  size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
+  size_t g, mom, F;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -53,6 +54,7 @@ bool valid(const l1pr_problem* p) {
   if (p->history != 0 && p->history != 1) return false;
   if (p->source_time != 0 && p->source_time != 1) return false;
   if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
+  if (p->assembly != 0 && p->assembly != 1) return false;
   return true;
 }
 
@@ -80,6 +82,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.phi = take(cur, D * Qp * Mp);
   L.phiT = take(cur, D * Qp * Mp);
   L.dphi = take(cur, D * Qp * Mp);
+  L.cosq = take(cur, D * Qp * (2 * Mp + 1));
   L.inst = take(cur, D * B * NSCAL);
   L.bw = take(cur, D * B * tb.LB);
   L.bhyb = take(cur, D * B * P * S);
@@ -99,6 +102,9 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.d = take(cur, D * units * Qp);
   L.rhs = take(cur, D * units * Mp);
   L.A = take(cur, D * units * Mp * Mp);
+  L.g = take(cur, D * units * Qp);
+  L.mom = take(cur, D * units * (2 * Mp + 1));
+  L.F = take(cur, D * units * Mp);
   L.incrk = take(cur, D * B);
   L.total = cur;
 }
@@ -106,6 +112,8 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
 struct Ctx {
   Tables tb;
   Layout L;
+  bool reg;      // register-resident step kernel (Mp <= 256)
+  bool moments;  // stiffness from cosine moments, inside that kernel
   char* ws;
   hipStream_t s;
   double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -140,13 +148,16 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.inst = c.ptr(c.L.inst);
   tb.bw = c.ptr(c.L.bw);
   tb.bhyb = c.ptr(c.L.bhyb);
+  tb.cosq = c.ptr(c.L.cosq);
+  c.reg = reg_path_ok(tb.Mp, tb.Qp);
+  c.moments = c.reg && p->assembly == 0;
   if (alpha)  // pageable source: the copy is staged before the call returns
     L1PR_TRY(hipMemcpyAsync(c.ptr(c.L.alpha), al.data(), sizeof(double) * B, hipMemcpyHostToDevice, c.s));
   else
     L1PR_TRY(launch_fill(c.ptr(c.L.alpha), B, p->alpha, c.s));
   L1PR_TRY(launch_tables(tb, c.ptr(c.L.xq), c.ptr(c.L.wq), c.ptr(c.L.phi), c.ptr(c.L.phiT),
                          c.ptr(c.L.dphi), c.ptr(c.L.inst), c.ptr(c.L.bw), c.ptr(c.L.bhyb),
-                         c.ptr(c.L.alpha), c.s));
+                         c.ptr(c.L.cosq), c.ptr(c.L.alpha), c.s));
   return L1PR_OK;
 }
 
@@ -195,8 +206,27 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
   return r;
 }
 
-// eval + assemble + solve for `units` units
+// One step for `units` units.
+// Mp <= 256: batched MFMA GEMMs for the lagged state on the quadrature grid (then D and f)
+//   and for the moments and load vector, a streaming kernel for the history sums, then the
+//   register-resident factorisation and solve (stiffness from the moments, or from the
+//   quadrature-GEMM assembly kernel when assembly = 1).
+// Mp > 256: evaluation, quadrature-GEMM assembly and the blocked factorisation through
+//   device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
+  if (c.reg) {
+    L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, c.s); }));
+    L1PR_TRY(timed("proj", a, units, c.s, [&] {
+      return launch_proj_gemm(c.tb, units, a.d, a.g, c.moments ? a.mom : nullptr, a.F, c.s);
+    }));
+    if (!c.moments)
+      L1PR_TRY(timed("assemble", a, units, c.s, [&] { return launch_assemble(c.tb, a, units, c.s); }));
+    L1PR_TRY(timed("history", a, units, c.s, [&] { return launch_history(c.tb, a, units, a.rhs, c.s); }));
+    L1PR_TRY(timed("chol", a, units, c.s, [&] {
+      return launch_chol_reg(c.tb, a, e, units, c.moments ? a.mom : nullptr, a.F, a.rhs, c.s);
+    }));
+    return L1PR_OK;
+  }
   L1PR_TRY(timed("eval", a, units, c.s, [&] { return launch_eval(c.tb, a, units, c.s); }));
   L1PR_TRY(timed("assemble", a, units, c.s, [&] { return launch_assemble(c.tb, a, units, c.s); }));
   L1PR_TRY(timed("solve", a, units, c.s, [&] { return launch_solve(c.tb, a, e, units, c.s); }));
@@ -209,6 +239,9 @@ StepArgs base_args(const Ctx& c) {
   a.d = c.ptr(c.L.d);
   a.rhs = c.ptr(c.L.rhs);
   a.A = c.ptr(c.L.A);
+  a.g = c.ptr(c.L.g);
+  a.mom = c.ptr(c.L.mom);
+  a.F = c.ptr(c.L.F);
   return a;
 }
 

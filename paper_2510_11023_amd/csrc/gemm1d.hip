@@ -1,0 +1,218 @@
+// Batched dense contractions and the history sum of one step, over all units of a launch.
+//
+//   k_lag_gemm1d     U = C Phi^T : u_q = sum_k phi_k(x_q) c_k for every unit (its lagged
+//                    state c); then d_q = w_q D(x_q, t, u_q), g_q = w_q f(x_q, t, u_q).
+//   k_proj_gemm1d    m = d cosq (cosine moments m_j = sum_q w_q D_q cos(j pi x_q)) and
+//                    F = g Phi (load vector F_k = sum_q w_q f_q phi_k(x_q)).
+//   k_history1d      hist = y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1})
+//                           [- S^-a sum_{i=1}^{n} b_{n-i+r/S} (C_i - C_{i-1})   (fine steps)].
+// The GEMMs tile 64 units x 64 columns per work-group (four waves, 2x2 MFMA 16x16x4 tiles
+// each) and stream the shared table through LDS in chunks of 16 rows, so each table is read
+// once per 64 units instead of once per unit.  An output element is a fixed-order sum over
+// its own row only, so a unit's values do not depend on the other units of the launch.
+#include "l1pr_internal.h"
+
+namespace l1pr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 64;   // units and columns per work-group tile
+constexpr int GK = 16;   // reduction chunk
+
+// Row pointer of the lagged state of unit u.
+__device__ inline const double* lag_row(const Tables& tb, const StepArgs& a, int u) {
+  const UnitView v = decode_unit(tb, a, u);
+  return v.y + (long)v.L * tb.Mp;
+}
+
+// C[u][n] = sum_k Arow(u)[k] * B[k][n] for a 64 x 64 tile; returns the accumulators.
+// A rows come from `rowp(u)` (nullptr rows read as zero), B is [K][ldb] row-major.
+template <class RowFn>
+__device__ inline void tile_gemm(RowFn rowp, int units, int u0, int n0, int K, const double* B,
+                                 int ldb, int ncols, d4 (&acc)[2][2], double (*sA)[GK + 1],
+                                 double (*sB)[GT + 1]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += GK) {
+    for (int e = tid; e < GT * GK; e += 256) {
+      const int r = e / GK, kk = e % GK;
+      const int u = u0 + r;
+      double v = 0.0;
+      if (u < units) {
+        const double* row = rowp(u);
+        v = row[k0 + kk];
+      }
+      sA[r][kk] = v;
+    }
+    for (int e = tid; e < GK * GT; e += 256) {
+      const int kk = e / GT, c = e % GT;
+      sB[kk][c] = (n0 + c < ncols) ? B[(long)(k0 + kk) * ldb + n0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      const int kq = ks * 4 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = sA[wi * 32 + a * 16 + (lane & 15)][kq];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = sB[kq][wj * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+// grid: (ceil(Qp / 64), ceil(units / 64))
+__global__ __launch_bounds__(256) void k_lag_gemm1d(Tables tb, StepArgs a, int units, double* dq,
+                                                    double* gq) {
+  __shared__ double sA[GT][GK + 1];
+  __shared__ double sB[GK][GT + 1];
+  const int n0 = blockIdx.x * GT, u0 = blockIdx.y * GT;
+  d4 acc[2][2];
+  tile_gemm([&](int u) { return lag_row(tb, a, u); }, units, u0, n0, tb.Mp, tb.phiT, tb.Qp,
+            tb.Qp, acc, sA, sB);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+#pragma unroll
+  for (int ai = 0; ai < 2; ++ai)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = u0 + wi * 32 + ai * 16 + (lane >> 4) + 4 * e;
+      if (u >= units) continue;
+      const UnitView v = decode_unit(tb, a, u);
+      const double* ins = tb.inst + (long)v.b * NSCAL;
+      const double tD = t_level(tb, v.m_prev);
+      const double tf = tb.source_time ? t_level(tb, v.m_src) : tD;
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int q = n0 + wj * 32 + bj * 16 + (lane & 15);
+        if (q >= tb.Qp) continue;
+        const double uq = acc[ai][bj][e];
+        const double w = tb.wq[q];
+        dq[(long)u * tb.Qp + q] = w * coef_D(tb.d_sel, tb.d_param, uq);
+        gq[(long)u * tb.Qp + q] = w * coef_f(tb, ins, tb.xq[q], 0.0, tf, uq);
+      }
+    }
+}
+
+// grid: (ceil(max(Jm, Mp) / 64), ceil(units / 64), 2); z = 0: moments (skipped when m is
+// nullptr), z = 1: load vector.
+__global__ __launch_bounds__(256) void k_proj_gemm1d(Tables tb, int units, const double* dq,
+                                                     const double* gq, double* m, int Jm,
+                                                     double* F) {
+  __shared__ double sA[GT][GK + 1];
+  __shared__ double sB[GK][GT + 1];
+  const int which = blockIdx.z;
+  const int n0 = blockIdx.x * GT, u0 = blockIdx.y * GT;
+  const int ncols = which == 0 ? Jm : tb.Mp;
+  if (which == 0 && m == nullptr) return;
+  if (n0 >= ncols) return;
+  const double* Ain = which == 0 ? dq : gq;
+  const double* B = which == 0 ? tb.cosq : tb.phi;
+  const int ldb = which == 0 ? Jm : tb.Mp;
+  double* out = which == 0 ? m : F;
+  d4 acc[2][2];
+  tile_gemm([&](int u) { return Ain + (long)u * tb.Qp; }, units, u0, n0, tb.Qp, B, ldb, ncols,
+            acc, sA, sB);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+#pragma unroll
+  for (int ai = 0; ai < 2; ++ai)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int u = u0 + wi * 32 + ai * 16 + (lane >> 4) + 4 * e;
+      if (u >= units) continue;
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int c = n0 + wj * 32 + bj * 16 + (lane & 15);
+        if (c < ncols) out[(long)u * ncols + c] = acc[ai][bj][e];
+      }
+    }
+}
+
+// One work-group per unit, one thread per mode: coalesced rows of the trajectory and of the
+// slice-end sequence, loads issued four rows ahead of the sequential (ascending-i) sum.
+__global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double* hist) {
+  const int u = blockIdx.x;
+  const UnitView v = decode_unit(tb, a, u);
+  const double* bw = tb.bw + (long)v.b * tb.LB;
+  const int Mp = tb.Mp;
+  for (int k = threadIdx.x; k < Mp; k += blockDim.x) {
+    const double* y = v.y + k;
+    double acc = 0.0;
+    double prev = y[0];
+    int i = 1;
+    for (; i + 3 <= v.L; i += 4) {
+      const double y1 = y[(long)i * Mp], y2 = y[(long)(i + 1) * Mp];
+      const double y3 = y[(long)(i + 2) * Mp], y4 = y[(long)(i + 3) * Mp];
+      acc += bw[v.L + 1 - i] * (y1 - prev);
+      acc += bw[v.L - i] * (y2 - y1);
+      acc += bw[v.L - 1 - i] * (y3 - y2);
+      acc += bw[v.L - 2 - i] * (y4 - y3);
+      prev = y4;
+    }
+    for (; i <= v.L; ++i) {
+      const double yi = y[(long)i * Mp];
+      acc += bw[v.L + 1 - i] * (yi - prev);
+      prev = yi;
+    }
+    double h = y[(long)v.L * Mp] - acc;
+    if (a.mode == MODE_FINE) {
+      const double* bh = tb.bhyb + (long)v.b * tb.P * tb.S + (a.r - 1);
+      const double* z = v.z + k;
+      double acc2 = 0.0;
+      double zp = z[0];
+      int c = 1;
+      for (; c + 3 <= v.nz; c += 4) {
+        const double z1 = z[(long)c * Mp], z2 = z[(long)(c + 1) * Mp];
+        const double z3 = z[(long)(c + 2) * Mp], z4 = z[(long)(c + 3) * Mp];
+        acc2 += bh[(long)(v.nz - c) * tb.S] * (z1 - zp);
+        acc2 += bh[(long)(v.nz - c - 1) * tb.S] * (z2 - z1);
+        acc2 += bh[(long)(v.nz - c - 2) * tb.S] * (z3 - z2);
+        acc2 += bh[(long)(v.nz - c - 3) * tb.S] * (z4 - z3);
+        zp = z4;
+      }
+      for (; c <= v.nz; ++c) {
+        const double zc = z[(long)c * Mp];
+        acc2 += bh[(long)(v.nz - c) * tb.S] * (zc - zp);
+        zp = zc;
+      }
+      h = h - tb.inst[(long)v.b * NSCAL + IS_SFAC] * acc2;
+    }
+    hist[(long)u * Mp + k] = h;
+  }
+}
+
+hipError_t launch_lag_gemm(const Tables& tb, const StepArgs& a, int units, double* dq, double* gq,
+                           hipStream_t s) {
+  dim3 grid((tb.Qp + GT - 1) / GT, (units + GT - 1) / GT);
+  k_lag_gemm1d<<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
+  return hipGetLastError();
+}
+
+hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const double* gq,
+                            double* m, double* F, hipStream_t s) {
+  const int Jm = 2 * tb.Mp + 1;
+  const int nc = Jm > tb.Mp ? Jm : tb.Mp;
+  dim3 grid((nc + GT - 1) / GT, (units + GT - 1) / GT, 2);
+  k_proj_gemm1d<<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
+                          hipStream_t s) {
+  const int threads = tb.Mp < 256 ? roundup(tb.Mp, 64) : 256;
+  k_history1d<<<units, threads, 0, s>>>(tb, a, hist);
+  return hipGetLastError();
+}
+
+}  // namespace l1pr

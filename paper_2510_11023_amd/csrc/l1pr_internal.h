@@ -42,6 +42,7 @@ struct Tables {
   const double* inst;
   const double* bw;
   const double* bhyb;
+  const double* cosq;  // [Qp][2 Mp + 1] = cos(j pi x_q) (zero for padding nodes)
 };
 
 // What one step-launch computes for each of its units.
@@ -54,9 +55,12 @@ struct StepArgs {
   double* traj; // MODE_FINE: slots [B*trajP][S+1][Mp]; MODE_FULL: [B][N+1][Mp]
   int trajP, trajN0;
   const double* Z;  // slice-end sequence [B][P+1][Mp]
-  double* d;        // [units][Qp]
-  double* rhs;      // [units][Mp]
+  double* d;        // [units][Qp]   w_q D_q
+  double* rhs;      // [units][Mp]   right-hand side (history sums on the batched path)
   double* A;        // [units][Mp][Mp]
+  double* g;        // [units][Qp]   w_q f_q
+  double* mom;      // [units][2 Mp + 1] cosine moments
+  double* F;        // [units][Mp]   load vector
 };
 
 struct Epilogue {
@@ -134,15 +138,78 @@ __device__ inline double coef_f(const Tables& tb, const double* inst, double x, 
 // fine time level t_m = T m / N
 __device__ inline double t_level(const Tables& tb, long m) { return (tb.T * (double)m) / (double)tb.N; }
 
+// Where a unit's data lives and which time level / step size it uses.
+struct UnitView {
+  int b, n;
+  const double* y;   // sequence whose last entry is the lagged state
+  int L;             // index of that last entry
+  const double* z;   // coarse sequence for the hybrid history (MODE_FINE) or nullptr
+  int nz;
+  long m_prev;       // fine index of the lagged time level
+  long m_src;        // fine index of the new time level (source_time = 1)
+  int tau_slot;      // IS_TAU or IS_TAUC
+  long slot;         // trajectory slot (MODE_FINE)
+};
+
+__device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int u) {
+  UnitView v;
+  const long vecP = (long)(tb.P + 1) * tb.Mp;
+  if (a.mode == MODE_FINE) {
+    v.b = u / a.nP;
+    v.n = a.n_lo + u % a.nP;
+    v.slot = (long)v.b * a.trajP + (v.n - a.trajN0);
+    v.y = a.traj + v.slot * (long)(tb.S + 1) * tb.Mp;
+    v.L = a.r - 1;
+    v.z = a.Z + v.b * vecP;
+    v.nz = v.n;
+    v.m_prev = (long)v.n * tb.S + a.r - 1;
+    v.m_src = v.m_prev + 1;
+    v.tau_slot = IS_TAU;
+  } else if (a.mode == MODE_COARSE) {
+    v.b = u;
+    v.n = a.n;
+    v.slot = u;
+    v.y = a.Z + v.b * vecP;
+    v.L = a.n;
+    v.z = nullptr;
+    v.nz = 0;
+    v.m_prev = (long)a.n * tb.S;
+    v.m_src = (long)(a.n + 1) * tb.S;
+    v.tau_slot = IS_TAUC;
+  } else {
+    v.b = u;
+    v.n = 0;
+    v.slot = u;
+    v.y = a.traj + (long)v.b * (tb.N + 1) * tb.Mp;
+    v.L = a.m;
+    v.z = nullptr;
+    v.nz = 0;
+    v.m_prev = a.m;
+    v.m_src = a.m + 1;
+    v.tau_slot = IS_TAU;
+  }
+  return v;
+}
+
 // ---- launchers (implemented in the .hip files) ----
 hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
-                         double* dphi, double* inst, double* bw, double* bhyb,
+                         double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
                          const double* alpha_dev, hipStream_t s);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
                         hipStream_t s);
+bool reg_path_ok(int Mp, int Qp);
+hipError_t launch_lag_gemm(const Tables& tb, const StepArgs& a, int units, double* dq, double* gq,
+                           hipStream_t s);
+hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const double* gq,
+                            double* m, double* F, hipStream_t s);
+hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
+                          hipStream_t s);
+hipError_t launch_chol_reg(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                           const double* mom, const double* F, const double* hist,
+                           hipStream_t s);
 hipError_t launch_pack(const double* src, int M, int B, long src_stride, double* dst, int Mp,
                        long dst_stride, hipStream_t s);
 hipError_t launch_copy_rows(const double* src, long src_unit_stride, double* dst,

@@ -18,58 +18,6 @@ namespace l1pr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-struct UnitView {
-  int b, n;
-  const double* y;   // sequence whose last entry is the lagged state
-  int L;             // index of that last entry
-  const double* z;   // coarse sequence for the hybrid history (MODE_FINE) or nullptr
-  int nz;
-  long m_prev;       // fine index of the lagged time level
-  long m_src;        // fine index of the new time level (source_time = 1)
-  int tau_slot;      // IS_TAU or IS_TAUC
-  long slot;         // trajectory slot (MODE_FINE)
-};
-
-__device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int u) {
-  UnitView v;
-  const long vecP = (long)(tb.P + 1) * tb.Mp;
-  if (a.mode == MODE_FINE) {
-    v.b = u / a.nP;
-    v.n = a.n_lo + u % a.nP;
-    v.slot = (long)v.b * a.trajP + (v.n - a.trajN0);
-    v.y = a.traj + v.slot * (long)(tb.S + 1) * tb.Mp;
-    v.L = a.r - 1;
-    v.z = a.Z + v.b * vecP;
-    v.nz = v.n;
-    v.m_prev = (long)v.n * tb.S + a.r - 1;
-    v.m_src = v.m_prev + 1;
-    v.tau_slot = IS_TAU;
-  } else if (a.mode == MODE_COARSE) {
-    v.b = u;
-    v.n = a.n;
-    v.slot = u;
-    v.y = a.Z + v.b * vecP;
-    v.L = a.n;
-    v.z = nullptr;
-    v.nz = 0;
-    v.m_prev = (long)a.n * tb.S;
-    v.m_src = (long)(a.n + 1) * tb.S;
-    v.tau_slot = IS_TAUC;
-  } else {
-    v.b = u;
-    v.n = 0;
-    v.slot = u;
-    v.y = a.traj + (long)v.b * (tb.N + 1) * tb.Mp;
-    v.L = a.m;
-    v.z = nullptr;
-    v.nz = 0;
-    v.m_prev = a.m;
-    v.m_src = a.m + 1;
-    v.tau_slot = IS_TAU;
-  }
-  return v;
-}
-
 // ------------------------------------------------------------------------------ eval
 __global__ __launch_bounds__(256) void k_eval1d(Tables tb, StepArgs a) {
   extern __shared__ double sm[];

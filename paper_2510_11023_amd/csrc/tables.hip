@@ -62,6 +62,14 @@ __global__ void k_basis(int M, int Q, int Mp, int Qp, const double* xq, double* 
   dphi[(long)q * Mp + k] = dv;
 }
 
+// cosq[q][j] = cos(j pi x_q), j = 0..Jp-1 (cosine moments of the stiffness)
+__global__ void k_cosq(int Q, int Qp, int Jp, const double* xq, double* cosq) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)Qp * Jp) return;
+  const int q = (int)(idx / Jp), j = (int)(idx % Jp);
+  cosq[idx] = (q < Q) ? cos((j * kPi) * xq[q]) : 0.0;
+}
+
 __global__ void k_inst_scalars(int B, int N, int P, int S, double T, const double* alpha,
                                double* inst) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -110,12 +118,16 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t s) {
 }
 
 hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
-                         double* dphi, double* inst, double* bw, double* bhyb,
+                         double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
                          const double* alpha_dev, hipStream_t s) {
   const int T = 256;
   k_gauss_legendre<<<(tb.Qp + T - 1) / T, T, 0, s>>>(tb.Q, tb.Qp, xq, wq);
   const long nb = (long)tb.Qp * tb.Mp;
   k_basis<<<(unsigned)((nb + T - 1) / T), T, 0, s>>>(tb.M, tb.Q, tb.Mp, tb.Qp, xq, phi, phiT, dphi);
+  if (cosq) {
+    const long nc = (long)tb.Qp * (2 * tb.Mp + 1);
+    k_cosq<<<(unsigned)((nc + T - 1) / T), T, 0, s>>>(tb.Q, tb.Qp, 2 * tb.Mp + 1, xq, cosq);
+  }
   k_inst_scalars<<<(tb.B + T - 1) / T, T, 0, s>>>(tb.B, tb.N, tb.P, tb.S, tb.T, alpha_dev, inst);
   const long nw = (long)tb.B * tb.LB;
   k_weights<<<(unsigned)((nw + T - 1) / T), T, 0, s>>>(tb.B, tb.LB, alpha_dev, bw);

@@ -13,10 +13,15 @@ from . import _lib
 from ._lib import Problem
 
 
+ASSEMBLY_MOMENTS = 0   # stiffness from cosine moments (Toeplitz-plus-Hankel form)
+ASSEMBLY_GEMM = 1      # stiffness as the quadrature GEMM dphi^T diag(w D) dphi on FP64 MFMA
+
+
 def make_problem(dim=1, modes=32, quad=64, steps=256, slices=8, alpha=0.5, T=1.0, d_sel=0,
-                 d_param=1.0, f_sel=0, history=0, source_time=0) -> Problem:
+                 d_param=1.0, f_sel=0, history=0, source_time=0,
+                 assembly=ASSEMBLY_MOMENTS) -> Problem:
     return Problem(dim, modes, quad, steps, slices, alpha, T, d_sel, d_param, f_sel, history,
-                   source_time)
+                   source_time, assembly)
 
 
 def nmodes(p: Problem) -> int:

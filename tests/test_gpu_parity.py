@@ -35,8 +35,8 @@ def gpu():
     return l1
 
 
-def both(gpu, orc, **kw):
-    return gpu.make_problem(**kw), orc.problem(**kw)
+def both(gpu, orc, assembly=0, **kw):
+    return gpu.make_problem(assembly=assembly, **kw), orc.problem(**kw)
 
 
 def dev(a):
@@ -79,9 +79,13 @@ def _u0(kw, seeds):
     return W.u0_batch_1d(kw["modes"], seeds)
 
 
-@pytest.mark.parametrize("name,kw,seeds", SERIAL_CASES, ids=[c[0] for c in SERIAL_CASES])
-def test_serial_matches_oracle(gpu, orc, name, kw, seeds):
-    pg, po = both(gpu, orc, **kw)
+GEMM_CASES = [c for c in SERIAL_CASES if c[0] in (
+    "config1", "small_c2_a03", "ragged_M40_Q61", "M1", "full_history", "tiles_M128")]
+GEMM_CASES += [("beyond_register_path_M272", W.with_(W.C2, modes=272, quad=300, steps=12, slices=3, alpha=0.5), [18])]
+
+
+def _serial_case(gpu, orc, name, kw, seeds, assembly):
+    pg, po = both(gpu, orc, assembly=assembly, **kw)
     u0 = _u0(kw, seeds)
     Ug, trg = run_serial(gpu, pg, u0)
     for b in range(u0.shape[0]):
@@ -91,6 +95,19 @@ def test_serial_matches_oracle(gpu, orc, name, kw, seeds):
         # each fine state, not only the aggregate
         per = [rel(trg[b][m], tro[m]) for m in range(tro.shape[0]) if np.linalg.norm(tro[m]) > 0]
         assert max(per) <= 10 * TOL, (name, b, max(per))
+
+
+@pytest.mark.parametrize("name,kw,seeds", SERIAL_CASES, ids=[c[0] for c in SERIAL_CASES])
+def test_serial_matches_oracle(gpu, orc, name, kw, seeds):
+    """Default path: cosine-moment stiffness inside the register-resident step kernel."""
+    _serial_case(gpu, orc, name, kw, seeds, assembly=0)
+
+
+@pytest.mark.parametrize("name,kw,seeds", GEMM_CASES, ids=[c[0] for c in GEMM_CASES])
+def test_serial_gemm_assembly_matches_oracle(gpu, orc, name, kw, seeds):
+    """Quadrature-GEMM stiffness on MFMA (register Cholesky for M <= 256, the blocked
+    device-memory Cholesky beyond)."""
+    _serial_case(gpu, orc, name, kw, seeds, assembly=1)
 
 
 def test_serial_per_instance_alpha(gpu, orc):
@@ -116,9 +133,10 @@ PARA_CASES = [
 ]
 
 
+@pytest.mark.parametrize("assembly", [0, 1])
 @pytest.mark.parametrize("name,kw,seeds,iters", PARA_CASES, ids=[c[0] for c in PARA_CASES])
-def test_parareal_iterates_match_oracle(gpu, orc, name, kw, seeds, iters):
-    pg, po = both(gpu, orc, **kw)
+def test_parareal_iterates_match_oracle(gpu, orc, name, kw, seeds, iters, assembly):
+    pg, po = both(gpu, orc, assembly=assembly, **kw)
     u0 = _u0(kw, seeds)
     for K in iters:
         res = gpu.solve_parareal(pg, dev(u0), K, tol=0.0, want_iterates=True)
@@ -156,12 +174,13 @@ def test_parareal_notconv_status(gpu):
 
 # ------------------------------------------------------------ GPU self-consistency
 
-def test_parareal_exact_after_P_sweeps_bitwise(gpu):
+@pytest.mark.parametrize("assembly,modes", [(0, 64), (1, 64), (1, 272)])
+def test_parareal_exact_after_P_sweeps_bitwise(gpu, assembly, modes):
     """After k sweeps the first k+1 slice ends equal the GPU serial solution bit for bit
     (finite termination of parareal, Section 3.2)."""
-    kw = W.with_(W.C2, modes=64, quad=96, steps=80, slices=10, alpha=0.3)
-    pg = gpu.make_problem(**kw)
-    u0 = dev(W.u0_batch_1d(64, [40, 41, 42]))
+    kw = W.with_(W.C2, modes=modes, quad=modes * 3 // 2, steps=80, slices=10, alpha=0.3)
+    pg = gpu.make_problem(assembly=assembly, **kw)
+    u0 = dev(W.u0_batch_1d(modes, [40, 41, 42]))
     Us, _ = gpu.solve_serial(pg, u0)
     res = gpu.solve_parareal(pg, u0, 10, tol=0.0, want_iterates=True)
     torch.cuda.synchronize()
@@ -209,21 +228,21 @@ def test_invalid_arguments_rejected(gpu):
 
 # ------------------------------------------------- full size (config 2), sampled
 
-@pytest.fixture(scope="module")
-def c2_full(gpu):
+@pytest.fixture(scope="module", params=[0, 1], ids=["moments", "gemm"])
+def c2_full(gpu, request):
     kw = W.with_(W.C2, alpha=0.3)
-    pg = gpu.make_problem(**kw)
+    pg = gpu.make_problem(assembly=request.param, **kw)
     u0 = W.u0_batch_1d(256, range(W.C2_BATCH))
     U, _ = gpu.solve_serial(pg, dev(u0))
     torch.cuda.synchronize()
-    return kw, u0, U.cpu().numpy()
+    return kw, u0, U.cpu().numpy(), request.param
 
 
 def test_full_size_serial_sampled_slices(gpu, orc, c2_full):
     """Full config-2 size (B = 32, M = 256, Q = 384, N = 4096, P = 64): the oracle's fine
     propagator on the GPU's slice ends C_0..C_n reproduces the GPU's C_{n+1} for sampled
     (instance, slice) pairs."""
-    kw, u0, U = c2_full
+    kw, u0, U, asm = c2_full
     po = orc.problem(**kw)
     for b, n in ((0, 0), (17, 1), (31, 63)):
         ref = orc.fine_F(po, n, U[b, : n + 1])
@@ -231,8 +250,8 @@ def test_full_size_serial_sampled_slices(gpu, orc, c2_full):
 
 
 def test_full_size_parareal_prefix_exact(gpu, c2_full):
-    kw, u0, U = c2_full
-    pg = gpu.make_problem(**kw)
+    kw, u0, U, asm = c2_full
+    pg = gpu.make_problem(assembly=asm, **kw)
     res = gpu.solve_parareal(pg, dev(u0), 3, tol=0.0, want_iterates=True)
     torch.cuda.synchronize()
     its = res.iterates.cpu().numpy()
