@@ -119,6 +119,25 @@ l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double
                               const double* u0, double* U, double* traj,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* The two propagators on given slice ends, for every slice at once (Section 2.2):
+ *   l1pr_coarse_apply: out[b][n] = G_n(Z_b[0..n])   (one coarse L1 step of size T/P),
+ *   l1pr_fine_apply:   out[b][n] = F_n(Z_b[0..n])   (S fine steps with the hybrid history),
+ * for n = 0..P-1.  These are the parallel stage of parareal as stand-alone operations (and,
+ * applied to a serial solution, the training pairs of the learned coarse propagator).
+ *   alpha : host [batch] per-instance orders, or NULL for p->alpha.
+ *   Z     : device [batch][P+1][Md];  out : device [batch][P][Md].
+ *   ws    : device workspace >= l1pr_workspace_bytes(p, batch, L1PR_OP_PARAREAL). */
+l1pr_status l1pr_coarse_apply(const l1pr_problem* p, int32_t batch, const double* alpha,
+                              const double* Z, double* out, void* ws, size_t ws_bytes,
+                              void* stream);
+l1pr_status l1pr_fine_apply(const l1pr_problem* p, int32_t batch, const double* alpha,
+                            const double* Z, double* out, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Coarse propagators of parareal. */
+enum { L1PR_COARSE_L1 = 0,       /* the coarse L1 step G of Section 2.1 */
+       L1PR_COARSE_LEARNED = 1   /* G plus a learned residual correction (below) */ };
+
 /* Parareal solve of `batch` instances (hybrid history only), Section 2.2.
  *   max_iter : number of fine sweeps allowed, 0 <= max_iter <= P.
  *   tol      : > 0 stops after the sweep whose relative increment
@@ -134,6 +153,68 @@ l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const doub
                                 const double* u0, double* U, int32_t max_iter, double tol,
                                 double* U_iters, double* incr, int32_t* iters,
                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Parareal with a chosen coarse propagator.  coarse = L1PR_COARSE_L1 is l1pr_solve_parareal;
+ * coarse = L1PR_COARSE_LEARNED uses G_L,n = G_n + r with the residual r from the network in
+ * `mlp_params` (device, layout from l1pr_mlp_layout for M = p->modes, 1D, M <= 256).  The
+ * network is a deterministic function of its input, so parareal keeps its exactness (after k
+ * sweeps the first k+1 slice ends equal the serial solution).  A unit whose correction is not
+ * finite or larger than ||G_n|| + 1 uses the plain G_n (the plain coarse step is the fallback).
+ * ws_bytes must also cover l1pr_parareal_learned_extra_bytes(p, batch) more bytes. */
+l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const double* alpha,
+                                   const double* u0, double* U, int32_t max_iter, double tol,
+                                   int32_t coarse, const void* mlp_params, double* U_iters,
+                                   double* incr, int32_t* iters, void* ws, size_t ws_bytes,
+                                   void* stream);
+size_t l1pr_parareal_learned_extra_bytes(const l1pr_problem* p, int32_t batch);
+
+/* ---- Learned coarse propagator (configuration with a residual MLP) ----------------------
+ * Network: inputs x = [G_n coefficients (M) ; alpha ; n/P] (M + 2), normalised per column
+ * with the stored mean and standard deviation; three hidden layers of 512 units with SiLU
+ * activation z / (1 + exp(-z)); M outputs, the normalised residual F_n - G_n, mapped back with
+ * the stored output mean and standard deviation.  Weights and activations are BF16, products
+ * accumulate in FP32 (MFMA), biases and normalisation are FP32.
+ *   params : device blob read by inference (normalisation, biases, BF16 weights [out][in] with
+ *            the inner dimension padded); offsets and sizes from l1pr_mlp_layout.
+ *   state  : device FP32 [3][flat_count]: master parameters, Adam first and second moments;
+ *            the flat order is W1 b1 W2 b2 W3 b3 W4 b4 (each W row-major [out][in_padded]).
+ * Training data and initial weights are supplied by the caller. */
+typedef struct {
+  int32_t in, in_padded, hidden, out, out_padded;
+  size_t  param_bytes, state_bytes;
+  int64_t flat_count;
+  size_t  off_in_mean, off_in_std, off_out_mean, off_out_std;   /* FP32 arrays in params */
+  size_t  off_w[4], off_b[4];                                   /* in params */
+  int64_t flat_w[4], flat_b[4];                                 /* element offsets in state */
+} l1pr_mlp_info;
+
+l1pr_status l1pr_mlp_layout(int32_t modes, l1pr_mlp_info* info);
+size_t      l1pr_mlp_workspace_bytes(int32_t modes, int32_t n, int32_t train);
+/* params weights/biases <- state masters (BF16 rounding to nearest even). */
+l1pr_status l1pr_mlp_sync(int32_t modes, const void* state, void* params, void* stream);
+/* zero the Adam moments in state */
+l1pr_status l1pr_mlp_reset_moments(int32_t modes, void* state, void* stream);
+/* per-column mean and (population) standard deviation of x [n][M+2] and t [n][M] into params
+ * (a column with no spread gets standard deviation 1) */
+l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_t n,
+                           void* params, void* stream);
+/* training pairs from slice ends Z [B][P+1][M] and coarse values G [B][P][M] (device FP64):
+ * x [B*P][M+2] = [G_n ; alpha_b ; n/P],  t [B*P][M] = Z_{n+1} - G_n  (device FP32, row b*P+n);
+ * alpha is a device array [B]. */
+l1pr_status l1pr_mlp_features(int32_t modes, int32_t batch, int32_t slices, const double* alpha,
+                              const double* Z, const double* G, float* x, float* t,
+                              void* stream);
+/* y [n][M] = normalised network output for raw inputs x [n][M+2] (device FP32). */
+l1pr_status l1pr_mlp_forward(int32_t modes, const void* params, const float* x, int32_t n,
+                             float* y, void* ws, size_t ws_bytes, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction with `step`, 1-based) on the
+ * mean squared error of the normalised output over the rows idx[0..n) (device int32, or NULL
+ * for rows 0..n-1) of x [*][M+2] and t [*][M]; then params <- masters.  loss (device FP32 [1])
+ * and grad_out (device FP32 [flat_count], the gradient before the update) may be NULL. */
+l1pr_status l1pr_mlp_train_step(int32_t modes, void* params, void* state, const float* x,
+                                const float* t, const int32_t* idx, int32_t n, float lr,
+                                int32_t step, float* loss, float* grad_out, void* ws,
+                                size_t ws_bytes, void* stream);
 
 /* Kernel-launch profiling (for benchmarks).  After l1pr_profile_start(), every step kernel
  * that the solvers enqueue is bracketed by two HIP events recorded on its stream.

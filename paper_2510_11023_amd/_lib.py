@@ -43,6 +43,19 @@ class KernelStat(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class MlpInfo(ctypes.Structure):
+    """Mirror of l1pr_mlp_info."""
+
+    _fields_ = [("in_", ctypes.c_int32), ("in_padded", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("out", ctypes.c_int32), ("out_padded", ctypes.c_int32),
+                ("param_bytes", ctypes.c_size_t), ("state_bytes", ctypes.c_size_t),
+                ("flat_count", ctypes.c_int64),
+                ("off_in_mean", ctypes.c_size_t), ("off_in_std", ctypes.c_size_t),
+                ("off_out_mean", ctypes.c_size_t), ("off_out_std", ctypes.c_size_t),
+                ("off_w", ctypes.c_size_t * 4), ("off_b", ctypes.c_size_t * 4),
+                ("flat_w", ctypes.c_int64 * 4), ("flat_b", ctypes.c_int64 * 4)]
+
+
 class L1prError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -72,6 +85,36 @@ def lib():
                                           ctypes.c_double, vp, vp, ctypes.POINTER(ctypes.c_int32),
                                           vp, ctypes.c_size_t, vp]
         L.l1pr_solve_parareal.restype = ctypes.c_int
+        L.l1pr_solve_parareal_ex.argtypes = [pp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_int32, vp, vp, vp,
+                                             ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
+        L.l1pr_solve_parareal_ex.restype = ctypes.c_int
+        L.l1pr_parareal_learned_extra_bytes.argtypes = [pp, ctypes.c_int32]
+        L.l1pr_parareal_learned_extra_bytes.restype = ctypes.c_size_t
+        for name in ("l1pr_coarse_apply", "l1pr_fine_apply"):
+            f = getattr(L, name)
+            f.argtypes = [pp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+            f.restype = ctypes.c_int
+        L.l1pr_mlp_layout.argtypes = [ctypes.c_int32, ctypes.POINTER(MlpInfo)]
+        L.l1pr_mlp_layout.restype = ctypes.c_int
+        L.l1pr_mlp_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.l1pr_mlp_workspace_bytes.restype = ctypes.c_size_t
+        L.l1pr_mlp_sync.argtypes = [ctypes.c_int32, vp, vp, vp]
+        L.l1pr_mlp_sync.restype = ctypes.c_int
+        L.l1pr_mlp_reset_moments.argtypes = [ctypes.c_int32, vp, vp]
+        L.l1pr_mlp_reset_moments.restype = ctypes.c_int
+        L.l1pr_mlp_stats.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int64, vp, vp]
+        L.l1pr_mlp_stats.restype = ctypes.c_int
+        L.l1pr_mlp_features.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                        vp, vp, vp]
+        L.l1pr_mlp_features.restype = ctypes.c_int
+        L.l1pr_mlp_forward.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
+                                       ctypes.c_size_t, vp]
+        L.l1pr_mlp_forward.restype = ctypes.c_int
+        L.l1pr_mlp_train_step.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int32,
+                                          ctypes.c_float, ctypes.c_int32, vp, vp, vp,
+                                          ctypes.c_size_t, vp]
+        L.l1pr_mlp_train_step.restype = ctypes.c_int
         L.l1pr_profile_start.argtypes = []
         L.l1pr_profile_start.restype = None
         L.l1pr_profile_stop.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32]

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "l1pr_internal.h"
+#include "l1pr_mlp.h"
 
 namespace l1pr {
 
@@ -307,17 +308,71 @@ l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_
   return L1PR_OK;
 }
 
-// One coarse step G_n over all instances; `e` decides what is stored.
-l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e) {
+// Learned coarse propagator: network parameters and scratch (plain G values, network
+// activations) carved after the solver's own workspace.
+struct Learned {
+  const void* params = nullptr;
+  MlpLayout L{};
+  double* G = nullptr;  // [B][Mp]
+  void* ws = nullptr;
+};
+
+size_t learned_extra_bytes(const Tables& tb) {
+  const MlpLayout L = mlp_layout(tb.M);
+  return (sizeof(double) * (size_t)tb.B * tb.Mp + 255) / 256 * 256 + mlp_ws_bytes(L, tb.B, false);
+}
+
+// One coarse step G_n over all instances; `e` decides what is stored.  With a learned
+// propagator, the plain step goes to a scratch vector and the network adds its correction
+// before the epilogue.
+l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e, const Learned* lg) {
   StepArgs a = base_args(c);
   a.mode = MODE_COARSE;
   a.n = n;
   a.Z = Z;
-  return run_step(c, a, e, c.tb.B);
+  if (!lg) return run_step(c, a, e, c.tb.B);
+  Epilogue tmp{};
+  tmp.kind = EPI_STORE;
+  tmp.out = lg->G;
+  tmp.out_stride = c.tb.Mp;
+  l1pr_status st = run_step(c, a, tmp, c.tb.B);
+  if (st != L1PR_OK) return st;
+  L1PR_TRY(timed("mlp", a, c.tb.B, c.s, [&] {
+    return mlp_coarse_apply(lg->L, lg->params, lg->G, c.tb.Mp, c.tb.inst, c.tb.B, c.tb.M, c.tb.Mp,
+                            n, c.tb.P, e, lg->ws, c.s);
+  }));
+  return L1PR_OK;
+}
+
+// All B*P fine propagators at once on the slice ends Z: traj[b*P + n][r] = c_{n,r}.
+l1pr_status fine_sweep(const Ctx& c, const double* Z) {
+  const Tables& tb = c.tb;
+  const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp;
+  const long slotS = (long)(S + 1) * Mp;
+  double* traj = c.ptr(c.L.traj);
+  L1PR_TRY(launch_fill_slot0(tb, Z, traj, B, P, c.s));
+  for (int r = 1; r <= S; ++r) {
+    StepArgs a = base_args(c);
+    a.mode = MODE_FINE;
+    a.r = r;
+    a.nP = P;
+    a.n_lo = 0;
+    a.traj = traj;
+    a.trajP = P;
+    a.trajN0 = 0;
+    a.Z = Z;
+    Epilogue e{};
+    e.kind = EPI_STORE;
+    e.out = traj + (long)r * Mp;
+    e.out_stride = slotS;
+    l1pr_status st = run_step(c, a, e, B * P);
+    if (st != L1PR_OK) return st;
+  }
+  return L1PR_OK;
 }
 
 l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, double tol,
-                     double* U_iters, double* incr, int* iters_out) {
+                     double* U_iters, double* incr, int* iters_out, const Learned* lg) {
   const Tables& tb = c.tb;
   const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp, M = tb.M;
   const long vecP = (long)(P + 1) * Mp, slotS = (long)(S + 1) * Mp;
@@ -337,7 +392,7 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
     e.out_stride = vecP;
     e.gold = Gold + (long)n * Mp;
     e.gold_stride = (long)P * Mp;
-    l1pr_status st = coarse_step(c, Zk, n, e);
+    l1pr_status st = coarse_step(c, Zk, n, e, lg);
     if (st != L1PR_OK) return st;
   }
   if (U_iters) L1PR_TRY(launch_unpack(Zk, Mp, vecP, U_iters, M, (long)(P + 1) * M, P + 1, B, c.s));
@@ -347,24 +402,8 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   std::vector<double> h_incr(B);
   for (int k = 0; k < max_iter; ++k) {
     // parallel stage: F_old(n) = F_n(U^k_0..U^k_n) for all (b, n)
-    L1PR_TRY(launch_fill_slot0(tb, Zk, traj, B, P, c.s));
-    for (int r = 1; r <= S; ++r) {
-      StepArgs a = base_args(c);
-      a.mode = MODE_FINE;
-      a.r = r;
-      a.nP = P;
-      a.n_lo = 0;
-      a.traj = traj;
-      a.trajP = P;
-      a.trajN0 = 0;
-      a.Z = Zk;
-      Epilogue e{};
-      e.kind = EPI_STORE;
-      e.out = traj + (long)r * Mp;
-      e.out_stride = slotS;
-      l1pr_status st = run_step(c, a, e, B * P);
-      if (st != L1PR_OK) return st;
-    }
+    l1pr_status stf = fine_sweep(c, Zk);
+    if (stf != L1PR_OK) return stf;
     // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n))
     L1PR_TRY(launch_pack(u0, M, B, M, Zk1, Mp, vecP, c.s));
     for (int n = 0; n < P; ++n) {
@@ -376,7 +415,7 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
       e.gold_stride = (long)P * Mp;
       e.fold = traj + ((long)n * (S + 1) + S) * Mp;
       e.fold_stride = (long)P * slotS;
-      l1pr_status st = coarse_step(c, Zk1, n, e);
+      l1pr_status st = coarse_step(c, Zk1, n, e, lg);
       if (st != L1PR_OK) return st;
     }
     L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, c.s));
@@ -443,20 +482,103 @@ l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double
   }
 }
 
+l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const double* alpha,
+                                   const double* u0, double* U, int32_t max_iter, double tol,
+                                   int32_t coarse, const void* mlp_params, double* U_iters,
+                                   double* incr, int32_t* iters, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  try {
+    if (!u0 || !U || !p) return L1PR_EINVAL;
+    if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
+    if (coarse != L1PR_COARSE_L1 && coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
+    const bool learned = coarse == L1PR_COARSE_LEARNED;
+    if (learned && (!mlp_params || p->dim != 1 || p->modes > kMlpMaxModes)) return L1PR_EINVAL;
+    Ctx c;
+    l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
+    if (st != L1PR_OK) return st;
+    Learned lg;
+    if (learned) {
+      if (ws_bytes < c.L.total + learned_extra_bytes(c.tb)) return L1PR_ENOMEM;
+      lg.params = mlp_params;
+      lg.L = mlp_layout(c.tb.M);
+      lg.G = c.ptr(c.L.total);
+      lg.ws = c.ws + c.L.total + (sizeof(double) * (size_t)c.tb.B * c.tb.Mp + 255) / 256 * 256;
+    }
+    int it = 0;
+    st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it, learned ? &lg : nullptr);
+    if (iters) *iters = it;
+    return st;
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
 l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const double* alpha,
                                 const double* u0, double* U, int32_t max_iter, double tol,
                                 double* U_iters, double* incr, int32_t* iters, void* ws,
                                 size_t ws_bytes, void* stream) {
+  return l1pr_solve_parareal_ex(p, batch, alpha, u0, U, max_iter, tol, L1PR_COARSE_L1, nullptr,
+                                U_iters, incr, iters, ws, ws_bytes, stream);
+}
+
+size_t l1pr_parareal_learned_extra_bytes(const l1pr_problem* p, int32_t batch) {
+  if (!valid(p) || batch < 1 || p->modes > kMlpMaxModes) return 0;
+  Layout L;
+  Tables tb;
+  make_layout(p, batch, L1PR_OP_PARAREAL, L, tb);
+  return learned_extra_bytes(tb);
+}
+
+l1pr_status l1pr_coarse_apply(const l1pr_problem* p, int32_t batch, const double* alpha,
+                              const double* Z, double* out, void* ws, size_t ws_bytes,
+                              void* stream) {
   try {
-    if (!u0 || !U || !p) return L1PR_EINVAL;
-    if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
+    if (!Z || !out) return L1PR_EINVAL;
     Ctx c;
     l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
-    int it = 0;
-    st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it);
-    if (iters) *iters = it;
-    return st;
+    if (p->history != 0) return L1PR_EINVAL;
+    const Tables& tb = c.tb;
+    const int B = tb.B, P = tb.P, Mp = tb.Mp, M = tb.M;
+    const long vecP = (long)(P + 1) * Mp;
+    double* Zp = c.ptr(c.L.Z0);
+    double* Gout = c.ptr(c.L.Gold);
+    L1PR_TRY(launch_unpack_pad(Z, M, (long)(P + 1) * M, Zp, Mp, vecP, P + 1, B, c.s));
+    for (int n = 0; n < P; ++n) {
+      Epilogue e{};
+      e.kind = EPI_STORE;
+      e.out = Gout + (long)n * Mp;
+      e.out_stride = (long)P * Mp;
+      st = coarse_step(c, Zp, n, e, nullptr);
+      if (st != L1PR_OK) return st;
+    }
+    L1PR_TRY(launch_unpack(Gout, Mp, (long)P * Mp, out, M, (long)P * M, P, B, c.s));
+    return L1PR_OK;
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
+l1pr_status l1pr_fine_apply(const l1pr_problem* p, int32_t batch, const double* alpha,
+                            const double* Z, double* out, void* ws, size_t ws_bytes,
+                            void* stream) {
+  try {
+    if (!Z || !out) return L1PR_EINVAL;
+    Ctx c;
+    l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
+    if (st != L1PR_OK) return st;
+    if (p->history != 0) return L1PR_EINVAL;
+    const Tables& tb = c.tb;
+    const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp, M = tb.M;
+    const long vecP = (long)(P + 1) * Mp;
+    double* Zp = c.ptr(c.L.Z0);
+    L1PR_TRY(launch_unpack_pad(Z, M, (long)(P + 1) * M, Zp, Mp, vecP, P + 1, B, c.s));
+    st = fine_sweep(c, Zp);
+    if (st != L1PR_OK) return st;
+    // slot b*P + n, row S  ->  out[b][n]
+    L1PR_TRY(launch_unpack(c.ptr(c.L.traj) + (long)S * Mp, Mp, (long)(S + 1) * Mp, out, M, M, 1,
+                           B * P, c.s));
+    return L1PR_OK;
   } catch (...) {
     return L1PR_EHIP;
   }

@@ -218,6 +218,8 @@ hipError_t launch_fill_slot0(const Tables& tb, const double* Z, double* traj, in
                              hipStream_t s);
 hipError_t launch_unpack(const double* src, int Mp, long src_stride, double* dst, int M,
                          long dst_stride, int rows_per_unit, int units, hipStream_t s);
+hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* dst, int Mp,
+                             long dst_stride, int rows_per_unit, int units, hipStream_t s);
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
                             hipStream_t s);

@@ -385,6 +385,26 @@ hipError_t launch_unpack(const double* src, int Mp, long src_stride, double* dst
   return hipGetLastError();
 }
 
+// dst[u][row][k] = src[u][row][k] for k < M, 0 for M <= k < Mp (adds the padding)
+__global__ void k_unpack_pad(const double* src, int M, long sstr, double* dst, int Mp, long dstr,
+                             int rows, int units) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)rows * Mp;
+  if (idx >= per * units) return;
+  const long u = idx / per, e = idx % per;
+  const long row = e / Mp, k = e % Mp;
+  dst[u * dstr + row * Mp + k] = (k < M) ? src[u * sstr + row * M + k] : 0.0;
+}
+
+hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* dst, int Mp,
+                             long dst_stride, int rows_per_unit, int units, hipStream_t s) {
+  const long n = (long)rows_per_unit * Mp * units;
+  if (n == 0) return hipSuccess;
+  k_unpack_pad<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, M, src_stride, dst, Mp, dst_stride,
+                                                           rows_per_unit, units);
+  return hipGetLastError();
+}
+
 // Relative increment ||Znew_b - Zold_b|| / ||Znew_b|| per instance, fixed-order tree
 // reduction (one work-group per instance).
 __global__ __launch_bounds__(256) void k_increment(const double* Znew, const double* Zold, int rows,

@@ -90,10 +90,51 @@ class PararealResult:
     iterates: torch.Tensor | None
 
 
+COARSE_L1 = 0
+COARSE_LEARNED = 1
+
+
+def parareal_workspace(p: Problem, batch: int, device, learned: bool = False) -> torch.Tensor:
+    n = workspace_bytes(p, batch, _lib.OP_PARAREAL)
+    if learned:
+        n += int(_lib.lib().l1pr_parareal_learned_extra_bytes(ctypes.byref(p), batch))
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _apply(name, p, Z, alpha, workspace):
+    if not (Z.is_cuda and Z.dtype == torch.float64 and Z.is_contiguous()):
+        raise ValueError("Z must be a contiguous float64 device tensor")
+    B = Z.shape[0]
+    Md = nmodes(p)
+    if tuple(Z.shape[1:]) != (p.slices + 1, Md):
+        raise ValueError(f"Z must have shape [batch, {p.slices + 1}, {Md}]")
+    out = torch.empty((B, p.slices, Md), dtype=torch.float64, device=Z.device)
+    if workspace is None:
+        workspace = parareal_workspace(p, B, Z.device)
+    keep, aptr = _alpha_arg(alpha, B)
+    st = getattr(_lib.lib(), name)(ctypes.byref(p), B, aptr, _ptr(Z), _ptr(out), _ptr(workspace),
+                                   workspace.numel(), _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, name)
+    return out
+
+
+def coarse_apply(p: Problem, Z: torch.Tensor, alpha=None, workspace=None) -> torch.Tensor:
+    """out[b][n] = G_n(Z_b[0..n]) for every slice n (one coarse L1 step each)."""
+    return _apply("l1pr_coarse_apply", p, Z, alpha, workspace)
+
+
+def fine_apply(p: Problem, Z: torch.Tensor, alpha=None, workspace=None) -> torch.Tensor:
+    """out[b][n] = F_n(Z_b[0..n]) for every slice n (the hybrid fine propagator)."""
+    return _apply("l1pr_fine_apply", p, Z, alpha, workspace)
+
+
 def solve_parareal(p: Problem, u0: torch.Tensor, max_iter: int, tol: float = 0.0, alpha=None,
                    want_iterates: bool = False, want_incr: bool = True,
-                   workspace: torch.Tensor | None = None, allow_notconv: bool = True):
-    """Parareal solve.  Returns a PararealResult; iterates is [iters+1, B, P+1, Md]."""
+                   workspace: torch.Tensor | None = None, allow_notconv: bool = True,
+                   coarse: int = COARSE_L1, mlp_params: torch.Tensor | None = None):
+    """Parareal solve.  Returns a PararealResult; iterates is [iters+1, B, P+1, Md].
+    coarse = COARSE_LEARNED uses the residual network in mlp_params (LearnedCoarse.params)."""
     _check_u0(p, u0)
     B = u0.shape[0]
     Md = nmodes(p)
@@ -103,14 +144,14 @@ def solve_parareal(p: Problem, u0: torch.Tensor, max_iter: int, tol: float = 0.0
         if want_iterates else None
     incr = torch.zeros((B, max(max_iter, 1)), dtype=torch.float64, device=dev) if want_incr else None
     if workspace is None:
-        workspace, n = _workspace(p, B, _lib.OP_PARAREAL, dev)
-    else:
-        n = workspace.numel() * workspace.element_size()
+        workspace = parareal_workspace(p, B, dev, learned=(coarse == COARSE_LEARNED))
+    n = workspace.numel() * workspace.element_size()
     keep, aptr = _alpha_arg(alpha, B)
     it = ctypes.c_int32(0)
-    st = _lib.lib().l1pr_solve_parareal(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U), int(max_iter),
-                                        float(tol), _ptr(its), _ptr(incr), ctypes.byref(it),
-                                        _ptr(workspace), n, _stream())
+    st = _lib.lib().l1pr_solve_parareal_ex(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U),
+                                           int(max_iter), float(tol), int(coarse), _ptr(mlp_params),
+                                           _ptr(its), _ptr(incr), ctypes.byref(it),
+                                           _ptr(workspace), n, _stream())
     if st != _lib.OK and not (allow_notconv and st == _lib.ENOTCONV):
         raise _lib.L1prError(st, "l1pr_solve_parareal")
     k = it.value

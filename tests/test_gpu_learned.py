@@ -1,0 +1,245 @@
+"""GPU tests of the learned coarse propagator and the stand-alone propagator operations.
+
+FP64 operations (coarse_apply, fine_apply) match the oracle to 1e-10 relative L2.  The
+network is BF16 with FP32 accumulation: its forward output and gradients are compared with
+the numpy reference at a tolerance set by BF16 rounding (2^-8 relative per rounding; a
+single flipped rounding of an activation moves an output by about that much), and the
+learned parareal is checked for what does not depend on rounding: exactness against the
+GPU serial solution, and the fallback to the plain coarse step.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_2510_11023_amd import workloads as W  # noqa: E402
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_11023_amd as l1
+    from paper_2510_11023_amd import _lib
+
+    _lib.lib()
+    return l1
+
+
+def dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+SMALL = W.with_(W.C4, modes=32, quad=48, steps=48, slices=8, alpha=0.5)
+
+
+def test_coarse_and_fine_apply_match_oracle(gpu, orc):
+    kw = SMALL
+    pg, po = gpu.make_problem(**kw), orc.problem(**kw)
+    rng = np.random.default_rng(3)
+    B, P, M = 3, kw["slices"], kw["modes"]
+    Z = rng.normal(size=(B, P + 1, M)) * (np.arange(1, M + 1) ** -1.5)
+    G = gpu.coarse_apply(pg, dev(Z)).cpu().numpy()
+    F = gpu.fine_apply(pg, dev(Z)).cpu().numpy()
+    for b in range(B):
+        for n in range(P):
+            assert rel(G[b, n], orc.coarse_G(po, n, Z[b, : n + 1])) <= 1e-10
+            assert rel(F[b, n], orc.fine_F(po, n, Z[b, : n + 1])) <= 1e-10
+
+
+def test_fine_apply_on_serial_solution_is_its_next_slice_end(gpu):
+    """F_n(C*_0..C*_n) = C*_{n+1} bitwise for the GPU serial solution (the fixed point)."""
+    pg = gpu.make_problem(**SMALL)
+    u0 = dev(W.u0_batch_1d(SMALL["modes"], [1, 2]))
+    Z, _ = gpu.solve_serial(pg, u0)
+    F = gpu.fine_apply(pg, Z)
+    assert torch.equal(F, Z[:, 1:])
+
+
+@pytest.fixture(scope="module")
+def net(gpu):
+    from paper_2510_11023_amd.learned import LearnedCoarse
+
+    M = 32
+    model = LearnedCoarse(M, seed=5)
+    rng = np.random.default_rng(6)
+    x = dev(rng.normal(size=(512, M + 2)) * 0.3 + 0.1, torch.float32)
+    t = dev(rng.normal(size=(512, M)) * 0.01, torch.float32)
+    model.set_stats(x, t)
+    torch.cuda.synchronize()
+    return model, x, t
+
+
+def _oracle_params(model):
+    ws, bs = model.param_arrays()
+    return ws, bs, model.norms()
+
+
+def test_mlp_stats(gpu, net):
+    model, x, t = net
+    im, isd, omu, osd = model.norms()
+    xn, tn = x.cpu().numpy().astype(np.float64), t.cpu().numpy().astype(np.float64)
+    assert np.allclose(im, xn.mean(0), rtol=1e-6, atol=1e-7)
+    assert np.allclose(isd, xn.std(0), rtol=1e-6)
+    assert np.allclose(omu, tn.mean(0), rtol=1e-5, atol=1e-8)
+    assert np.allclose(osd, tn.std(0), rtol=1e-6)
+
+
+def test_mlp_forward_matches_oracle(gpu, net):
+    from oracle import mlp as om
+
+    model, x, t = net
+    ws, bs, norms = _oracle_params(model)
+    y = model.forward(x[:200]).cpu().numpy()
+    ref = om.forward(ws, bs, norms, x[:200].cpu().numpy(), model.info.in_padded)[:, : model.modes]
+    assert rel(y, ref) <= 1e-2, rel(y, ref)
+
+
+def test_mlp_gradient_and_adam_match_oracle(gpu, net):
+    from oracle import mlp as om
+    from paper_2510_11023_amd.learned import LearnedCoarse
+
+    _, x, t = net
+    model = LearnedCoarse(32, seed=9)
+    model.set_stats(x, t)
+    ws, bs, norms = _oracle_params(model)
+    w0 = model.masters()
+    n = 256
+    _, gW, gb = om.loss_and_grads(ws, bs, norms, x[:n].cpu().numpy(), t[:n].cpu().numpy(),
+                                  model.info.in_padded, model.modes)
+    from paper_2510_11023_amd import _lib
+
+    wsb = torch.empty(_lib.lib().l1pr_mlp_workspace_bytes(32, n, 1), dtype=torch.uint8, device="cuda")
+    grad = torch.zeros(model.info.flat_count, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    idx = torch.arange(n, dtype=torch.int32, device="cuda")
+    model.train_step(x, t, idx, 1e-3, wsb, loss=loss, grad=grad)
+    g = grad.cpu().numpy()
+    i = model.info
+    for l in range(4):
+        rows = gW[l].shape[0]
+        gw = g[i.flat_w[l]: i.flat_w[l] + gW[l].size].reshape(gW[l].shape)
+        assert rel(gw, gW[l]) <= 3e-2, (l, rel(gw, gW[l]))
+        assert rel(g[i.flat_b[l]: i.flat_b[l] + rows], gb[l]) <= 3e-2
+    # one Adam step on the GPU gradient gives the oracle's update exactly up to FP32 rounding
+    w1 = model.masters()
+    ref, _, _ = om.adam(w0.astype(np.float64), 0.0, 0.0, g.astype(np.float64), 1e-3, 1)
+    assert np.max(np.abs(w1 - ref)) < 1e-6
+
+
+def test_mlp_training_reduces_loss(gpu):
+    from paper_2510_11023_amd.learned import LearnedCoarse
+
+    M = 16
+    rng = np.random.default_rng(2)
+    xs = rng.normal(size=(2048, M + 2))
+    ts = np.tanh(xs[:, :M] * 0.7 + 0.2 * xs[:, M:M + 1]) * 0.05   # a smooth target
+    model = LearnedCoarse(M, seed=1)
+    x, t = dev(xs, torch.float32), dev(ts, torch.float32)
+    model.set_stats(x, t)
+    losses = model.train(x, t, epochs=6, batch=256, lr=2e-3, seed=0)
+    assert losses[-1] < 0.2 * losses[0], losses
+
+
+# -------------------------------------------------------------- learned parareal
+
+def _trained(gpu, kw, alphas, seeds, epochs=3):
+    from paper_2510_11023_amd.learned import LearnedCoarse, training_data
+
+    pg = gpu.make_problem(**kw)
+    model = LearnedCoarse(kw["modes"], seed=3)
+    u0 = dev(W.u0_batch_1d(kw["modes"], seeds))
+    x, t = training_data(pg, u0, alphas, model)
+    model.set_stats(x, t)
+    model.train(x, t, epochs=epochs, batch=128, lr=1e-3, seed=1)
+    return model
+
+
+def test_learned_parareal_is_exact(gpu):
+    kw = SMALL
+    alphas = list(W.alphas_uniform(64, seed=11))
+    model = _trained(gpu, kw, alphas, range(64))
+    pg = gpu.make_problem(**kw)
+    u0 = dev(W.u0_batch_1d(kw["modes"], [500, 501, 502]))
+    al = [0.35, 0.6, 0.9]
+    Us, _ = gpu.solve_serial(pg, u0, alpha=al)
+    res = gpu.solve_parareal(pg, u0, kw["slices"], alpha=al, want_iterates=True,
+                             coarse=gpu.COARSE_LEARNED, mlp_params=model.params)
+    torch.cuda.synchronize()
+    for k in range(res.iters + 1):
+        assert torch.equal(res.iterates[k][:, : k + 1], Us[:, : k + 1]), k
+    assert torch.equal(res.U, Us)
+    # deterministic
+    res2 = gpu.solve_parareal(pg, u0, 3, alpha=al, coarse=gpu.COARSE_LEARNED, mlp_params=model.params)
+    res3 = gpu.solve_parareal(pg, u0, 3, alpha=al, coarse=gpu.COARSE_LEARNED, mlp_params=model.params)
+    assert torch.equal(res2.U, res3.U)
+
+
+def test_learned_coarse_prediction_matches_oracle_composition(gpu, orc):
+    """The first learned coarse sweep against the oracle's coarse step plus the numpy
+    network, composed slice by slice (wiring of features, normalisation and correction)."""
+    from oracle import mlp as om
+
+    kw = SMALL
+    model = _trained(gpu, kw, list(W.alphas_uniform(32, seed=4)), range(32), epochs=2)
+    pg, po = gpu.make_problem(**kw), orc.problem(**kw)
+    u0 = W.u0_batch_1d(kw["modes"], [700])
+    res = gpu.solve_parareal(pg, dev(u0), 0, want_iterates=True, coarse=gpu.COARSE_LEARNED,
+                             mlp_params=model.params)
+    U0 = res.iterates[0][0].cpu().numpy()
+    ws, bs, norms = _oracle_params(model)
+    P = kw["slices"]
+    C = np.zeros((P + 1, kw["modes"]))
+    C[0] = u0[0]
+    for n in range(P):
+        g = orc.coarse_G(po, n, C[: n + 1])
+        r = om.correction(ws, bs, norms, g[None, :], [kw["alpha"]], n, P, model.info.in_padded,
+                          kw["modes"])[0]
+        C[n + 1] = g + r.astype(np.float64)
+    assert rel(U0, C) <= 2e-3, rel(U0, C)
+    Gp = gpu.solve_parareal(pg, dev(u0), 0, want_iterates=True).iterates[0][0].cpu().numpy()
+    assert rel(U0, Gp) > 10 * rel(U0, C)   # the correction is really applied
+
+
+def test_learned_falls_back_to_plain_coarse(gpu):
+    """Non-finite network output: every unit uses the plain coarse step, bit for bit."""
+    from paper_2510_11023_amd.learned import LearnedCoarse
+
+    kw = SMALL
+    model = LearnedCoarse(kw["modes"], seed=2)
+    bad = model.masters()
+    bad[model.info.flat_b[3]] = np.nan
+    model.set_masters(bad)
+    pg = gpu.make_problem(**kw)
+    u0 = dev(W.u0_batch_1d(kw["modes"], [9, 10]))
+    a = gpu.solve_parareal(pg, u0, 2, coarse=gpu.COARSE_LEARNED, mlp_params=model.params)
+    b = gpu.solve_parareal(pg, u0, 2)
+    assert torch.equal(a.U, b.U)
+
+
+def test_features_match_definition(gpu):
+    from paper_2510_11023_amd.learned import LearnedCoarse
+
+    kw = SMALL
+    M, P = kw["modes"], kw["slices"]
+    rng = np.random.default_rng(8)
+    Z = rng.normal(size=(2, P + 1, M))
+    G = rng.normal(size=(2, P, M))
+    al = np.array([0.3, 0.8])
+    model = LearnedCoarse(M, seed=0)
+    x, t = model.features(gpu.make_problem(**kw), dev(Z), dev(G), dev(al))
+    x, t = x.cpu().numpy(), t.cpu().numpy()
+    for b in range(2):
+        for n in range(P):
+            s = b * P + n
+            assert np.array_equal(x[s, :M], G[b, n].astype(np.float32))
+            assert x[s, M] == np.float32(al[b]) and x[s, M + 1] == np.float32(n / P)
+            assert np.array_equal(t[s], (Z[b, n + 1] - G[b, n]).astype(np.float32))
