@@ -194,8 +194,9 @@ size_t      l1pr_mlp_workspace_bytes(int32_t modes, int32_t n, int32_t train);
 l1pr_status l1pr_mlp_sync(int32_t modes, const void* state, void* params, void* stream);
 /* zero the Adam moments in state */
 l1pr_status l1pr_mlp_reset_moments(int32_t modes, void* state, void* stream);
-/* per-column mean and (population) standard deviation of x [n][M+2] and t [n][M] into params
- * (a column with no spread gets standard deviation 1) */
+/* normalisation into params: per-column mean and (population) standard deviation of the
+ * inputs x [n][M+2] (a column with no spread gets 1); per-mode mean of the targets t [n][M]
+ * and one common output scale, the root mean square of the per-mode standard deviations */
 l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_t n,
                            void* params, void* stream);
 /* training pairs from slice ends Z [B][P+1][M] and coarse values G [B][P][M] (device FP64):
@@ -204,9 +205,17 @@ l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_
 l1pr_status l1pr_mlp_features(int32_t modes, int32_t batch, int32_t slices, const double* alpha,
                               const double* Z, const double* G, float* x, float* t,
                               void* stream);
-/* y [n][M] = normalised network output for raw inputs x [n][M+2] (device FP32). */
+/* y [n][M] = normalised network output for raw inputs x [n][M+2] (device FP32), evaluated as
+ * in training (activations rounded to BF16 between layers). */
 l1pr_status l1pr_mlp_forward(int32_t modes, const void* params, const float* x, int32_t n,
                              float* y, void* ws, size_t ws_bytes, void* stream);
+/* The same network evaluated as parareal uses it, in FP64: BF16 weights (exact in FP64), FP64
+ * activations and sums.  x [n][M+2] raw inputs, y [n][M] normalised output (device FP64).
+ * The parareal correction G_L(U^{k+1}) - G_L(U^k) then vanishes as U^{k+1} -> U^k down to
+ * FP64 rounding; a shorter activation format would floor it at that format's resolution. */
+l1pr_status l1pr_mlp_infer(int32_t modes, const void* params, const double* x, int32_t n,
+                           double* y, void* ws, size_t ws_bytes, void* stream);
+size_t      l1pr_mlp_infer_workspace_bytes(int32_t modes, int32_t n);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction with `step`, 1-based) on the
  * mean squared error of the normalised output over the rows idx[0..n) (device int32, or NULL
  * for rows 0..n-1) of x [*][M+2] and t [*][M]; then params <- masters.  loss (device FP32 [1])

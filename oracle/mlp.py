@@ -5,6 +5,10 @@ Definition (shared with the HIP library only through this description):
   z_l = W_l h_{l-1} + b_l  (BF16 weights and inputs, exact products, sums rounded to FP32),
   h_l = BF16(silu(z_l)),  silu(z) = z / (1 + exp(-z)),  l = 1, 2, 3;
   o = W_4 h_3 + b_4 (FP32): the normalised residual; r = o * out_std + out_mean.
+Inside parareal the same network is evaluated in FP64 (the BF16 weights are exact in FP64;
+inputs, activations and sums in FP64): forward(..., exact=True).
+Normalisation: per-column input mean/std; per-mode output mean and one common output scale
+(the root mean square of the per-mode standard deviations).
 Loss: mean over rows and the M real outputs of (o - (t - out_mean) / out_std)^2.
 Backward as the library forms it: dO = BF16(2 (o - tn) / (n M)); dW_l = dZ_l^T h_{l-1};
 db_l = column sums of dZ_l; dZ_{l-1} = BF16((dZ_l W_l) * silu'(z_{l-1})).
@@ -52,7 +56,8 @@ def _ident(x):
 
 def forward(ws, bs, norms, x_raw, in_padded, keep=False, exact=False):
     """ws: BF16-valued weights [out][in_padded] (float32 arrays); bs: FP32 biases.
-    Returns o [n][out_padded] (and the intermediates when keep)."""
+    Returns o [n][out_padded] (and the intermediates when keep).  exact=True evaluates in
+    float64 throughout (the inference form used inside parareal)."""
     rnd = _ident if exact else bf16
     ft = np.float64 if exact else np.float32
     in_mean, in_std, out_mean, out_std = norms
@@ -109,12 +114,13 @@ def adam(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def correction(ws, bs, norms, G, alpha, n, P, in_padded, out):
-    """Denormalised residual r for coarse values G [B][M] at slice n (FP32 network)."""
+    """Denormalised residual r for coarse values G [B][M] at slice n, the network evaluated in
+    float64 as inside parareal."""
     B, M = G.shape
-    x = np.zeros((B, M + 2), dtype=np.float32)
-    x[:, :M] = G.astype(np.float32)
-    x[:, M] = np.asarray(alpha, dtype=np.float32)
-    x[:, M + 1] = np.float32(n / P)
-    o = forward(ws, bs, norms, x, in_padded)
+    x = np.zeros((B, M + 2), dtype=np.float64)
+    x[:, :M] = G
+    x[:, M] = np.asarray(alpha, dtype=np.float64)
+    x[:, M + 1] = n / P
+    o = forward(ws, bs, norms, x, in_padded, exact=True)
     in_mean, in_std, out_mean, out_std = norms
-    return (o[:, :out] * out_std + out_mean).astype(np.float32)
+    return o[:, :out] * out_std.astype(np.float64) + out_mean.astype(np.float64)

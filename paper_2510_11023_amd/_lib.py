@@ -111,6 +111,11 @@ def lib():
         L.l1pr_mlp_forward.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
                                        ctypes.c_size_t, vp]
         L.l1pr_mlp_forward.restype = ctypes.c_int
+        L.l1pr_mlp_infer.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
+                                     ctypes.c_size_t, vp]
+        L.l1pr_mlp_infer.restype = ctypes.c_int
+        L.l1pr_mlp_infer_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.l1pr_mlp_infer_workspace_bytes.restype = ctypes.c_size_t
         L.l1pr_mlp_train_step.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_int32,
                                           ctypes.c_float, ctypes.c_int32, vp, vp, vp,
                                           ctypes.c_size_t, vp]

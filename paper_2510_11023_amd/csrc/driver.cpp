@@ -319,7 +319,7 @@ struct Learned {
 
 size_t learned_extra_bytes(const Tables& tb) {
   const MlpLayout L = mlp_layout(tb.M);
-  return (sizeof(double) * (size_t)tb.B * tb.Mp + 255) / 256 * 256 + mlp_ws_bytes(L, tb.B, false);
+  return (sizeof(double) * (size_t)tb.B * tb.Mp + 255) / 256 * 256 + mlp_infer_ws_bytes(L, tb.B);
 }
 
 // One coarse step G_n over all instances; `e` decides what is stored.  With a learned

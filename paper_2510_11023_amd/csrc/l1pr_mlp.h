@@ -26,6 +26,7 @@ struct MlpLayout {
 
 MlpLayout mlp_layout(int modes);
 size_t mlp_ws_bytes(const MlpLayout& L, int n, bool train);
+size_t mlp_infer_ws_bytes(const MlpLayout& L, int n);
 struct Epilogue;
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,

@@ -143,6 +143,54 @@ hipError_t gemm_bf16(bool at, bool bt, const bf16* A, int lda, const bf16* B, in
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ FP64 inference GEMM
+// Y[M][N] = act(X[M][K] W[N][K]^T + b) in FP64: BF16 weights (exact in FP64), FP64
+// activations, FP64 sums in ascending k.  Parareal evaluates the network in this form: its
+// correction G_L(U^{k+1}) - G_L(U^k) must shrink with U^{k+1} - U^k down to the solver's
+// tolerance, and any rounding of the network's input or activations to a shorter format puts
+// a floor under it at that format's resolution.  32x32 tile per work-group (a coarse step
+// carries only one row per instance, so small tiles keep enough work-groups in flight),
+// 2x2 outputs per thread.
+constexpr int IT = 32;
+
+__global__ __launch_bounds__(256) void k_gemm_f64a(const double* X, int ldx, const bf16* Wt, int ldw,
+                                                   const float* bias, int M, int N, int K, int act,
+                                                   double* Y, int ldy) {
+  __shared__ double sX[16][IT + 1];
+  __shared__ double sW[16][IT + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * IT, j0 = blockIdx.x * IT;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int e = tid; e < 16 * IT; e += 256) {
+      const int r = e / 16, kk = e % 16;
+      const int i = i0 + r, j = j0 + r, k = k0 + kk;
+      sX[kk][r] = (i < M && k < K) ? X[(long)i * ldx + k] : 0.0;
+      sW[kk][r] = (j < N && k < K) ? (double)from_bf16(Wt[(long)j * ldw + k]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double x0 = sX[kk][ty * 2], x1 = sX[kk][ty * 2 + 1];
+      const double w0 = sW[kk][tx * 2], w1 = sW[kk][tx * 2 + 1];
+      acc[0][0] = fma(x0, w0, acc[0][0]);
+      acc[0][1] = fma(x0, w1, acc[0][1]);
+      acc[1][0] = fma(x1, w0, acc[1][0]);
+      acc[1][1] = fma(x1, w1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = i0 + ty * 2 + a, j = j0 + tx * 2 + b;
+      if (i >= M || j >= N) continue;
+      const double z = acc[a][b] + (double)bias[j];
+      Y[(long)i * ldy + j] = act ? z / (1.0 + exp(-z)) : z;
+    }
+}
+
 // ---------------------------------------------------------------- layout helpers
 MlpLayout mlp_layout(int modes) {
   MlpLayout L{};
@@ -317,6 +365,22 @@ __global__ void k_colstats(const float* x, int ld, int n, float* mean, float* sd
   }
 }
 
+// sd[c] <- sqrt(mean_c sd[c]^2) for every c (fixed-order reduction)
+__global__ void k_common_scale(float* sd, int n) {
+  __shared__ double red[256];
+  double q = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) q += (double)sd[c] * (double)sd[c];
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const float v = (float)sqrt(red[0] / n);
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += 256) sd[c] = v > 0.f ? v : 1.f;
+}
+
 // Training samples from slice ends Z [B][P+1][Mz] (stride Mz) and coarse values
 // G [B][P][Mz]: x = [G_n ; alpha_b ; n/P], t = Z_{n+1} - G_n.
 __global__ void k_features(const double* Z, const double* G, const double* alpha, int B, int P,
@@ -336,22 +400,30 @@ __global__ void k_features(const double* Z, const double* G, const double* alpha
   if (c < M) t[s * M + c] = (float)(Z[((long)b * (P + 1) + n + 1) * Mz + c] - g[c]);
 }
 
-// Inference input: x = normalise([G_L1 ; alpha_b ; n/P]) in bf16 for B rows
+// Inference input: x = normalise([G_L1 ; alpha_b ; n/P]) in FP64 for B rows
 __global__ void k_infer_input(const double* G, long gstride, const double* inst, int B, int M,
-                              int n, int P, const float* mean, const float* sd, bf16* X0, int ldo) {
+                              int n, int P, const float* mean, const float* sd, double* X0, int ldo) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)B * ldo) return;
   const int b = (int)(e / ldo), c = (int)(e % ldo);
-  float v = 0.f;
-  if (c < M) v = (float)G[b * gstride + c];
-  else if (c == M) v = (float)inst[(long)b * NSCAL + IS_ALPHA];
-  else if (c == M + 1) v = (float)((double)n / (double)P);
-  X0[e] = to_bf16(c < M + 2 ? (v - mean[c]) / sd[c] : 0.f);
+  double v = 0.0;
+  if (c < M) v = G[b * gstride + c];
+  else if (c == M) v = inst[(long)b * NSCAL + IS_ALPHA];
+  else if (c == M + 1) v = (double)n / (double)P;
+  X0[e] = c < M + 2 ? (v - (double)mean[c]) / (double)sd[c] : 0.0;
+}
+
+__global__ void k_norm_f64(const double* x, int ldx, int ncols, int n, const float* mean,
+                           const float* sd, double* X0, int ldo) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * ldo) return;
+  const int i = (int)(e / ldo), c = (int)(e % ldo);
+  X0[e] = (c < ncols) ? (x[(long)i * ldx + c] - (double)mean[c]) / (double)sd[c] : 0.0;
 }
 
 // G_L = G_L1 + (O * out_std + out_mean); falls back to G_L1 for a unit whose correction is
 // not finite or larger than ||G_L1|| + 1.  Then the step epilogue.  One work-group per unit.
-__global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstride, const float* O,
+__global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstride, const double* O,
                                                      int outp, int M, int Mp, const float* om,
                                                      const float* osd, Epilogue ep) {
   const int u = blockIdx.x;
@@ -361,7 +433,7 @@ __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstri
   __syncthreads();
   double sc = 0.0, sg = 0.0;
   for (int k = threadIdx.x; k < M; k += blockDim.x) {
-    const double c = (double)(O[(long)u * outp + k] * osd[k] + om[k]);
+    const double c = O[(long)u * outp + k] * (double)osd[k] + (double)om[k];
     if (!isfinite(c)) atomicOr(&bad, 1);
     sc += c * c;
     const double g = G[u * gstride + k];
@@ -380,7 +452,7 @@ __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstri
   const bool use = (bad == 0) && isfinite(rc[0]) && sqrt(rc[0]) <= sqrt(rg[0]) + 1.0;
   for (int k = threadIdx.x; k < Mp; k += blockDim.x) {
     double x = G[u * gstride + k];
-    if (use && k < M) x = x + (double)(O[(long)u * outp + k] * osd[k] + om[k]);
+    if (use && k < M) x = x + (O[(long)u * outp + k] * (double)osd[k] + (double)om[k]);
     if (ep.kind == EPI_CORRECT) {
       const double go = ep.gold[(long)u * ep.gold_stride + k];
       ep.out[(long)u * ep.out_stride + k] = ep.fold[(long)u * ep.fold_stride + k] + (x - go);
@@ -451,6 +523,46 @@ MlpWs carve(const MlpLayout& L, int n, bool train, void* ws) {
   return W;
 }
 
+// FP64 forward from Xf [n][inp] through two ping-pong buffers to O [n][outp]
+hipError_t mlp_forward_f64(const MlpLayout& L, const char* params, int n, double* Xf, double* Ha,
+                           double* Hb, double* O, hipStream_t s) {
+  const double* in = Xf;
+  int ldin = L.inp, kin = L.inp;
+  double* outs[3] = {Ha, Hb, Ha};
+  for (int l = 0; l < 3; ++l) {
+    dim3 grid((L.hidden + IT - 1) / IT, (n + IT - 1) / IT);
+    k_gemm_f64a<<<grid, 256, 0, s>>>(in, ldin, (const bf16*)(params + L.w[l]), kin,
+                                     (const float*)(params + L.b[l]), n, L.hidden, kin, 1, outs[l],
+                                     L.hidden);
+    in = outs[l];
+    ldin = L.hidden;
+    kin = L.hidden;
+  }
+  dim3 grid((L.outp + IT - 1) / IT, (n + IT - 1) / IT);
+  k_gemm_f64a<<<grid, 256, 0, s>>>(in, ldin, (const bf16*)(params + L.w[3]), L.hidden,
+                                   (const float*)(params + L.b[3]), n, L.outp, L.hidden, 0, O, L.outp);
+  return hipGetLastError();
+}
+
+// Inference buffers (FP64): input, two hidden, output.
+struct InferWs {
+  double *X, *Ha, *Hb, *O;
+};
+static size_t r256(size_t x) { return (x + 255) / 256 * 256; }
+size_t mlp_infer_ws_bytes(const MlpLayout& L, int n) {
+  return r256(8 * (size_t)n * L.inp) + 2 * r256(8 * (size_t)n * L.hidden) +
+         r256(8 * (size_t)n * L.outp);
+}
+static InferWs carve_infer(const MlpLayout& L, int n, void* ws) {
+  char* w = (char*)ws;
+  InferWs W;
+  W.X = (double*)w;
+  W.Ha = (double*)(w + r256(8 * (size_t)n * L.inp));
+  W.Hb = (double*)((char*)W.Ha + r256(8 * (size_t)n * L.hidden));
+  W.O = (double*)((char*)W.Hb + r256(8 * (size_t)n * L.hidden));
+  return W;
+}
+
 // forward from X0 (already in the workspace) to O
 hipError_t mlp_forward_ws(const MlpLayout& L, const char* params, int n, MlpWs& W, hipStream_t s) {
   const bf16* in = W.X0;
@@ -484,11 +596,11 @@ hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double
                             const double* inst, int B, int M, int Mp, int n, int P,
                             const Epilogue& ep, void* ws, hipStream_t s) {
   const char* pp = (const char*)params;
-  MlpWs W = carve(L, B, false, ws);
+  const InferWs W = carve_infer(L, B, ws);
   k_infer_input<<<nblk((long)B * L.inp), 256, 0, s>>>(G, gstride, inst, B, M, n, P,
                                                        (const float*)(pp + L.in_mean),
-                                                       (const float*)(pp + L.in_std), W.X0, L.inp);
-  hipError_t r = mlp_forward_ws(L, pp, B, W, s);
+                                                       (const float*)(pp + L.in_std), W.X, L.inp);
+  hipError_t r = mlp_forward_f64(L, pp, B, W.X, W.Ha, W.Hb, W.O, s);
   if (r != hipSuccess) return r;
   k_infer_apply<<<B, 256, 0, s>>>(G, gstride, W.O, L.outp, M, Mp, (const float*)(pp + L.out_mean),
                                   (const float*)(pp + L.out_std), ep);
@@ -562,6 +674,9 @@ l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_
   hipStream_t s = (hipStream_t)stream;
   k_colstats<<<L.in, 256, 0, s>>>(x, L.in, (int)n, (float*)(p + L.in_mean), (float*)(p + L.in_std));
   k_colstats<<<L.out, 256, 0, s>>>(t, L.out, (int)n, (float*)(p + L.out_mean), (float*)(p + L.out_std));
+  // one output scale for every mode: the root mean square of the per-mode deviations, so the
+  // loss weighs each mode by its absolute contribution to the error of the state
+  k_common_scale<<<1, 256, 0, s>>>((float*)(p + L.out_std), L.out);
   return hipGetLastError() == hipSuccess ? L1PR_OK : L1PR_EHIP;
 }
 
@@ -583,6 +698,27 @@ l1pr_status l1pr_mlp_forward(int32_t modes, const void* params, const float* x, 
   hipError_t r = hipMemcpy2DAsync(y, sizeof(float) * L.out, W.O, sizeof(float) * L.outp,
                                   sizeof(float) * L.out, n, hipMemcpyDeviceToDevice, s);
   return r == hipSuccess ? L1PR_OK : L1PR_EHIP;
+}
+
+l1pr_status l1pr_mlp_infer(int32_t modes, const void* params, const double* x, int32_t n, double* y,
+                           void* ws, size_t ws_bytes, void* stream) {
+  if (modes < 1 || modes > kMlpMaxModes || !params || !x || !y || n < 1 || !ws) return L1PR_EINVAL;
+  const MlpLayout L = mlp_layout(modes);
+  if (ws_bytes < mlp_infer_ws_bytes(L, n)) return L1PR_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  const char* p = (const char*)params;
+  const InferWs W = carve_infer(L, n, ws);
+  k_norm_f64<<<nblk((long)n * L.inp), 256, 0, s>>>(x, L.in, L.in, n, (const float*)(p + L.in_mean),
+                                                   (const float*)(p + L.in_std), W.X, L.inp);
+  if (mlp_forward_f64(L, p, n, W.X, W.Ha, W.Hb, W.O, s) != hipSuccess) return L1PR_EHIP;
+  hipError_t r = hipMemcpy2DAsync(y, sizeof(double) * L.out, W.O, sizeof(double) * L.outp,
+                                  sizeof(double) * L.out, n, hipMemcpyDeviceToDevice, s);
+  return r == hipSuccess ? L1PR_OK : L1PR_EHIP;
+}
+
+size_t l1pr_mlp_infer_workspace_bytes(int32_t modes, int32_t n) {
+  if (modes < 1 || modes > kMlpMaxModes || n < 1) return 0;
+  return mlp_infer_ws_bytes(mlp_layout(modes), n);
 }
 
 l1pr_status l1pr_mlp_train_step(int32_t modes, void* params, void* state, const float* x,

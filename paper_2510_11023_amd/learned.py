@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .solver import _alpha_arg, _ptr, _stream, coarse_apply, solve_serial
+from .solver import _ptr, _stream, coarse_apply, solve_serial
 
 
 def _check(st, what):
@@ -111,6 +111,16 @@ class LearnedCoarse:
         y = torch.empty((n, self.modes), dtype=torch.float32, device=self.device)
         _check(_lib.lib().l1pr_mlp_forward(self.modes, _ptr(self.params), _ptr(x), n, _ptr(y),
                                            _ptr(ws), ws.numel(), _stream()), "forward")
+        return y
+
+    def infer(self, x: torch.Tensor) -> torch.Tensor:
+        """The network as parareal evaluates it (FP64; x [n][M+2] FP64)."""
+        n = x.shape[0]
+        ws = torch.empty(_lib.lib().l1pr_mlp_infer_workspace_bytes(self.modes, n), dtype=torch.uint8,
+                         device=self.device)
+        y = torch.empty((n, self.modes), dtype=torch.float64, device=self.device)
+        _check(_lib.lib().l1pr_mlp_infer(self.modes, _ptr(self.params), _ptr(x), n, _ptr(y),
+                                         _ptr(ws), ws.numel(), _stream()), "infer")
         return y
 
     def train_step(self, x, t, idx, lr, ws, loss=None, grad=None):

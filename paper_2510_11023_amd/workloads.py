@@ -25,9 +25,14 @@ C2_BATCH = 32
 # config 3: 2D, 64x64 modes, 96x96 quadrature, alpha = 0.6, D = 1 + exp(-u^2)/2, f = sin u
 C3 = dict(dim=2, modes=64, quad=96, steps=2048, slices=128, alpha=0.6, T=1.0, d_sel=3,
           d_param=1.0, f_sel=3, history=0, source_time=0)
-# config 4: learned coarse propagator, 1D, M = 128 (Q = 192), N = 2048, P = 64, alpha ~ U(0.2, 1)
+# config 4: learned coarse propagator, 1D, M = 128 (Q = 192), N = 2048, P = 64, alpha ~ U(0.2, 1);
+# D, f and the u0 law as in config 2; 4096 training instances, 64 held-out instances
 C4 = dict(dim=1, modes=128, quad=192, steps=2048, slices=64, alpha=0.5, T=1.0, d_sel=2,
           d_param=1.0, f_sel=2, history=0, source_time=0)
+C4_TRAIN_SEEDS = range(0, 4096)
+C4_EVAL_SEEDS = range(100000, 100064)
+C4_TRAIN_ALPHA_SEED = 4242
+C4_EVAL_ALPHA_SEED = 2424
 
 
 def with_(base: dict, **kw) -> dict:

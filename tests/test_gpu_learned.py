@@ -90,7 +90,8 @@ def test_mlp_stats(gpu, net):
     assert np.allclose(im, xn.mean(0), rtol=1e-6, atol=1e-7)
     assert np.allclose(isd, xn.std(0), rtol=1e-6)
     assert np.allclose(omu, tn.mean(0), rtol=1e-5, atol=1e-8)
-    assert np.allclose(osd, tn.std(0), rtol=1e-6)
+    # one output scale shared by every mode: the RMS of the per-mode standard deviations
+    assert np.allclose(osd, np.sqrt(np.mean(tn.std(0) ** 2)), rtol=1e-6)
 
 
 def test_mlp_forward_matches_oracle(gpu, net):
@@ -101,6 +102,28 @@ def test_mlp_forward_matches_oracle(gpu, net):
     y = model.forward(x[:200]).cpu().numpy()
     ref = om.forward(ws, bs, norms, x[:200].cpu().numpy(), model.info.in_padded)[:, : model.modes]
     assert rel(y, ref) <= 1e-2, rel(y, ref)
+
+
+def test_mlp_inference_form_matches_oracle(gpu, net):
+    """FP64 evaluation (the form parareal uses) against the float64 reference: only the order
+    of FP64 sums separates them."""
+    from oracle import mlp as om
+
+    model, x, t = net
+    ws, bs, norms = _oracle_params(model)
+    xd = x[:200].double()
+    y = model.infer(xd).cpu().numpy()
+    ref = om.forward(ws, bs, norms, xd.cpu().numpy(), model.info.in_padded, exact=True)
+    assert rel(y, ref[:, : model.modes]) <= 1e-12, rel(y, ref[:, : model.modes])
+    # smooth in its input down to FP64 rounding: a 1e-9 relative input change moves the output
+    # as the reference's does
+    dx = torch.zeros_like(xd)
+    dx[:, 0] = 1e-9 * xd[:, 0].abs().max()
+    y2 = model.infer(xd + dx).cpu().numpy()
+    ref2 = om.forward(ws, bs, norms, (xd + dx).cpu().numpy(), model.info.in_padded, exact=True)
+    d, dref = y2 - y, (ref2 - ref)[:, : model.modes]
+    assert np.linalg.norm(dref) > 0
+    assert rel(d, dref) <= 1e-3, rel(d, dref)
 
 
 def test_mlp_gradient_and_adam_match_oracle(gpu, net):
@@ -204,7 +227,7 @@ def test_learned_coarse_prediction_matches_oracle_composition(gpu, orc):
         r = om.correction(ws, bs, norms, g[None, :], [kw["alpha"]], n, P, model.info.in_padded,
                           kw["modes"])[0]
         C[n + 1] = g + r.astype(np.float64)
-    assert rel(U0, C) <= 2e-3, rel(U0, C)
+    assert rel(U0, C) <= 1e-10, rel(U0, C)
     Gp = gpu.solve_parareal(pg, dev(u0), 0, want_iterates=True).iterates[0][0].cpu().numpy()
     assert rel(U0, Gp) > 10 * rel(U0, C)   # the correction is really applied
 
