@@ -1,36 +1,45 @@
 #!/usr/bin/env python
 """Benchmark of the parareal / L1 / sine-Galerkin solver on one MI355X.
 
-Workload (1D, config 2 of the method's benchmark set): D = 1 + 1/(1+u^2), f = 0.1 u (1-u),
-M = 256 sine modes, Q = 384 Gauss points, N = 4096 fine L1 steps, P = 64 parareal slices,
-three batched runs (alpha = 0.3, 0.7, 1.0) of 32 instances each with u0 coefficients
-c_k ~ N(0, k^-3) (seeds 0..31).  Synthetic, seeded inputs.
+Main workload (1D): D = 1 + 1/(1+u^2), f = 0.1 u (1-u), M = 256 sine modes, Q = 384 Gauss
+points, N = 4096 fine L1 steps, P = 64 parareal slices, three batched runs (alpha = 0.3,
+0.7, 1.0) of 32 instances each, u0 coefficients c_k ~ N(0, k^-3) (seeds 0..31).  Synthetic,
+seeded inputs.
 
 One step = the three batched parareal solves (plain coarse L1 propagator G) run to the
 iteration count k*(alpha) at which every instance's slice ends are within 1e-8 (relative
 L2 over all P+1 slice ends) of the serial solution.  k* is found before the timed region
 from the GPU serial solution (itself parity-checked against the CPU oracle by the tests)
-and the parareal iterates.  Metric: useful mode-steps/s = sum_b M N / time-to-1e-8.
+and the parareal iterates.  Metric value: useful mode-steps/s = sum_b M N / time-to-1e-8.
 
 The JSON line also carries:
-  roofline      the dominant kernel: the fine-sweep step kernel (2048 units per launch;
-                evaluation, cosine-moment stiffness, register-resident Cholesky, solves).
-                Algorithmic flops per unit = M^3/3 + M^2/2 + M/6 (Cholesky) + 2 M^2
-                (two triangular solves) + 4 M Q (u_q and the load vector) + 2 (2M+1) Q
-                (cosine moments); divided by the average launch time measured with HIP
-                events on the launch stream over the timed region; peak = 78.6 TFLOP/s
-                (MI355X dense FP64 matrix).
-  gemm_assembly the same step with the stiffness formed as the quadrature GEMM
-                dphi^T diag(w D) dphi on FP64 MFMA (assembly = 1), timed for one step; its
-                assembly kernel's roofline counts Q M (M+1) flops per unit (the M(M+1)/2
-                distinct entries of the symmetric stiffness, 2Q flops each).
-  cpu_baseline  the CPU oracle (plain serial C) timed on this host's cores on a bounded
-                sample: the first slice (64 fine steps) of 16 instances of the alpha = 0.3
-                batch, one instance per thread.
+  roofline        the dominant kernel, the register-resident factor-and-solve kernel of the
+                  fine sweep (2048 units per launch).  Algorithmic flops per unit =
+                  M^3/3 + M^2/2 + M/6 (Cholesky) + 2 M^2 (two triangular solves), divided by
+                  the average launch time measured with HIP events on the launch stream over
+                  the timed region; peak = 78.6 TFLOP/s (MI355X dense FP64).  traffic = HBM
+                  bytes per launch from the FETCH_SIZE and WRITE_SIZE counters, scaled by
+                  what the counters read for a plain device copy, recorded for the kernel
+                  source with the hash below (null once the source differs).
+  history_hbm     the L1 history-sum kernel of the fine sweep: algorithmic bytes per sweep
+                  (every unit's trajectory rows 0..r-1, each instance's slice ends once, the
+                  output rows) over its summed launch time, against 8 TB/s.
+  gemm_assembly   the same step with the stiffness formed as the quadrature GEMM
+                  dphi^T diag(w D) dphi on FP64 MFMA (assembly = 1); its assembly kernel's
+                  roofline counts Q M (M+1) flops per unit (the M(M+1)/2 distinct entries of
+                  the symmetric stiffness, 2Q flops each).
+  learned_vs_plain  the learned-coarse workload: 1D, M = 128, Q = 192, N = 2048, P = 64,
+                  alpha ~ U(0.2, 1), D and f as above; the residual network is trained on
+                  4096 seeded serial trajectories (one-off, untimed but reported), then plain
+                  and learned parareal are each run to 1e-8 of the serial solution on 64
+                  held-out instances and timed.
+  cpu_baseline    the CPU oracle (plain serial C) timed on this host's cores on a bounded
+                  sample: the first slice (64 fine steps) of 16 instances of the alpha = 0.3
+                  batch, one instance per thread.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -40,12 +49,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8-rel solution: learned-G vs plain-G parareal; mode-steps/s"
-PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 TARGET = 1e-8
+
+# HBM traffic of the fine-sweep factor-and-solve kernel, 2048 units per launch, from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on `python bench.py --mode kernels`, divided by
+# the counters' reading for a plain copy of known size (fetch and write factors below).
+# Valid only for the kernel sources with this hash.
+TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
+TRAFFIC_RECORD = {"sha256": "6a1c276b0eee114a02ebf4f02f97d07cb5195deef956fb1ca1af70ebcd5c3158",
+                  "fetch_kib": 8678, "write_kib": 10452, "fetch_factor": 2.0, "write_factor": 1.0,
+                  "bytes_per_launch": (2 * 8678 + 10452) * 1024}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sources_hash():
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def rel_err_max(its_k, Us):
@@ -74,18 +101,83 @@ def cpu_baseline(kw, u0_np, n_inst):
                       f"alpha={kw['alpha']} instances, one instance per thread, {dt:.1f} s wall"}
 
 
+def find_kstar(l1, p, u0, Us, ws, max_iter, **kw):
+    res = l1.solve_parareal(p, u0, max_iter, tol=0.0, want_iterates=True, workspace=ws, **kw)
+    e = [rel_err_max(res.iterates[k], Us) for k in range(res.iters + 1)]
+    ks = next((k for k, v in enumerate(e) if v <= TARGET), None)
+    return ks, e
+
+
+def learned_vs_plain(l1, torch, W, dev):
+    from paper_2510_11023_amd.learned import LearnedCoarse, training_data
+
+    kw = dict(W.C4)
+    M, N, P = kw["modes"], kw["steps"], kw["slices"]
+    p = l1.make_problem(**kw)
+    ntrain, epochs = len(W.C4_TRAIN_SEEDS), 10
+    t0 = time.perf_counter()
+    model = LearnedCoarse(M, seed=0)
+    ta = W.alphas_uniform(ntrain, W.C4_TRAIN_ALPHA_SEED)
+    u0t = torch.tensor(W.u0_batch_1d(M, W.C4_TRAIN_SEEDS), device=dev)
+    x, t = training_data(p, u0t, ta, model)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    model.set_stats(x, t)
+    t0 = time.perf_counter()
+    losses = model.train(x, t, epochs=epochs, batch=1024, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del x, t, u0t
+    log(f"learned G: data {t_data:.1f} s, training {t_train:.1f} s, loss {losses[0]:.3g} -> {losses[-1]:.3g}")
+
+    ea = [float(a) for a in W.alphas_uniform(len(W.C4_EVAL_SEEDS), W.C4_EVAL_ALPHA_SEED)]
+    u0 = torch.tensor(W.u0_batch_1d(M, W.C4_EVAL_SEEDS), device=dev)
+    B = u0.shape[0]
+    Us, _ = l1.solve_serial(p, u0, alpha=ea)
+    ws = l1.parareal_workspace(p, B, dev, learned=True)
+    out = {"workload": f"1D, M={M}, Q={kw['quad']}, N={N}, P={P}, D=1+1/(1+u^2), f=0.1u(1-u), "
+                       f"{B} held-out instances with alpha~U(0.2,1); network 3x512 SiLU, "
+                       f"trained on {ntrain} seeded serial trajectories ({ntrain * P} samples)",
+           "train": {"data_s": round(t_data, 2), "train_s": round(t_train, 2), "epochs": epochs,
+                     "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}}
+    for name, extra in (("plain", {}), ("learned", {"coarse": l1.COARSE_LEARNED, "mlp_params": model.params})):
+        ks, e = find_kstar(l1, p, u0, Us, ws, 30, alpha=ea, **extra)
+        log(f"{name} G: k*={ks} errors " + " ".join(f"{v:.1e}" for v in e[: (ks or 30) + 1]))
+        rec = {"kstar": ks, "rel_err_by_sweep": [float(f"{v:.3e}") for v in e[: (ks or 30) + 1]]}
+        if ks is not None:
+            run = lambda: l1.solve_parareal(p, u0, ks, alpha=ea, tol=0.0, want_incr=False,
+                                            workspace=ws, **extra)
+            run()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                U = run().U
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            tm = sorted(times)[1]
+            rec.update({"ms": round(tm * 1e3, 2), "mode_steps_per_s": B * M * N / tm,
+                        "achieved_rel_err": rel_err_max(U, Us)})
+        out[name] = rec
+    if out["plain"].get("ms") and out["learned"].get("ms"):
+        out["speedup_learned_over_plain"] = round(out["plain"]["ms"] / out["learned"]["ms"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernels"], default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
                          "device copy (for hardware-counter runs); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this solver runs on one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: this solver runs on one GPU; a run on several GPUs is not supported "
+              "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -98,6 +190,8 @@ def main():
     torch.cuda.set_device(dev)
     base = dict(W.C2)
     M, N, P, Q = base["modes"], base["steps"], base["slices"], base["quad"]
+    S = N // P
+    Mp = M  # 256 is a multiple of 16
     B, alphas = W.C2_BATCH, W.C2_ALPHAS
     u0_np = W.u0_batch_1d(M, range(B))
     u0 = torch.tensor(u0_np, dtype=torch.float64, device=dev)
@@ -132,16 +226,10 @@ def main():
         log(f"serial alpha={a}: {t_serial[a] * 1e3:.1f} ms")
 
     # k*(alpha): first sweep count whose iterate is within 1e-8 of the serial solution
-    kstar, errs = {}, {}
+    kstar = {}
     for a in alphas:
-        res = l1.solve_parareal(probs[a], u0, P, tol=1e-11, want_iterates=True, workspace=ws_par)
-        torch.cuda.synchronize()
-        e = [rel_err_max(res.iterates[k], Us[a]) for k in range(res.iters + 1)]
-        ks = next((k for k, v in enumerate(e) if v <= TARGET), None)
-        if ks is None:
-            ks = P  # exact after P sweeps
-        kstar[a] = max(ks, 1)
-        errs[a] = e
+        ks, e = find_kstar(l1, probs[a], u0, Us[a], ws_par, 24)
+        kstar[a] = max(ks if ks is not None else P, 1)   # exact after P sweeps
         log(f"parareal alpha={a}: k*={kstar[a]} errors " + " ".join(f"{v:.1e}" for v in e[: kstar[a] + 1]))
 
     def step(pr=probs):
@@ -172,23 +260,41 @@ def main():
     value = useful / (ms_per_step / 1e3)
     executed = sum(kstar[a] for a in alphas) * B * M * N
     serial_total = sum(t_serial.values())
-
-    # dominant kernel: the fine-sweep step kernel
     units = B * P
-    key = f"step/fine/{units}"
-    n_l, tot_l = stats.get(key, (0, 0.0))
+    total_ms = sum(x[1] for x in stats.values())
+    share = {k: round(v[1] / total_ms, 4) for k, v in stats.items()}
+
+    # dominant kernel: the fine-sweep factor-and-solve kernel
     roofline = None
-    if n_l:
-        avg_s = tot_l / n_l / 1e3
-        per_unit = M ** 3 / 3 + M ** 2 / 2 + M / 6 + 2 * M ** 2 + 4 * M * Q + 2 * (2 * M + 1) * Q
+    n_c, tot_c = stats.get(f"chol/fine/{units}", (0, 0.0))
+    if n_c:
+        avg_s = tot_c / n_c / 1e3
+        per_unit = M ** 3 / 3 + M ** 2 / 2 + M / 6 + 2 * M ** 2
         flops = units * per_unit
         achieved = flops / avg_s / 1e12
-        roofline = {"bound": "mfma", "kernel": "k_step1d_reg<moments> (fine sweep, 2048 units)",
-                    "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
-                    "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": int(flops),
-                    "traffic": None}
-    share = {k: round(v[1] / sum(x[1] for x in stats.values()), 4) for k, v in stats.items()}
+        traffic = None
+        if TRAFFIC_RECORD and TRAFFIC_RECORD.get("sha256") == sources_hash():
+            traffic = TRAFFIC_RECORD["bytes_per_launch"]
+        roofline = {"bound": "mfma", "kernel": f"k_chol_reg<moments> (fine sweep, {units} units)",
+                    "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                    "traffic": traffic, "avg_launch_ms": round(avg_s * 1e3, 4),
+                    "flops_per_launch": int(flops), "launches": n_c}
+
+    # history sum: algorithmic bytes of one fine sweep (S launches, local step r = 1..S)
+    history = None
+    n_h, tot_h = stats.get(f"history/fine/{units}", (0, 0.0))
+    if n_h:
+        row = Mp * 8
+        traj_rows = units * sum(range(1, S + 1))          # rows 0..r-1 of every unit
+        ends_rows = S * B * (P + 1)                        # each instance's slice ends, once
+        out_rows = S * units
+        sweep_bytes = (traj_rows + ends_rows + out_rows) * row
+        sweeps = n_h / S
+        gbs = sweep_bytes * sweeps / (tot_h / 1e3) / 1e9
+        history = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_sweep": sweep_bytes,
+                   "avg_launch_us": round(tot_h / n_h * 1e3, 2)}
 
     # the same step with the quadrature-GEMM stiffness (assembly = 1)
     step(probs_gemm)
@@ -200,19 +306,21 @@ def main():
     t_gemm = time.perf_counter() - t0
     stats_g = _lib.profile_stop()
     n_a, tot_a = stats_g.get(f"assemble/fine/{units}", (0, 0.0))
-    gemm = {"ms_per_step": t_gemm * 1e3,
+    gemm = {"ms_per_step": round(t_gemm * 1e3, 1),
             "achieved_rel_err": {str(a): rel_err_max(out_g[a], Us[a]) for a in alphas}}
     if n_a:
         avg_a = tot_a / n_a / 1e3
         fl = units * Q * M * (M + 1)
         gemm["assemble_roofline"] = {
-            "bound": "mfma", "kernel": "k_assemble1d<64> (fine sweep, 2048 units)",
-            "achieved": round(fl / avg_a / 1e12, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(fl / avg_a / 1e12 / PEAK_FP64_MFMA_TFLOPS, 4),
+            "bound": "mfma", "kernel": f"k_assemble1d<64> (fine sweep, {units} units)",
+            "achieved": round(fl / avg_a / 1e12, 3), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(fl / avg_a / 1e12 / PEAK_FP64_TFLOPS, 4),
             "avg_launch_ms": round(avg_a * 1e3, 4), "flops_per_launch": fl}
-    for k in sorted(stats_g):
-        n, tot = stats_g[k]
-        log(f"  gemm {k:27s} launches {n:7d}  avg {tot / n * 1e3:9.1f} us  total {tot:9.1f} ms")
+    log(f"assembly=1 step: {t_gemm * 1e3:.1f} ms")
+
+    learned = None
+    if not args.no_learned:
+        learned = learned_vs_plain(l1, torch, W, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -234,10 +342,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "config2: 1D, M=256, Q=384, N=4096, P=64, D=1+1/(1+u^2), f=0.1u(1-u), "
+            "workload": "1D, M=256, Q=384, N=4096, P=64, D=1+1/(1+u^2), f=0.1u(1-u), "
                         "alpha in {0.3,0.7,1.0} x 32 instances (seeds 0..31); plain-G parareal "
                         "run to 1e-8 relative of the serial solution",
-            "coarse": "plain L1 (learned G not in this line)",
+            "coarse": "plain L1 (learned G: see learned_vs_plain)",
             "kstar": {str(a): kstar[a] for a in alphas},
             "achieved_rel_err": {str(a): achieved_err[a] for a in alphas},
         },
@@ -247,7 +355,9 @@ def main():
         "executed_mode_steps_per_s": executed / (ms_per_step / 1e3),
         "kernel_time_share": share,
         "roofline": roofline,
+        "history_hbm": history,
         "gemm_assembly": gemm,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -172,10 +172,12 @@ size_t l1pr_parareal_learned_extra_bytes(const l1pr_problem* p, int32_t batch);
  * Network: inputs x = [G_n coefficients (M) ; alpha ; n/P] (M + 2), normalised per column
  * with the stored mean and standard deviation; three hidden layers of 512 units with SiLU
  * activation z / (1 + exp(-z)); M outputs, the normalised residual F_n - G_n, mapped back with
- * the stored output mean and standard deviation.  Weights and activations are BF16, products
- * accumulate in FP32 (MFMA), biases and normalisation are FP32.
+ * the stored output mean and standard deviation.  Training keeps weights and activations in
+ * BF16 with FP32 accumulation (MFMA); inside parareal (and in l1pr_mlp_infer) the same BF16
+ * weights are applied in FP64.  Biases and normalisation are FP32.
  *   params : device blob read by inference (normalisation, biases, BF16 weights [out][in] with
- *            the inner dimension padded); offsets and sizes from l1pr_mlp_layout.
+ *            the inner dimension padded); offsets and sizes from l1pr_mlp_layout.  Must be
+ *            256-byte aligned (EINVAL otherwise): the inference kernel uses 16-byte loads.
  *   state  : device FP32 [3][flat_count]: master parameters, Adam first and second moments;
  *            the flat order is W1 b1 W2 b2 W3 b3 W4 b4 (each W row-major [out][in_padded]).
  * Training data and initial weights are supplied by the caller. */

@@ -216,9 +216,15 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 //   device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
   if (c.reg) {
-    L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, c.s); }));
+    // GEMM variants: the lagged-state product always takes the skinny tiles (faster at every
+    // unit count measured); the projections take them for coarse steps only (one unit per
+    // instance) and the 64 x 64 tiles otherwise.  The choice never depends on the unit count
+    // of a fine or full-history step, so a serial solve and a parareal fine sweep do the same
+    // arithmetic.
+    const bool sk_proj = a.mode == MODE_COARSE;
+    L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, true, c.s); }));
     L1PR_TRY(timed("proj", a, units, c.s, [&] {
-      return launch_proj_gemm(c.tb, units, a.d, a.g, c.moments ? a.mom : nullptr, a.F, c.s);
+      return launch_proj_gemm(c.tb, units, a.d, a.g, c.moments ? a.mom : nullptr, a.F, sk_proj, c.s);
     }));
     if (!c.moments)
       L1PR_TRY(timed("assemble", a, units, c.s, [&] { return launch_assemble(c.tb, a, units, c.s); }));
@@ -492,7 +498,9 @@ l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const d
     if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
     if (coarse != L1PR_COARSE_L1 && coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
     const bool learned = coarse == L1PR_COARSE_LEARNED;
-    if (learned && (!mlp_params || p->dim != 1 || p->modes > kMlpMaxModes)) return L1PR_EINVAL;
+    if (learned && (!mlp_params || ((uintptr_t)mlp_params & 255) || p->dim != 1 ||
+                    p->modes > kMlpMaxModes))
+      return L1PR_EINVAL;
     Ctx c;
     l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;

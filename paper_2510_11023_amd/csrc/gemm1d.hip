@@ -192,19 +192,105 @@ __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double
   }
 }
 
+// ------------------------------------------------------------------ skinny variants
+// For launches with few units (the coarse steps: one unit per instance) the 64 x 64 tiles
+// leave most of the chip idle and expose every load's latency.  These variants give each
+// work-group one 16 x 16 output tile and cut the reduction into 32-wide chunks: lane group q
+// of wave w owns chunk 4 (w + 4 i) + q, loads all of it before its first MFMA, and the four
+// waves' partial tiles are added in LDS in wave order.  Each output is still a fixed-order
+// sum over its own row, independent of the other units of the launch.
+constexpr int ST = 16;
+
+template <class RowFn>
+__device__ inline double skinny_tile(RowFn rowp, int units, int u0, int n0, int K, const double* B,
+                                     int ldb, int ncols, double (*red)[ST][ST + 1]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const double* ap = (u0 + r < units) ? rowp(u0 + r) : nullptr;
+  const int col = n0 + r;
+  const bool bc = col < ncols;
+  const int nchunk = (K + 31) / 32;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int blk = w; 4 * blk < nchunk; blk += 4) {
+    const int k0 = (4 * blk + q) * 32;
+    double xa[32], xb[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int k = k0 + t;
+      xa[t] = (ap != nullptr && k < K) ? ap[k] : 0.0;
+      xb[t] = (bc && k < K) ? B[(long)k * ldb + col] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[t], xb[t], acc, 0, 0, 0);
+  }
+  // accumulator element v of lane (r, q) is tile entry [q + 4v][r]
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[w][q + 4 * v][r] = acc[v];
+  __syncthreads();
+  const int ro = threadIdx.x >> 4, co = threadIdx.x & 15;
+  return red[0][ro][co] + red[1][ro][co] + red[2][ro][co] + red[3][ro][co];
+}
+
+// grid: (ceil(Qp / 16), ceil(units / 16))
+__global__ __launch_bounds__(256) void k_lag_skinny1d(Tables tb, StepArgs a, int units, double* dq,
+                                                      double* gq) {
+  __shared__ double red[4][ST][ST + 1];
+  const int n0 = blockIdx.x * ST, u0 = blockIdx.y * ST;
+  const double uq = skinny_tile([&](int u) { return lag_row(tb, a, u); }, units, u0, n0, tb.Mp,
+                                tb.phiT, tb.Qp, tb.Qp, red);
+  const int u = u0 + (threadIdx.x >> 4), q = n0 + (threadIdx.x & 15);
+  if (u >= units || q >= tb.Qp) return;
+  const UnitView v = decode_unit(tb, a, u);
+  const double* ins = tb.inst + (long)v.b * NSCAL;
+  const double tD = t_level(tb, v.m_prev);
+  const double tf = tb.source_time ? t_level(tb, v.m_src) : tD;
+  const double w = tb.wq[q];
+  dq[(long)u * tb.Qp + q] = w * coef_D(tb.d_sel, tb.d_param, uq);
+  gq[(long)u * tb.Qp + q] = w * coef_f(tb, ins, tb.xq[q], 0.0, tf, uq);
+}
+
+// grid: (ceil(max(Jm, Mp) / 16), ceil(units / 16), 2); z as in k_proj_gemm1d
+__global__ __launch_bounds__(256) void k_proj_skinny1d(Tables tb, int units, const double* dq,
+                                                       const double* gq, double* m, int Jm,
+                                                       double* F) {
+  __shared__ double red[4][ST][ST + 1];
+  const int which = blockIdx.z;
+  const int n0 = blockIdx.x * ST, u0 = blockIdx.y * ST;
+  const int ncols = which == 0 ? Jm : tb.Mp;
+  if (which == 0 && m == nullptr) return;   // uniform per work-group
+  if (n0 >= ncols) return;
+  const double* Ain = which == 0 ? dq : gq;
+  const double* B = which == 0 ? tb.cosq : tb.phi;
+  double* out = which == 0 ? m : F;
+  const double x = skinny_tile([&](int u) { return Ain + (long)u * tb.Qp; }, units, u0, n0, tb.Qp,
+                               B, ncols, ncols, red);
+  const int u = u0 + (threadIdx.x >> 4), c = n0 + (threadIdx.x & 15);
+  if (u < units && c < ncols) out[(long)u * ncols + c] = x;
+}
+
 hipError_t launch_lag_gemm(const Tables& tb, const StepArgs& a, int units, double* dq, double* gq,
-                           hipStream_t s) {
-  dim3 grid((tb.Qp + GT - 1) / GT, (units + GT - 1) / GT);
-  k_lag_gemm1d<<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
+                           bool skinny, hipStream_t s) {
+  if (skinny) {
+    dim3 grid((tb.Qp + ST - 1) / ST, (units + ST - 1) / ST);
+    k_lag_skinny1d<<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
+  } else {
+    dim3 grid((tb.Qp + GT - 1) / GT, (units + GT - 1) / GT);
+    k_lag_gemm1d<<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const double* gq,
-                            double* m, double* F, hipStream_t s) {
+                            double* m, double* F, bool skinny, hipStream_t s) {
   const int Jm = 2 * tb.Mp + 1;
   const int nc = Jm > tb.Mp ? Jm : tb.Mp;
-  dim3 grid((nc + GT - 1) / GT, (units + GT - 1) / GT, 2);
-  k_proj_gemm1d<<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
+  if (skinny) {
+    dim3 grid((nc + ST - 1) / ST, (units + ST - 1) / ST, 2);
+    k_proj_skinny1d<<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
+  } else {
+    dim3 grid((nc + GT - 1) / GT, (units + GT - 1) / GT, 2);
+    k_proj_gemm1d<<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
+  }
   return hipGetLastError();
 }
 

@@ -201,10 +201,14 @@ hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipSt
 hipError_t launch_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
                         hipStream_t s);
 bool reg_path_ok(int Mp, int Qp);
+// skinny: 16 x 16 tiles with a split reduction (few units) instead of 64 x 64 tiles.  Both
+// give every output as a fixed-order sum over its own row, but the two orders differ, so
+// every step whose result must match another run bit for bit (the fine steps of a serial
+// solve and of a parareal sweep) has to use the same variant.
 hipError_t launch_lag_gemm(const Tables& tb, const StepArgs& a, int units, double* dq, double* gq,
-                           hipStream_t s);
+                           bool skinny, hipStream_t s);
 hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const double* gq,
-                            double* m, double* F, hipStream_t s);
+                            double* m, double* F, bool skinny, hipStream_t s);
 hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
                           hipStream_t s);
 hipError_t launch_chol_reg(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,

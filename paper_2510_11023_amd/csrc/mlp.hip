@@ -145,50 +145,81 @@ hipError_t gemm_bf16(bool at, bool bt, const bf16* A, int lda, const bf16* B, in
 
 // ------------------------------------------------------------ FP64 inference GEMM
 // Y[M][N] = act(X[M][K] W[N][K]^T + b) in FP64: BF16 weights (exact in FP64), FP64
-// activations, FP64 sums in ascending k.  Parareal evaluates the network in this form: its
-// correction G_L(U^{k+1}) - G_L(U^k) must shrink with U^{k+1} - U^k down to the solver's
-// tolerance, and any rounding of the network's input or activations to a shorter format puts
-// a floor under it at that format's resolution.  32x32 tile per work-group (a coarse step
-// carries only one row per instance, so small tiles keep enough work-groups in flight),
-// 2x2 outputs per thread.
-constexpr int IT = 32;
+// activations, FP64 sums.  Parareal evaluates the network in this form: its correction
+// G_L(U^{k+1}) - G_L(U^k) must shrink with U^{k+1} - U^k down to the solver's tolerance, and
+// any rounding of the input or the activations to a shorter format puts a floor under it at
+// that format's resolution.
+//
+// A coarse step carries one row per instance, so the product is skinny (M of tens, K and N
+// of hundreds) and latency-bound.  One 16x16 output tile per work-group (FP64 MFMA 16x16x4);
+// K is cut into 32-wide chunks, each lane group q of each wave owns one chunk of a 128-wide
+// block and loads it with wide loads before the first MFMA, so every load is in flight at
+// once; the four waves take interleaved blocks and their partial tiles are added in LDS in
+// wave order (a fixed order: the network stays a deterministic function of its input).
+// K must be a multiple of 32 (the layout pads every inner dimension to that).
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gemm_f64a(const double* X, int ldx, const bf16* Wt, int ldw,
-                                                   const float* bias, int M, int N, int K, int act,
-                                                   double* Y, int ldy) {
-  __shared__ double sX[16][IT + 1];
-  __shared__ double sW[16][IT + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.y * IT, j0 = blockIdx.x * IT;
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int e = tid; e < 16 * IT; e += 256) {
-      const int r = e / 16, kk = e % 16;
-      const int i = i0 + r, j = j0 + r, k = k0 + kk;
-      sX[kk][r] = (i < M && k < K) ? X[(long)i * ldx + k] : 0.0;
-      sW[kk][r] = (j < N && k < K) ? (double)from_bf16(Wt[(long)j * ldw + k]) : 0.0;
-    }
-    __syncthreads();
+__global__ __launch_bounds__(256) void k_gemm_f64_skinny(const double* X, int ldx, const bf16* Wt,
+                                                         int ldw, const float* bias, int M, int N,
+                                                         int K, int act, double* Y, int ldy) {
+  __shared__ double red[4][16][17];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const bool xrow = i0 + r < M, wrow = j0 + r < N;
+  const double* xp = X + (long)(xrow ? i0 + r : 0) * ldx;
+  const bf16* wp = Wt + (long)(wrow ? j0 + r : 0) * ldw;
+  const int nchunk = K / 32;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int blk = w; 4 * blk < nchunk; blk += 4) {
+    const int c = 4 * blk + q;
+    double xa[32];
+    unsigned int wr[16];
+    if (c < nchunk && xrow) {
+      const double2* px = (const double2*)(xp + c * 32);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const double x0 = sX[kk][ty * 2], x1 = sX[kk][ty * 2 + 1];
-      const double w0 = sW[kk][tx * 2], w1 = sW[kk][tx * 2 + 1];
-      acc[0][0] = fma(x0, w0, acc[0][0]);
-      acc[0][1] = fma(x0, w1, acc[0][1]);
-      acc[1][0] = fma(x1, w0, acc[1][0]);
-      acc[1][1] = fma(x1, w1, acc[1][1]);
+      for (int t = 0; t < 16; ++t) {
+        const double2 v = px[t];
+        xa[2 * t] = v.x;
+        xa[2 * t + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 32; ++t) xa[t] = 0.0;
     }
-    __syncthreads();
+    if (c < nchunk && wrow) {
+      const uint4* pw = (const uint4*)(wp + c * 32);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint4 v = pw[t];
+        wr[4 * t] = v.x;
+        wr[4 * t + 1] = v.y;
+        wr[4 * t + 2] = v.z;
+        wr[4 * t + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) wr[t] = 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      // element 2t is the low half of word t (little-endian BF16 pairs)
+      const double w0 = (double)__uint_as_float(wr[t] << 16);
+      const double w1 = (double)__uint_as_float(wr[t] & 0xffff0000u);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[2 * t], w0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[2 * t + 1], w1, acc, 0, 0, 0);
+    }
   }
+  // accumulator element v of lane (r, q) is D[q + 4v][r]
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int i = i0 + ty * 2 + a, j = j0 + tx * 2 + b;
-      if (i >= M || j >= N) continue;
-      const double z = acc[a][b] + (double)bias[j];
-      Y[(long)i * ldy + j] = act ? z / (1.0 + exp(-z)) : z;
-    }
+  for (int v = 0; v < 4; ++v) red[w][q + 4 * v][r] = acc[v];
+  __syncthreads();
+  const int ro = threadIdx.x >> 4, co = threadIdx.x & 15;
+  const int i = i0 + ro, j = j0 + co;
+  if (i < M && j < N) {
+    const double z = red[0][ro][co] + red[1][ro][co] + red[2][ro][co] + red[3][ro][co] + (double)bias[j];
+    Y[(long)i * ldy + j] = act ? z / (1.0 + exp(-z)) : z;
+  }
 }
 
 // ---------------------------------------------------------------- layout helpers
@@ -527,20 +558,20 @@ MlpWs carve(const MlpLayout& L, int n, bool train, void* ws) {
 hipError_t mlp_forward_f64(const MlpLayout& L, const char* params, int n, double* Xf, double* Ha,
                            double* Hb, double* O, hipStream_t s) {
   const double* in = Xf;
-  int ldin = L.inp, kin = L.inp;
+  int kin = L.inp;
   double* outs[3] = {Ha, Hb, Ha};
   for (int l = 0; l < 3; ++l) {
-    dim3 grid((L.hidden + IT - 1) / IT, (n + IT - 1) / IT);
-    k_gemm_f64a<<<grid, 256, 0, s>>>(in, ldin, (const bf16*)(params + L.w[l]), kin,
-                                     (const float*)(params + L.b[l]), n, L.hidden, kin, 1, outs[l],
-                                     L.hidden);
+    dim3 grid(L.hidden / 16, (n + 15) / 16);
+    k_gemm_f64_skinny<<<grid, 256, 0, s>>>(in, kin, (const bf16*)(params + L.w[l]), kin,
+                                           (const float*)(params + L.b[l]), n, L.hidden, kin, 1,
+                                           outs[l], L.hidden);
     in = outs[l];
-    ldin = L.hidden;
     kin = L.hidden;
   }
-  dim3 grid((L.outp + IT - 1) / IT, (n + IT - 1) / IT);
-  k_gemm_f64a<<<grid, 256, 0, s>>>(in, ldin, (const bf16*)(params + L.w[3]), L.hidden,
-                                   (const float*)(params + L.b[3]), n, L.outp, L.hidden, 0, O, L.outp);
+  dim3 grid(L.outp / 16, (n + 15) / 16);
+  k_gemm_f64_skinny<<<grid, 256, 0, s>>>(in, L.hidden, (const bf16*)(params + L.w[3]), L.hidden,
+                                         (const float*)(params + L.b[3]), n, L.outp, L.hidden, 0, O,
+                                         L.outp);
   return hipGetLastError();
 }
 
@@ -682,7 +713,9 @@ l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_
 
 l1pr_status l1pr_mlp_forward(int32_t modes, const void* params, const float* x, int32_t n,
                              float* y, void* ws, size_t ws_bytes, void* stream) {
-  if (modes < 1 || modes > kMlpMaxModes || !params || !x || !y || n < 1 || !ws) return L1PR_EINVAL;
+  if (modes < 1 || modes > kMlpMaxModes || !params || ((uintptr_t)params & 255) || !x || !y ||
+      n < 1 || !ws)
+    return L1PR_EINVAL;
   const MlpLayout L = mlp_layout(modes);
   if (ws_bytes < mlp_ws_bytes(L, n, false)) return L1PR_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
@@ -702,7 +735,9 @@ l1pr_status l1pr_mlp_forward(int32_t modes, const void* params, const float* x, 
 
 l1pr_status l1pr_mlp_infer(int32_t modes, const void* params, const double* x, int32_t n, double* y,
                            void* ws, size_t ws_bytes, void* stream) {
-  if (modes < 1 || modes > kMlpMaxModes || !params || !x || !y || n < 1 || !ws) return L1PR_EINVAL;
+  if (modes < 1 || modes > kMlpMaxModes || !params || ((uintptr_t)params & 255) || !x || !y ||
+      n < 1 || !ws)
+    return L1PR_EINVAL;
   const MlpLayout L = mlp_layout(modes);
   if (ws_bytes < mlp_infer_ws_bytes(L, n)) return L1PR_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
