@@ -3,22 +3,28 @@
 //
 // The lower triangle of A = I + tau K is split into 16x16 tiles (at most 136); wave w keeps
 // the tile-rows w and nt-1-w in its registers as FP64 MFMA accumulators (at most 17 tiles,
-// 136 registers, per wave).  Two ways to fill the tiles:
+// 136 registers, per wave).  A tile is stored transposed: slot (I, K) holds A_IK^T in the
+// accumulator layout (lane l, element v <-> row l/16 + 4v, column l%16).  That layout is
+// the B-operand layout of MFMA 16x16x4 (k-chunk v): the panel product takes its register
+// tile straight as B operand, and a published panel tile serves as A or B operand lane for
+// lane (linear, conflict-free LDS reads):
+//   panel     L_Ij^T = W_j^T A_Ij^T                (W_j = L_jj^-T from LDS, A_Ij^T registers)
+//   trailing  A_IK^T -= L_Kj L_Ij^T                 (both published panel tiles)
+// Two ways to fill the tiles:
 //   SRC_MOMENTS  from the cosine moments m_j = sum_q w_q D_q cos(j pi x_q): in the sine basis
 //                phi_k' phi_l' = k l pi^2 [cos((k-l) pi x) + cos((k+l) pi x)], so the
 //                quadrature stiffness is K_kl = k l pi^2 (m_|k-l| + m_{k+l}) term by term
 //                (Toeplitz-plus-Hankel form; 2M+1 moments instead of M^2 dot products);
 //   SRC_LOAD     from the stiffness tiles that k_assemble1d (quadrature GEMM) wrote.
 // The right-hand side is hist + tau F (history sums and load vector from the batched
-// kernels).  Then a right-looking Cholesky by 16-column blocks without leaving the chip:
-//   - wave 0 factors the diagonal tile (one row per lane, values broadcast with readlane,
-//     pivots from a reciprocal square root refined by two Newton steps), forms
-//     W = L_jj^-T by column substitution and y_j = W^T b_j;
-//   - panel tiles become L_Ij = A_Ij W (MFMA), staged in LDS;
-//   - the owners of trailing tiles subtract L_Ij L_Kj^T (MFMA), and b_I -= L_Ij y_j.
-// Back substitution L^T x = y uses the L tiles still in registers and W_j kept in the
-// diagonal tiles.  All reductions have a fixed order, so a unit's result does not depend on
-// the launch it is part of.
+// kernels).  Right-looking Cholesky by 16-column blocks, with look-ahead: while the other
+// waves apply block j to the right-hand side, the owner of diagonal tile j+1 updates that
+// tile and turns it into W_{j+1} = L^-T directly (column elimination on [A ; I] in the
+// accumulator layout); then every wave updates its trailing tiles.  Forward substitution
+// runs alongside (y_j = W_j^T b_j, then b_I -= L_Ij y_j).  Before the back substitution
+// L^T x = y every wave transposes its tiles back (L_IK, and L_jj^-1 on the diagonal); the back
+// substitution then runs as a pipeline across waves (see there).  All reductions have a
+// fixed order, so a unit's result does not depend on the launch it is part of.
 #include "l1pr_internal.h"
 
 namespace l1pr {
@@ -32,9 +38,11 @@ constexpr int RMAXMP = 256;
 
 enum { SRC_MOMENTS = 0, SRC_LOAD = 1 };
 
-__device__ inline double bcast(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+// Value of lane P of the caller's 16-lane row (DPP row broadcast), for a double.
+template <int P>
+__device__ inline double rowbc(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + P, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + P, 0xf, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -54,16 +62,6 @@ __device__ inline void slot_tile(int s, int wave, int nt, int& I, int& K) {
   }
 }
 
-// Slot coordinates for use inside the block loop.  The empty asm marks them as redefined on
-// every use, so the compiler does not hoist per-slot addresses out of the loop and keep
-// them live next to the 136 accumulator registers.
-__device__ inline void slot_tile_here(int s, int wave, int nt, int& I, int& K) {
-  slot_tile(s, wave, nt, I, K);
-  I = __builtin_amdgcn_readfirstlane(I);
-  K = __builtin_amdgcn_readfirstlane(K);
-  asm volatile("" : "+s"(I), "+s"(K));
-}
-
 // owner wave and slot of the diagonal tile (j, j)
 __device__ inline void diag_owner(int j, int nt, int& w, int& s) {
   w = j < nt - 1 - j ? j : nt - 1 - j;
@@ -73,20 +71,26 @@ __device__ inline void diag_owner(int j, int nt, int& w, int& s) {
 #define SLOT_FENCE() __builtin_amdgcn_sched_barrier(0)
 
 struct RegLds {
-  int sb, sD, sW, sI, ct, big;  // offsets in doubles; `big` holds the moments, then the panel
+  int sb;     // right-hand side, then y, then x            [Mp]
+  int sWA;    // W_j in A-operand order: [v][lane]           [4][64]
+  int prog;   // back-substitution turn counters per tile-row (16 ints)
+  int big;    // the moments (fill), the published panel [nt][4][64], then per-wave
+              // transposition scratch [8][16 x 17]
   int total;
 };
 
 __host__ __device__ inline RegLds reg_lds(int Mp) {
   RegLds L;
   L.sb = 0;
-  L.sD = Mp;
-  L.sW = L.sD + 16 * 17;
-  L.sI = L.sW + 16 * 17;
-  L.ct = L.sI + 16;
-  L.big = L.ct + 16 * 16;
+  L.sWA = Mp;
+  L.prog = L.sWA + 256;
+  L.big = L.prog + 8;
   const int Jm = 2 * Mp + 1;
-  L.total = L.big + (Jm > Mp * 17 ? Jm : Mp * 17);
+  const int panel = (Mp / 16) * 256;
+  const int scratch = RW * 16 * 17;
+  int big = Jm > panel ? Jm : panel;
+  big = big > scratch ? big : scratch;
+  L.total = L.big + big;
   return L;
 }
 
@@ -99,6 +103,95 @@ __device__ inline double rsqrt_nr(double x) {
   return y;
 }
 
+// 1/x to full double precision: the hardware estimate (relative error about 2^-23) and one
+// third-order step, y0 (1 + e + e^2) with e = 1 - x y0 (error about e^3): three dependent
+// operations after the estimate.
+__device__ inline double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y, fma(e, e, e), y);
+}
+
+#define WAVE_FENCE()                                     \
+  do {                                                   \
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+  } while (0)
+
+// Value of lane `src` (any lane) for every lane, for a double (LDS crossbar, no memory).
+__device__ inline double lane_read(double v, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Value of lane `src` as a wave-uniform double.
+__device__ inline double lane_uniform(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// W = L^-T for the Cholesky factor L of one symmetric positive definite 16x16 tile, inside
+// one wave, both in the accumulator layout (lane l, element v <-> row l/16 + 4v, column
+// l%16).  Column elimination on the stacked pair [A ; I]: step p subtracts
+// (a_pc / a_pp) x column p from every column c > p, so A E_0 ... E_15 = Lt is lower
+// triangular with column p equal to the trailing column at step p, and I E_0 ... E_15
+// S = A^-1 L = L^-T with S = diag(1 / sqrt(a_pp)) (a_pp: the pivot at step p).  Each lane owns four entries of each half:
+// the pivot comes from one lane (readlane), the pivot row from the lanes of its row group
+// (bpermute), the pivot column from lane p of the caller's 16-lane row (DPP broadcast).
+// Work that is zero by structure is skipped: at step p the pivot column of the A half is only
+// needed in rows >= p (rows above feed nothing that is read again), and the pivot column of
+// the I half is zero below row p.
+struct DiagFactor {
+  double a[4], w[4], sc;
+
+  __device__ __attribute__((always_inline)) void init(const d4& t, int lane) {
+    const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      a[v] = t[v];
+      w[v] = (lr + 4 * v == lc) ? 1.0 : 0.0;
+    }
+    sc = 0.0;
+  }
+
+  template <int P>
+  __device__ __attribute__((always_inline)) void step(int lane) {
+    const int lc = lane & 15;
+    const double piv = lane_uniform(a[P / 4], (P % 4) * 16 + P);
+    const double rowp = lane_read(a[P / 4], (P % 4) * 16 + lc);
+    // the next pivot waits on m only; the column scale 1/sqrt(a_pp) is off that chain
+    const double m = (lc > P) ? rowp * rcp_nr(piv) : 0.0;
+    if (lc == P) sc = rsqrt_nr(piv);
+#pragma unroll
+    for (int v = P / 4; v < 4; ++v) a[v] = fma(-rowbc<P>(a[v]), m, a[v]);
+#pragma unroll
+    for (int v = 0; v <= P / 4; ++v) w[v] = fma(-rowbc<P>(w[v]), m, w[v]);
+  }
+
+  // W in the accumulator layout; also published in A-operand order,
+  // sWA[v][lane] = W[4v + lane/16][lane%16]
+  __device__ __attribute__((always_inline)) d4 finish(int lane, double* sWA) {
+    d4 out;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      out[v] = w[v] * sc;
+      sWA[v * 64 + lane] = out[v];
+    }
+    WAVE_FENCE();
+    return out;
+  }
+};
+
+#define L1PR_DIAG_STEPS(DF, BETWEEN)                                                    \
+  DF.step<0>(lane); BETWEEN(0) DF.step<1>(lane); BETWEEN(1) DF.step<2>(lane); BETWEEN(2)    \
+  DF.step<3>(lane); BETWEEN(3) DF.step<4>(lane); BETWEEN(4) DF.step<5>(lane); BETWEEN(5)    \
+  DF.step<6>(lane); BETWEEN(6) DF.step<7>(lane); BETWEEN(7) DF.step<8>(lane); BETWEEN(8)    \
+  DF.step<9>(lane); BETWEEN(9) DF.step<10>(lane); BETWEEN(10) DF.step<11>(lane);           \
+  BETWEEN(11) DF.step<12>(lane); BETWEEN(12) DF.step<13>(lane); BETWEEN(13)                \
+  DF.step<14>(lane); BETWEEN(14) DF.step<15>(lane); BETWEEN(15)
+
 template <int SRC>
 __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue ep,
                                                  const double* mom, const double* F,
@@ -110,10 +203,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   const int Mp = tb.Mp, M = tb.M, nt = Mp / 16;
   const RegLds LO = reg_lds(Mp);
   double* sb = lds + LO.sb;
-  double* sD = lds + LO.sD;
-  double* sW = lds + LO.sW;
-  double* sI = lds + LO.sI;
-  double* ct = lds + LO.ct;
+  double* sWA = lds + LO.sWA;
   double* sP = lds + LO.big;
   d4 acc[RNS];
   const int lr = lane >> 4, lc = lane & 15;
@@ -123,6 +213,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   for (int k = tid; k < Mp; k += RT)
     sb[k] = hist[(long)u * Mp + k] + tau * F[(long)u * Mp + k];
 
+  // slot (I, K) element v of lane l holds A[16 I + l%16][16 K + l/16 + 4v]
   if (SRC == SRC_MOMENTS) {
     const int Jm = 2 * Mp + 1;
     double* sm = sP;
@@ -136,7 +227,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       if (tI < 0) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int k = tI * 16 + lr + 4 * e, l = tK * 16 + lc;
+        const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
         double val = (k == l) ? 1.0 : 0.0;
         if (k < M && l < M) {
           const int dkl = k > l ? k - l : l - k;
@@ -156,197 +247,202 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       if (tI < 0) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        acc[s][e] = A[(long)(tI * 16 + lr + 4 * e) * Mp + tK * 16 + lc];
+        acc[s][e] = A[(long)(tI * 16 + lc) * Mp + tK * 16 + lr + 4 * e];
     }
-    __syncthreads();
   }
 
   // ------------------------------------------------------------ factorisation
+  {
+    int wd, sdg;
+    diag_owner(0, nt, wd, sdg);
+    if (wave == wd) {  // the owner of tile-row 0 keeps (0, 0) in slot 0
+      DiagFactor df;
+      df.init(acc[0], lane);
+#define L1PR_NOTHING(P)
+      L1PR_DIAG_STEPS(df, L1PR_NOTHING)
+#undef L1PR_NOTHING
+      acc[0] = df.finish(lane, sWA);
+    }
+  }
+  __syncthreads();
   for (int j = 0; j < nt; ++j) {
     const int j0 = 16 * j;
-    int wd, sdg;
-    diag_owner(j, nt, wd, sdg);
-    // stage the diagonal tile and the panel tiles (I, j), I > j
-    if (wave == wd) {
-#pragma unroll
-      for (int s = 0; s < RNS; ++s)
-        if (s == sdg)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) sD[(lr + 4 * e) * 17 + lc] = acc[s][e];
-    }
+    // ---- panel: L_Ij^T = W_j^T A_Ij^T for the tiles (I, j), I > j, of this wave
 #pragma unroll
     for (int s = 0; s < RNS; ++s) {
       int tI, tK;
-      slot_tile_here(s, wave, nt, tI, tK);
-      if (tK == j && tI > j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sP[(tI * 16 + lr + 4 * e) * 17 + lc] = acc[s][e];
-    }
-    __syncthreads();
-    if (wave == 0) {
-      // Lane r holds row r of the diagonal block; columns are factored left to right.
-      // Branch-free: every lane scales its entry of column c (the entries above the diagonal
-      // are zero, so the same product is right for every row), every lane publishes it
-      // through LDS (lanes r and r + 16k hold identical rows and write identical values), and
-      // every lane applies the rank-one update; entries above the diagonal collect values
-      // that are never read and are masked when the factor is written out.
-      const int r = lane & 15;
-      double* col = ct;  // exchange space (the back substitution reuses it)
-      double v[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) v[c] = (c <= r) ? sD[r * 17 + c] : 0.0;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        col[r] = v[c];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double inv = rsqrt_nr(col[c]);
-        v[c] = v[c] * inv;
-        sI[c] = inv;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        col[r] = v[c];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double lsc[16];
-#pragma unroll
-        for (int s2 = c + 1; s2 < 16; ++s2) lsc[s2] = col[s2];
-#pragma unroll
-        for (int s2 = c + 1; s2 < 16; ++s2) v[s2] = fma(-v[c], lsc[s2], v[s2]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) sD[r * 17 + c] = (c <= r) ? v[c] : 0.0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // Column c of X = L^-1 (lane c), right-looking: once x_p is known it is removed from
-      // every later row, so the dependency chain is 16 steps deep.  W = X^T = L^-T.
-      {
-        const int c = lane & 15;
-        double sx[16];
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) sx[rr] = (rr == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int p2 = 0; p2 < 16; ++p2) {
-          sx[p2] = sx[p2] * sI[p2];
-#pragma unroll
-          for (int rr = p2 + 1; rr < 16; ++rr) sx[rr] -= sD[rr * 17 + p2] * sx[p2];
-        }
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) sW[c * 17 + rr] = sx[rr];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // y_j = L_jj^-1 b_j = W^T b_j
-      double y = 0.0;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) y += sW[c * 17 + r] * sb[j0 + c];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      sb[j0 + r] = y;
-    }
-    __syncthreads();
-    if (wave == wd) {
-      // keep W_j in the diagonal tile for the back substitution
-#pragma unroll
-      for (int s = 0; s < RNS; ++s)
-        if (s == sdg)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[s][e] = sW[(lr + 4 * e) * 17 + lc];
-    }
-    // L_Ij = A_Ij W; each wave reads and rewrites only the rows of its own panel tiles
-#pragma unroll
-    for (int s = 0; s < RNS; ++s) {
-      int tI, tK;
-      slot_tile_here(s, wave, nt, tI, tK);
+      slot_tile(s, wave, nt, tI, tK);
       if (tK == j && tI > j) {
-        d4 l = d4{0.0, 0.0, 0.0, 0.0};
+        d4 t = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const double aop = sP[(tI * 16 + lc) * 17 + 4 * kk + lr];
-          const double bop = sW[(4 * kk + lr) * 17 + lc];
-          l = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, l, 0, 0, 0);
-        }
-        acc[s] = l;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int v = 0; v < 4; ++v)
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(sWA[v * 64 + lane], acc[s][v], t, 0, 0, 0);
+        acc[s] = t;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) sP[(tI * 16 + lr + 4 * e) * 17 + lc] = l[e];
+        for (int v = 0; v < 4; ++v) sP[(tI * 4 + v) * 64 + lane] = t[v];
       }
       SLOT_FENCE();
     }
-    __syncthreads();
-    // right-hand side below the block, and the trailing tiles
-    for (int i = j0 + 16 + tid; i < Mp; i += RT) {
-      double bi = sb[i];
+    // ---- forward substitution for the block: y_j = W_j^T b_j
+    {
+      int wd, sdg;
+      diag_owner(j, nt, wd, sdg);
+      if (wave == wd) {
+        double pr = 0.0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c) bi -= sP[i * 17 + c] * sb[j0 + c];
-      sb[i] = bi;
-    }
-#pragma unroll
-    for (int s = 0; s < RNS; ++s) {
-      int tI, tK;
-      slot_tile_here(s, wave, nt, tI, tK);
-      if (tK > j) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const double aop = -sP[(tI * 16 + lc) * 17 + 4 * kk + lr];
-          const double bop = sP[(tK * 16 + lc) * 17 + 4 * kk + lr];
-          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc[s], 0, 0, 0);
-        }
+        for (int v = 0; v < 4; ++v) pr += sWA[v * 64 + lane] * sb[j0 + 4 * v + lr];
+        pr += __shfl_xor(pr, 16);
+        pr += __shfl_xor(pr, 32);
+        WAVE_FENCE();
+        if (lane < 16) sb[j0 + lc] = pr;
       }
-      SLOT_FENCE();
     }
     __syncthreads();
+    // ---- look-ahead: the owner of diagonal tile j+1 updates it and turns it into W_{j+1}
+    // while the other waves apply block j to the right-hand side; then every wave updates
+    // its trailing tiles, A_IK^T -= L_Kj L_Ij^T for K > j.
+    const int j1 = j + 1;
+    int wd1 = -1, sd1 = -1;
+    if (j1 < nt) diag_owner(j1, nt, wd1, sd1);
+    if (wave == wd1) {
+      d4 t = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < RNS; ++s)
+        if (s == sd1) t = acc[s];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double px = sP[(j1 * 4 + v) * 64 + lane];
+        t = __builtin_amdgcn_mfma_f64_16x16x4f64(-px, px, t, 0, 0, 0);
+      }
+      DiagFactor df;
+      df.init(t, lane);
+#define L1PR_NOTHING(P)
+      L1PR_DIAG_STEPS(df, L1PR_NOTHING)
+#undef L1PR_NOTHING
+      t = df.finish(lane, sWA);
+#pragma unroll
+      for (int s = 0; s < RNS; ++s)
+        if (s == sd1) acc[s] = t;
+    } else {
+      // right-hand side below the block: b_i -= L_ij y_j
+      const int nthr = (wd1 >= 0) ? RT - 64 : RT;
+      const int tt = (wd1 >= 0 && wave > wd1) ? tid - 64 : tid;
+      for (int i = j0 + 16 + tt; i < Mp; i += nthr) {
+        const int I = i >> 4, r = i & 15;
+        double bi = sb[i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) bi -= sP[(I * 4 + (c >> 2)) * 64 + (c & 3) * 16 + r] * sb[j0 + c];
+        sb[i] = bi;
+      }
+    }
+#define L1PR_TRAIL(S)                                                                          \
+  {                                                                                            \
+    int tI, tK;                                                                                \
+    slot_tile((S), wave, nt, tI, tK);                                                     \
+    if (tK > j && !(tI == j1 && tK == j1)) {                                                   \
+      _Pragma("unroll") for (int v = 0; v < 4; ++v) acc[(S)] =                                 \
+          __builtin_amdgcn_mfma_f64_16x16x4f64(-sP[(tK * 4 + v) * 64 + lane],                  \
+                                               sP[(tI * 4 + v) * 64 + lane], acc[(S)], 0, 0, 0); \
+    }                                                                                          \
+    SLOT_FENCE();                                                                              \
+  }
+#pragma unroll
+    for (int s = 0; s < RNS; ++s) L1PR_TRAIL(s)
+    __syncthreads();
+#undef L1PR_TRAIL
   }
 
-  // ------------------------------------------------------- back substitution
-  // L^T x = y, last block first.  Tile-row j (W_j on the diagonal and L_jK, K < j) belongs to
-  // one wave, which forms x_j = W_j y_j in registers and removes L_jK^T x_j from every y_K.
-  for (int j = nt - 1; j >= 0; --j) {
-    const int j0 = 16 * j;
-    int wd, sdg;
-    diag_owner(j, nt, wd, sdg);
-    if (wave == wd) {
-      const double sv = sb[j0 + lc];
-      // x_j = W_j y_j: lane holds W[lr + 4e][lc]; sum over the 16 columns
-      double xr[4] = {0.0, 0.0, 0.0, 0.0};
+  // ---- every slot back to the accumulator layout of the untransposed tile: L_IK off the
+  // diagonal, X_j = W_j^T = L_jj^-1 on it; per-wave scratch in the panel space
+  int* tok = reinterpret_cast<int*>(lds + LO.prog);
+  if (tid < 16) tok[tid] = 0;
+  {
+    double* scr = sP + wave * (16 * 17);
 #pragma unroll
-      for (int s = 0; s < RNS; ++s) {
-        if (s == sdg) {
+    for (int s = 0; s < RNS; ++s) {
+      int tI, tK;
+      slot_tile(s, wave, nt, tI, tK);
+      if (tI >= 0) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            double p = acc[s][e] * sv;
-            p += __shfl_xor(p, 1);
-            p += __shfl_xor(p, 2);
-            p += __shfl_xor(p, 4);
-            p += __shfl_xor(p, 8);
-            xr[e] = p;
-          }
-        }
+        for (int v = 0; v < 4; ++v) scr[(lr + 4 * v) * 17 + lc] = acc[s][v];
+        WAVE_FENCE();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[s][v] = scr[lc * 17 + lr + 4 * v];
+        WAVE_FENCE();
       }
-      // y_K -= L_jK^T x_j: lane holds L_jK[lr + 4e][lc] and x_j[lr + 4e]
+      SLOT_FENCE();
+    }
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------- back substitution
+  // L^T x = y by tile-rows, last first: z_j = y_j - sum_{I > j} L_Ij^T x_I, x_j = X_j^T z_j.
+  // z lives in sb in place of y.  The owner of tile-row j waits until every row I > j has
+  // subtracted its part from z_j (tok[j] == nt-1-j), forms x_j (stored over z_j), then
+  // subtracts L_jK^T x_j from z_K for K = j-1, j-2, ..., 0.  Each of those subtractions first
+  // waits for its turn on block K (tok[K] == nt-1-j), so the parts reach z_K in a fixed order
+  // (rows from the last down) whatever the timing.  A row only waits on higher rows, and each
+  // wave takes its higher row first, so every wait ends (the spins are bounded all the same).
+  {
+    const int ra = wave, rb = nt - 1 - wave;
+#define L1PR_WAIT_TOKEN(K, WANT)                                                              \
+  if (lane == 0) {                                                                             \
+    for (int it = 0; it < (1 << 18); ++it) {                                                   \
+      if (__hip_atomic_load(&tok[(K)], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= (WANT)) \
+        break;                                                                                 \
+      __builtin_amdgcn_s_sleep(1);                                                             \
+    }                                                                                          \
+  }                                                                                            \
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
-      for (int s = 0; s < RNS; ++s) {
-        int tI, tK;
-        slot_tile_here(s, wave, nt, tI, tK);
-        if (tI == j && tK < j) {
-          double p = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      const int j = pass == 0 ? rb : ra;
+      if (ra > rb || (pass == 1 && ra == rb)) continue;  // wave-uniform
+      const int j0 = 16 * j;
+      int wd, sdg;
+      diag_owner(j, nt, wd, sdg);
+      L1PR_WAIT_TOKEN(j, nt - 1 - j)
+      double z[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) p += acc[s][e] * xr[e];
-          p += __shfl_xor(p, 16);
-          p += __shfl_xor(p, 32);
-          if (lane < 16) sb[tK * 16 + lc] -= p;
+      for (int v = 0; v < 4; ++v) z[v] = sb[j0 + lr + 4 * v];
+      d4 X = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < RNS; ++s)
+        if (s == sdg) X = acc[s];
+      double pr = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pr += X[v] * z[v];
+      pr += __shfl_xor(pr, 16);
+      pr += __shfl_xor(pr, 32);
+      WAVE_FENCE();
+      if (lane < 16) sb[j0 + lc] = pr;  // x_j over z_j
+      WAVE_FENCE();
+      double xv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xv[v] = sb[j0 + lr + 4 * v];
+      // nearest block first.  Slots of row ra are s = K, of row rb (when rb > ra)
+      // s = ra + 1 + K, so the slot range of row j is known without decoding every slot.
+      const int s_lo = (pass == 0 && ra < rb) ? ra + 1 : 0;  // slot of (j, 0)
+#pragma unroll
+      for (int s = RNS - 1; s >= 0; --s) {
+        if (s >= s_lo && s < s_lo + j) {
+          const int tK = s - s_lo;
+          double q = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) q += acc[s][v] * xv[v];
+          q += __shfl_xor(q, 16);
+          q += __shfl_xor(q, 32);
+          L1PR_WAIT_TOKEN(tK, nt - 1 - j)
+          if (lane < 16) sb[tK * 16 + lc] -= q;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          if (lane == 0) __hip_atomic_store(&tok[tK], nt - j, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         SLOT_FENCE();
       }
-      if (lc == 0)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) sb[j0 + lr + 4 * e] = xr[e];
     }
-    __syncthreads();
+#undef L1PR_WAIT_TOKEN
   }
+  __syncthreads();
 
   // --------------------------------------------------------------- epilogue
   long slot = u;
