@@ -118,11 +118,36 @@ __device__ inline double rcp_nr(double x) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
   } while (0)
 
+// Cross-row exchanges with the gfx950 row swaps (VALU, no LDS): for one register,
+// permlane16_swap gives the row pairs (r0, r0, r2, r2) and (r1, r1, r3, r3), and
+// permlane32_swap gives (r0, r1, r0, r1) and (r2, r3, r2, r3), where r_g is the value a lane
+// at the same position of 16-lane row g holds.
+__device__ inline void swap16(double v, double& even, double& odd) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  even = __hiloint2double(hi[0], lo[0]);
+  odd = __hiloint2double(hi[1], lo[1]);
+}
+__device__ inline void swap32(double v, double& low, double& high) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  low = __hiloint2double(hi[0], lo[0]);
+  high = __hiloint2double(hi[1], lo[1]);
+}
+
 // Value of lane `src` (any lane) for every lane, for a double (LDS crossbar, no memory).
 __device__ inline double lane_read(double v, int src) {
   const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
   const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
   return __hiloint2double(hi, lo);
+}
+
+// (r0 + r1) + (r2 + r3) over the four 16-lane rows, in every lane.
+__device__ inline double rowgroup_sum(double v) {
+  double e, o, l, h;
+  swap16(v, e, o);
+  swap32(e + o, l, h);
+  return l + h;
 }
 
 // Value of lane `src` as a wave-uniform double.
@@ -139,12 +164,13 @@ __device__ inline double lane_uniform(double v, int src) {
 // triangular with column p equal to the trailing column at step p, and I E_0 ... E_15
 // S = A^-1 L = L^-T with S = diag(1 / sqrt(a_pp)) (a_pp: the pivot at step p).  Each lane owns four entries of each half:
 // the pivot comes from one lane (readlane), the pivot row from the lanes of its row group
-// (bpermute), the pivot column from lane p of the caller's 16-lane row (DPP broadcast).
+// (bpermute, whose latency overlaps the reciprocal), the pivot column from lane p of the
+// caller's 16-lane row (DPP broadcast).
 // Work that is zero by structure is skipped: at step p the pivot column of the A half is only
 // needed in rows >= p (rows above feed nothing that is read again), and the pivot column of
 // the I half is zero below row p.
 struct DiagFactor {
-  double a[4], w[4], sc;
+  double a[4], w[4], sc;  // sc: the pivot of this lane's column, then 1/sqrt of it
 
   __device__ __attribute__((always_inline)) void init(const d4& t, int lane) {
     const int lr = lane >> 4, lc = lane & 15;
@@ -153,7 +179,7 @@ struct DiagFactor {
       a[v] = t[v];
       w[v] = (lr + 4 * v == lc) ? 1.0 : 0.0;
     }
-    sc = 0.0;
+    sc = 1.0;
   }
 
   template <int P>
@@ -161,9 +187,9 @@ struct DiagFactor {
     const int lc = lane & 15;
     const double piv = lane_uniform(a[P / 4], (P % 4) * 16 + P);
     const double rowp = lane_read(a[P / 4], (P % 4) * 16 + lc);
-    // the next pivot waits on m only; the column scale 1/sqrt(a_pp) is off that chain
+    // the next pivot waits on m only; the column scale 1/sqrt(a_pp) is formed at the end
     const double m = (lc > P) ? rowp * rcp_nr(piv) : 0.0;
-    if (lc == P) sc = rsqrt_nr(piv);
+    sc = (lc == P) ? piv : sc;
 #pragma unroll
     for (int v = P / 4; v < 4; ++v) a[v] = fma(-rowbc<P>(a[v]), m, a[v]);
 #pragma unroll
@@ -173,6 +199,7 @@ struct DiagFactor {
   // W in the accumulator layout; also published in A-operand order,
   // sWA[v][lane] = W[4v + lane/16][lane%16]
   __device__ __attribute__((always_inline)) d4 finish(int lane, double* sWA) {
+    sc = rsqrt_nr(sc);
     d4 out;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -291,8 +318,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
         double pr = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) pr += sWA[v * 64 + lane] * sb[j0 + 4 * v + lr];
-        pr += __shfl_xor(pr, 16);
-        pr += __shfl_xor(pr, 32);
+        pr = rowgroup_sum(pr);
         WAVE_FENCE();
         if (lane < 16) sb[j0 + lc] = pr;
       }
@@ -412,8 +438,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       double pr = 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) pr += X[v] * z[v];
-      pr += __shfl_xor(pr, 16);
-      pr += __shfl_xor(pr, 32);
+      pr = rowgroup_sum(pr);
       WAVE_FENCE();
       if (lane < 16) sb[j0 + lc] = pr;  // x_j over z_j
       WAVE_FENCE();
@@ -430,8 +455,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
           double q = 0.0;
 #pragma unroll
           for (int v = 0; v < 4; ++v) q += acc[s][v] * xv[v];
-          q += __shfl_xor(q, 16);
-          q += __shfl_xor(q, 32);
+          q = rowgroup_sum(q);
           L1PR_WAIT_TOKEN(tK, nt - 1 - j)
           if (lane < 16) sb[tK * 16 + lc] -= q;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
