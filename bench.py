@@ -28,6 +28,10 @@ The JSON line also carries:
                   dphi^T diag(w D) dphi on FP64 MFMA (assembly = 1); its assembly kernel's
                   roofline counts Q M (M+1) flops per unit (the M(M+1)/2 distinct entries of
                   the symmetric stiffness, 2Q flops each).
+  uneven_batch    256 instances with their own modes, steps per slice and order, grouped by
+                  padded mode count, all groups' parareal runs in one HIP graph (one branch per
+                  group, tiles autotuned per group); useful mode-steps/s and per-instance
+                  latency percentiles from device stamps at each instance's convergence sweep.
   learned_vs_plain  the learned-coarse workload: 1D, M = 128, Q = 192, N = 2048, P = 64,
                   alpha ~ U(0.2, 1), D and f as above; the residual network is trained on
                   4096 seeded serial trajectories (one-off, untimed but reported), then plain
@@ -82,7 +86,9 @@ def rel_err_max(its_k, Us):
     return float((d / n).max())
 
 
-def cpu_baseline(kw, u0_np, n_inst):
+def cpu_baseline(kw, u0_np, n_inst, min_seconds=10.0):
+    """The oracle's fine propagator on the first slice of n_inst instances, one instance per
+    thread, repeated until about min_seconds of wall time have passed."""
     import concurrent.futures as cf
 
     import oracle
@@ -91,14 +97,20 @@ def cpu_baseline(kw, u0_np, n_inst):
     po = oracle.problem(**kw)
     S = kw["steps"] // kw["slices"]
     threads = max(1, min(16, os.cpu_count() or 1, n_inst))
+    rounds = 0
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(lambda b: oracle.fine_F(po, 0, u0_np[b:b + 1]), range(n_inst)))
+        while True:
+            list(ex.map(lambda b: oracle.fine_F(po, 0, u0_np[b:b + 1]), range(n_inst)))
+            rounds += 1
+            if time.perf_counter() - t0 >= min_seconds or rounds >= 64:
+                break
     dt = time.perf_counter() - t0
-    mode_steps = n_inst * S * kw["modes"]
+    mode_steps = rounds * n_inst * S * kw["modes"]
     return {"value": mode_steps / dt, "unit": "mode-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle serial fine propagator, first slice ({S} steps) of {n_inst} "
-                      f"alpha={kw['alpha']} instances, one instance per thread, {dt:.1f} s wall"}
+            "sample": f"oracle serial fine propagator, first slice ({S} steps, M={kw['modes']}) of "
+                      f"{n_inst} alpha={kw['alpha']} instances, one instance per thread, "
+                      f"{rounds} rounds, {dt:.1f} s wall"}
 
 
 def find_kstar(l1, p, u0, Us, ws, max_iter, **kw):
@@ -164,6 +176,108 @@ def learned_vs_plain(l1, torch, W, dev):
     return out
 
 
+def uneven_batch(l1, torch, W, dev):
+    """Config 5: 256 instances with their own modes, steps per slice and order, grouped by
+    padded mode count; every group's parareal run is one branch of a single HIP graph."""
+    import numpy as np
+
+    from paper_2510_11023_amd import solver
+
+    modes, spp, alpha = W.c5_instances()
+    P = W.C5["slices"]
+    mp = (modes + 15) // 16 * 16
+    groups = []
+    t_ser = 0.0
+    for Mp in sorted(set(mp.tolist())):
+        idx = np.nonzero(mp == Mp)[0]
+        B = len(idx)
+        kw = W.with_(W.C5, modes=int(Mp), quad=2 * int(Mp), steps=P * int(spp[idx].max()))
+        p = l1.make_problem(**kw)
+        ws = solver._workspace(p, B, 1, dev)[0]
+        p.tune = l1.autotune(p, B, workspace=ws)
+        u0 = torch.zeros((B, int(Mp)), dtype=torch.float64, device=dev)
+        u0[:, 0] = 2.0 ** -0.5
+        g = dict(idx=idx, p=p, ws=ws, u0=u0, B=B, Mp=int(Mp),
+                 modes=torch.tensor(modes[idx], dtype=torch.int32, device=dev),
+                 spp=torch.tensor(spp[idx], dtype=torch.int32, device=dev),
+                 alpha=torch.tensor(alpha[idx], dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g["Us"] = l1.solve_serial_uneven(p, u0, g["modes"], g["spp"], g["alpha"])
+        torch.cuda.synchronize()
+        t_ser += time.perf_counter() - t0
+        groups.append(g)
+    # sweeps per group: until every instance's increment is <= 1e-8 (capped), found untimed
+    cap, tol = 24, 1e-8
+    for g in groups:
+        U, conv, _ = l1.solve_parareal_uneven(g["p"], g["u0"], cap, g["modes"], g["spp"],
+                                              g["alpha"], conv_tol=tol, workspace=g["ws"])
+        c = conv.cpu().numpy()
+        g["sweeps"] = int(cap if (c < 0).any() else c.max())
+        g["out"] = torch.empty_like(U)
+        g["conv"] = torch.empty(g["B"], dtype=torch.int32, device=dev)
+        g["stamps"] = torch.zeros(g["sweeps"] + 1, dtype=torch.int64, device=dev)
+        g["stream"] = torch.cuda.Stream()
+    t_start = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def run_all():
+        solver.device_stamp(t_start)
+        main = torch.cuda.current_stream()
+        for g in groups:
+            g["stream"].wait_stream(main)
+            with torch.cuda.stream(g["stream"]):
+                l1.solve_parareal_uneven(g["p"], g["u0"], g["sweeps"], g["modes"], g["spp"],
+                                         g["alpha"], conv_tol=tol, workspace=g["ws"],
+                                         out=g["out"], conv=g["conv"], stamps=g["stamps"])
+        for g in groups:
+            main.wait_stream(g["stream"])
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run_all()  # warm-up outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run_all()
+    graph.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_graph = sorted(times)[1]
+    khz = solver.wall_clock_khz()
+    lat, err = [], 0.0
+    t0d = int(t_start.item())
+    for g in groups:
+        conv = g["conv"].cpu().numpy()
+        st = g["stamps"].cpu().numpy()
+        for b in range(g["B"]):
+            k = conv[b] if conv[b] > 0 else g["sweeps"]
+            lat.append((st[k] - t0d) / khz)  # ms
+        d = (g["out"] - g["Us"]).flatten(1).norm(dim=1) / g["Us"].flatten(1).norm(dim=1)
+        err = max(err, float(d.max()))
+    lat = np.array(lat)
+    useful = float((modes.astype(np.int64) * P * spp).sum())
+    log(f"uneven batch: {len(groups)} groups, graph {t_graph * 1e3:.1f} ms, serial {t_ser * 1e3:.1f} ms, "
+        f"max error vs serial {err:.2e}, latency p50/p90/p99 {np.percentile(lat, 50):.1f}/"
+        f"{np.percentile(lat, 90):.1f}/{np.percentile(lat, 99):.1f} ms")
+    return {"workload": "256 instances, P=64, M~U{64..256}, S~U{8..64} (N=64 S), alpha~U(0.2,1), "
+                        "D=1+sin^2(u)/2, manufactured f, u0=sin(pi x); grouped by roundup16(M) "
+                        "(Q = 2 roundup16(M)); one HIP graph with one branch per group",
+            "groups": [{"Mp": g["Mp"], "instances": g["B"], "sweeps": g["sweeps"], "tune": g["p"].tune}
+                       for g in groups],
+            "graph_ms": round(t_graph * 1e3, 2), "serial_ms": round(t_ser * 1e3, 2),
+            "useful_mode_steps_per_s": useful / t_graph,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                           "p99": float(np.percentile(lat, 99))},
+            "max_rel_err_vs_serial": err, "convergence": "increment <= 1e-8 per instance"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +285,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernels"], default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
                          "device copy (for hardware-counter runs); prints no JSON line")
@@ -322,6 +437,10 @@ def main():
     if not args.no_learned:
         learned = learned_vs_plain(l1, torch, W, dev)
 
+    uneven = None
+    if not args.no_uneven:
+        uneven = uneven_batch(l1, torch, W, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -358,6 +477,7 @@ def main():
         "history_hbm": history,
         "gemm_assembly": gemm,
         "learned_vs_plain": learned,
+        "uneven_batch": uneven,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -96,6 +96,12 @@ typedef struct {
                               sine basis; the same quadrature sum, 2M+1 moments instead of
                               M^2 dot products), M <= 256; larger M uses 1
                            1: quadrature GEMM dphi^T diag(w D) dphi on FP64 MFMA */
+  int32_t tune;         /* GEMM variants of the fine and full-history steps (bit 0: 64 x 64
+                           tiles for the lagged-state product instead of 16 x 16 split-K
+                           tiles; bit 1: 16 x 16 split-K tiles for the projections instead of
+                           64 x 64); 0 is the default, l1pr_autotune measures the best.  The
+                           variants sum in different orders, so runs compared bit for bit
+                           must use the same value. */
 } l1pr_problem;
 
 /* Operation codes for l1pr_workspace_bytes. */
@@ -166,6 +172,56 @@ l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const d
                                    int32_t coarse, const void* mlp_params, double* U_iters,
                                    double* incr, int32_t* iters, void* ws, size_t ws_bytes,
                                    void* stream);
+/* Uneven batches (instances that differ in modes, fine steps per slice and order under one
+ * problem).  All arrays are device arrays of `batch` entries; any may be NULL.
+ *   modes : instance b's own modes M_b, 1 <= M_b <= p->modes (coefficients k >= M_b are
+ *           zero; u0 must be zero there).  Instances with roundup16(M_b) equal to
+ *           roundup16(p->modes) reproduce their own runs (modes = M_b, same quad) bit for bit.
+ *   spp   : instance b's own fine steps per slice S_b, 1 <= S_b <= p->steps / p->slices; its
+ *           fine grid has P S_b steps (dt = T / (P S_b)).
+ *   alpha : instance b's order (else p->alpha).
+ * Entries outside the ranges are clamped into them. */
+typedef struct {
+  const int32_t* modes;
+  const int32_t* spp;
+  const double* alpha;
+} l1pr_uneven;
+
+/* Serial (hybrid) solve of an uneven batch; the other arguments as in l1pr_solve_serial.
+ * Needs a 1D problem with history 0 and roundup16(M) <= 256.  Nothing is copied from the
+ * host, so the call can be captured into a HIP graph. */
+l1pr_status l1pr_solve_serial_uneven(const l1pr_problem* p, int32_t batch,
+                                     const l1pr_uneven* desc, const double* u0, double* U,
+                                     void* ws, size_t ws_bytes, void* stream);
+
+/* Parareal over an uneven batch with a fixed number of sweeps and no host synchronisation
+ * (the whole call can be captured into a HIP graph): the same algorithm as
+ * l1pr_solve_parareal with tol = 0.  Convergence is recorded on the device:
+ *   conv   : device int32 [batch] or NULL: the first sweep k (1-based) whose increment
+ *            max-relative ||U^k - U^(k-1)|| / ||U^k|| is <= conv_tol, -1 if none;
+ *   stamps : device int64 [sweeps + 1] or NULL: the device wall clock (constant rate, see
+ *            hipDeviceAttributeWallClockRate) at the end of the initial coarse sweep and of
+ *            each sweep;
+ *   incr   : device [batch][sweeps] or NULL: the increments. */
+l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
+                                       const l1pr_uneven* desc, const double* u0, double* U,
+                                       int32_t sweeps, double conv_tol, int32_t* conv,
+                                       int64_t* stamps, double* incr, void* ws, size_t ws_bytes,
+                                       void* stream);
+
+/* Rate of the device wall clock that l1pr_solve_parareal_uneven stamps, in kHz (-1 on
+ * error); for the current device. */
+int64_t     l1pr_wall_clock_khz(void);
+/* Writes the device wall clock to t (device int64) when the stream reaches this point. */
+l1pr_status l1pr_device_stamp(int64_t* t, void* stream);
+
+/* Measures the GEMM variants of a fine step of `batch` instances x P slices (the parareal
+ * fine sweep) and writes the fastest as tune bits (0 for problems without a choice).
+ * Needs a parareal workspace (ws_bytes >= l1pr_workspace_bytes(p, batch, L1PR_OP_PARAREAL));
+ * synchronises the stream. */
+l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t ws_bytes,
+                          void* stream, int32_t* tune_out);
+
 size_t l1pr_parareal_learned_extra_bytes(const l1pr_problem* p, int32_t batch);
 
 /* ---- Learned coarse propagator (configuration with a residual MLP) ----------------------

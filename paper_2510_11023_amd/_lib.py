@@ -33,7 +33,14 @@ class Problem(ctypes.Structure):
         ("history", ctypes.c_int32),
         ("source_time", ctypes.c_int32),
         ("assembly", ctypes.c_int32),
+        ("tune", ctypes.c_int32),
     ]
+
+
+class Uneven(ctypes.Structure):
+    """Mirror of l1pr_uneven (device pointers)."""
+
+    _fields_ = [("modes", ctypes.c_void_p), ("spp", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
 
 
 class KernelStat(ctypes.Structure):
@@ -111,6 +118,22 @@ def lib():
         L.l1pr_mlp_forward.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
                                        ctypes.c_size_t, vp]
         L.l1pr_mlp_forward.restype = ctypes.c_int
+        L.l1pr_solve_serial_uneven.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32,
+                                               ctypes.POINTER(Uneven), vp, vp, vp, ctypes.c_size_t,
+                                               vp]
+        L.l1pr_solve_serial_uneven.restype = ctypes.c_int
+        L.l1pr_solve_parareal_uneven.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32,
+                                                 ctypes.POINTER(Uneven), vp, vp, ctypes.c_int32,
+                                                 ctypes.c_double, vp, vp, vp, vp, ctypes.c_size_t,
+                                                 vp]
+        L.l1pr_solve_parareal_uneven.restype = ctypes.c_int
+        L.l1pr_device_stamp.argtypes = [vp, vp]
+        L.l1pr_device_stamp.restype = ctypes.c_int
+        L.l1pr_wall_clock_khz.argtypes = []
+        L.l1pr_wall_clock_khz.restype = ctypes.c_int64
+        L.l1pr_autotune.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, vp, ctypes.c_size_t,
+                                    vp, ctypes.POINTER(ctypes.c_int32)]
+        L.l1pr_autotune.restype = ctypes.c_int
         L.l1pr_mlp_infer.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
                                      ctypes.c_size_t, vp]
         L.l1pr_mlp_infer.restype = ctypes.c_int

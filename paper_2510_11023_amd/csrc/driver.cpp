@@ -56,6 +56,7 @@ bool valid(const l1pr_problem* p) {
   if (p->source_time != 0 && p->source_time != 1) return false;
   if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
   if (p->assembly != 0 && p->assembly != 1) return false;
+  if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY)) return false;
   return true;
 }
 
@@ -73,6 +74,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.d_sel = p->d_sel;
   tb.f_sel = p->f_sel;
   tb.source_time = p->source_time;
+  tb.tune = p->tune;
   tb.d_param = p->d_param;
   tb.T = p->T;
   const size_t D = sizeof(double);
@@ -125,8 +127,15 @@ struct Ctx {
     if ((expr) != hipSuccess) return L1PR_EHIP; \
   } while (0)
 
+// Per-instance inputs of an uneven batch (device arrays; any may be null).
+struct Uneven {
+  const double* alpha = nullptr;
+  const int32_t* modes = nullptr;
+  const int32_t* spp = nullptr;
+};
+
 l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, void* ws,
-                  size_t ws_bytes, void* stream, Ctx& c) {
+                  size_t ws_bytes, void* stream, Ctx& c, const Uneven& un = Uneven()) {
   if (!valid(p) || B < 1 || !ws) return L1PR_EINVAL;
   if (op == L1PR_OP_PARAREAL && p->history != 0) return L1PR_EINVAL;
   std::vector<double> al(B, p->alpha);
@@ -152,13 +161,16 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.cosq = c.ptr(c.L.cosq);
   c.reg = reg_path_ok(tb.Mp, tb.Qp);
   c.moments = c.reg && p->assembly == 0;
-  if (alpha)  // pageable source: the copy is staged before the call returns
+  const double* alpha_dev = c.ptr(c.L.alpha);
+  if (un.alpha)  // device array of the caller (nothing is copied, so the call can be captured)
+    alpha_dev = un.alpha;
+  else if (alpha)  // pageable source: the copy is staged before the call returns
     L1PR_TRY(hipMemcpyAsync(c.ptr(c.L.alpha), al.data(), sizeof(double) * B, hipMemcpyHostToDevice, c.s));
   else
     L1PR_TRY(launch_fill(c.ptr(c.L.alpha), B, p->alpha, c.s));
   L1PR_TRY(launch_tables(tb, c.ptr(c.L.xq), c.ptr(c.L.wq), c.ptr(c.L.phi), c.ptr(c.L.phiT),
                          c.ptr(c.L.dphi), c.ptr(c.L.inst), c.ptr(c.L.bw), c.ptr(c.L.bhyb),
-                         c.ptr(c.L.cosq), c.ptr(c.L.alpha), c.s));
+                         c.ptr(c.L.cosq), alpha_dev, un.modes, un.spp, c.s));
   return L1PR_OK;
 }
 
@@ -216,13 +228,14 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 //   device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
   if (c.reg) {
-    // GEMM variants: the lagged-state product always takes the skinny tiles (faster at every
-    // unit count measured); the projections take them for coarse steps only (one unit per
-    // instance) and the 64 x 64 tiles otherwise.  The choice never depends on the unit count
-    // of a fine or full-history step, so a serial solve and a parareal fine sweep do the same
-    // arithmetic.
-    const bool sk_proj = a.mode == MODE_COARSE;
-    L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, true, c.s); }));
+    // GEMM variants.  Coarse steps (one unit per instance) take the skinny tiles for both
+    // products.  Fine and full-history steps take the variants in the problem's tuning bits
+    // (default: skinny lagged-state product, 64 x 64 projections), never a choice made from
+    // the unit count, so a serial solve and a parareal fine sweep do the same arithmetic.
+    const bool coarse = a.mode == MODE_COARSE;
+    const bool sk_lag = coarse || !(c.tb.tune & TUNE_LAG_TILED);
+    const bool sk_proj = coarse || (c.tb.tune & TUNE_PROJ_SKINNY);
+    L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, sk_lag, c.s); }));
     L1PR_TRY(timed("proj", a, units, c.s, [&] {
       return launch_proj_gemm(c.tb, units, a.d, a.g, c.moments ? a.mom : nullptr, a.F, sk_proj, c.s);
     }));
@@ -272,8 +285,8 @@ l1pr_status serial_hybrid(const Ctx& c, const double* u0, double* U, double* tra
       a.trajP = 1;
       a.trajN0 = n;
       a.Z = Z;
-      Epilogue e{};
-      e.kind = (r == S) ? EPI_STORE2 : EPI_STORE;
+      Epilogue e{};  // the slice end is written at the instance's last step of the slice
+      e.kind = EPI_STORE2;
       e.out = traj + (long)r * Mp;
       e.out_stride = slotS;
       e.gold = Z + (long)(n + 1) * Mp;
@@ -367,18 +380,30 @@ l1pr_status fine_sweep(const Ctx& c, const double* Z) {
     a.trajP = P;
     a.trajN0 = 0;
     a.Z = Z;
-    Epilogue e{};
+    Epilogue e{};  // row r, and row S at the instance's last step of the slice
     e.kind = EPI_STORE;
     e.out = traj + (long)r * Mp;
     e.out_stride = slotS;
+    e.gold = traj + (long)S * Mp;
+    e.gold_stride = slotS;
     l1pr_status st = run_step(c, a, e, B * P);
     if (st != L1PR_OK) return st;
   }
   return L1PR_OK;
 }
 
+// Device-side convergence record: conv[b] = the first sweep whose increment is <= conv_tol
+// (-1 if none); stamps[k] = device wall clock at the end of sweep k (k = 0: initial coarse
+// sweep).  Both optional; neither needs the host, so the whole loop can be graph-captured.
+struct Track {
+  int32_t* conv = nullptr;
+  double conv_tol = 0.0;
+  int64_t* stamps = nullptr;
+};
+
 l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, double tol,
-                     double* U_iters, double* incr, int* iters_out, const Learned* lg) {
+                     double* U_iters, double* incr, int* iters_out, const Learned* lg,
+                     const Track& tr = Track()) {
   const Tables& tb = c.tb;
   const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp, M = tb.M;
   const long vecP = (long)(P + 1) * Mp, slotS = (long)(S + 1) * Mp;
@@ -389,6 +414,7 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   double* incrk = c.ptr(c.L.incrk);
   const long iterStride = (long)B * (P + 1) * M;
 
+  if (tr.conv) L1PR_TRY(launch_fill_int(tr.conv, B, -1, c.s));
   // coarse initial sweep: U^0_{n+1} = G_n(U^0_0..U^0_n), G_old(n) = the same value
   L1PR_TRY(launch_pack(u0, M, B, M, Zk, Mp, vecP, c.s));
   for (int n = 0; n < P; ++n) {
@@ -402,6 +428,7 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
     if (st != L1PR_OK) return st;
   }
   if (U_iters) L1PR_TRY(launch_unpack(Zk, Mp, vecP, U_iters, M, (long)(P + 1) * M, P + 1, B, c.s));
+  if (tr.stamps) L1PR_TRY(launch_stamp(tr.stamps, c.s));
 
   int done = 0;
   bool met = false;
@@ -424,7 +451,9 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
       l1pr_status st = coarse_step(c, Zk1, n, e, lg);
       if (st != L1PR_OK) return st;
     }
-    L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, c.s));
+    L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, tr.conv,
+                              tr.conv_tol, c.s));
+    if (tr.stamps) L1PR_TRY(launch_stamp(tr.stamps + k + 1, c.s));
     if (U_iters)
       L1PR_TRY(launch_unpack(Zk1, Mp, vecP, U_iters + (long)(k + 1) * iterStride, M,
                              (long)(P + 1) * M, P + 1, B, c.s));
@@ -529,6 +558,116 @@ l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const doub
                                 U_iters, incr, iters, ws, ws_bytes, stream);
 }
 
+l1pr_status l1pr_solve_serial_uneven(const l1pr_problem* p, int32_t batch,
+                                     const l1pr_uneven* desc, const double* u0, double* U,
+                                     void* ws, size_t ws_bytes, void* stream) {
+  try {
+    if (!p || !desc || !u0 || !U || p->history != 0 || p->dim != 1) return L1PR_EINVAL;
+    Uneven un;
+    un.alpha = desc->alpha;
+    un.modes = desc->modes;
+    un.spp = desc->spp;
+    Ctx c;
+    l1pr_status st = setup(p, batch, L1PR_OP_SERIAL, nullptr, ws, ws_bytes, stream, c, un);
+    if (st != L1PR_OK) return st;
+    if (!c.reg) return L1PR_EINVAL;
+    return serial_hybrid(c, u0, U, nullptr);
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
+l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
+                                       const l1pr_uneven* desc, const double* u0, double* U,
+                                       int32_t sweeps, double conv_tol, int32_t* conv,
+                                       int64_t* stamps, double* incr, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  try {
+    if (!p || !desc || !u0 || !U || p->history != 0 || p->dim != 1) return L1PR_EINVAL;
+    if (sweeps < 0 || sweeps > p->slices || !(conv_tol >= 0.0)) return L1PR_EINVAL;
+    Uneven un;
+    un.alpha = desc->alpha;
+    un.modes = desc->modes;
+    un.spp = desc->spp;
+    Ctx c;
+    l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c, un);
+    if (st != L1PR_OK) return st;
+    if (!c.reg) return L1PR_EINVAL;
+    Track tr;
+    tr.conv = conv;
+    tr.conv_tol = conv_tol;
+    tr.stamps = stamps;
+    int it = 0;
+    return parareal(c, u0, U, sweeps, 0.0, nullptr, incr, &it, nullptr, tr);
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
+l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t ws_bytes,
+                          void* stream, int32_t* tune_out) {
+  try {
+    if (!p || !tune_out) return L1PR_EINVAL;
+    l1pr_problem q = *p;
+    q.tune = 0;
+    Ctx c;
+    l1pr_status st = setup(&q, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c);
+    if (st != L1PR_OK) return st;
+    if (!c.reg || q.history != 0) {
+      *tune_out = 0;
+      return L1PR_OK;
+    }
+    const Tables& tb = c.tb;
+    const long vecP = (long)(tb.P + 1) * tb.Mp;
+    double* Z = c.ptr(c.L.Z0);
+    L1PR_TRY(launch_fill(Z, (long)tb.B * vecP, 0.0, c.s));
+    L1PR_TRY(launch_fill_slot0(tb, Z, c.ptr(c.L.traj), tb.B, tb.P, c.s));
+    hipEvent_t e0, e1;
+    L1PR_TRY(hipEventCreate(&e0));
+    L1PR_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int32_t best_t = 0;
+    for (int32_t t = 0; t <= (TUNE_LAG_TILED | TUNE_PROJ_SKINNY); ++t) {
+      c.tb.tune = t;
+      StepArgs a = base_args(c);
+      a.mode = MODE_FINE;
+      a.r = 1;
+      a.nP = tb.P;
+      a.traj = c.ptr(c.L.traj);
+      a.trajP = tb.P;
+      a.Z = Z;
+      Epilogue e{};
+      e.kind = EPI_STORE;
+      e.out = c.ptr(c.L.traj) + tb.Mp;  // row 1 of every slot
+      e.out_stride = (long)(tb.S + 1) * tb.Mp;
+      // the lagged-state product and the projections are what the bits change; time them
+      // over a few launches after one warm-up
+      float ms = 0.f;
+      for (int rep = 0; rep < 4; ++rep) {
+        if (rep == 1) L1PR_TRY(hipEventRecord(e0, c.s));
+        const bool sk_lag = !(t & TUNE_LAG_TILED), sk_proj = (t & TUNE_PROJ_SKINNY) != 0;
+        L1PR_TRY(launch_lag_gemm(c.tb, a, tb.B * tb.P, a.d, a.g, sk_lag, c.s));
+        L1PR_TRY(launch_proj_gemm(c.tb, tb.B * tb.P, a.d, a.g, c.moments ? a.mom : nullptr, a.F,
+                                  sk_proj, c.s));
+      }
+      L1PR_TRY(hipEventRecord(e1, c.s));
+      L1PR_TRY(hipEventSynchronize(e1));
+      L1PR_TRY(hipEventElapsedTime(&ms, e0, e1));
+      (void)e;
+      if (ms < best) {
+        best = ms;
+        best_t = t;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *tune_out = best_t;
+    return L1PR_OK;
+  } catch (...) {
+    return L1PR_EHIP;
+  }
+}
+
 size_t l1pr_parareal_learned_extra_bytes(const l1pr_problem* p, int32_t batch) {
   if (!valid(p) || batch < 1 || p->modes > kMlpMaxModes) return 0;
   Layout L;
@@ -626,6 +765,18 @@ int32_t l1pr_profile_stop(l1pr_kernel_stat* out, int32_t max_out) {
     ++n;
   }
   return n;
+}
+
+l1pr_status l1pr_device_stamp(int64_t* t, void* stream) {
+  if (!t) return L1PR_EINVAL;
+  return launch_stamp(t, static_cast<hipStream_t>(stream)) == hipSuccess ? L1PR_OK : L1PR_EHIP;
+}
+
+int64_t l1pr_wall_clock_khz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return -1;
+  return khz;
 }
 
 const char* l1pr_status_string(l1pr_status s) {

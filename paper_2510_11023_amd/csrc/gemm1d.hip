@@ -90,8 +90,8 @@ __global__ __launch_bounds__(256) void k_lag_gemm1d(Tables tb, StepArgs a, int u
       if (u >= units) continue;
       const UnitView v = decode_unit(tb, a, u);
       const double* ins = tb.inst + (long)v.b * NSCAL;
-      const double tD = t_level(tb, v.m_prev);
-      const double tf = tb.source_time ? t_level(tb, v.m_src) : tD;
+      const double tD = t_level(tb, v.m_prev, v.Nb);
+      const double tf = tb.source_time ? t_level(tb, v.m_src, v.Nb) : tD;
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) {
         const int q = n0 + wj * 32 + bj * 16 + (lane & 15);
@@ -242,8 +242,8 @@ __global__ __launch_bounds__(256) void k_lag_skinny1d(Tables tb, StepArgs a, int
   if (u >= units || q >= tb.Qp) return;
   const UnitView v = decode_unit(tb, a, u);
   const double* ins = tb.inst + (long)v.b * NSCAL;
-  const double tD = t_level(tb, v.m_prev);
-  const double tf = tb.source_time ? t_level(tb, v.m_src) : tD;
+  const double tD = t_level(tb, v.m_prev, v.Nb);
+  const double tf = tb.source_time ? t_level(tb, v.m_src, v.Nb) : tD;
   const double w = tb.wq[q];
   dq[(long)u * tb.Qp + q] = w * coef_D(tb.d_sel, tb.d_param, uq);
   gq[(long)u * tb.Qp + q] = w * coef_f(tb, ins, tb.xq[q], 0.0, tf, uq);

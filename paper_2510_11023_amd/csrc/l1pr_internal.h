@@ -21,8 +21,14 @@ namespace l1pr {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// per-instance scalar slots
-enum { IS_ALPHA = 0, IS_TAU, IS_TAUC, IS_SFAC, IS_G1A, IS_G3A, NSCAL = 8 };
+// per-instance scalar slots; IS_MB and IS_SB hold the instance's own number of modes and of
+// fine steps per slice (integers stored exactly as doubles; equal to M and S unless the batch
+// is uneven)
+enum { IS_ALPHA = 0, IS_TAU, IS_TAUC, IS_SFAC, IS_G1A, IS_G3A, IS_MB, IS_SB, NSCAL = 8 };
+
+// tuning bits (l1pr_problem.tune): GEMM variant of the lagged-state product and of the
+// projections in fine and full-history steps
+enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2 };
 
 // kinds of step
 enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
@@ -31,8 +37,8 @@ enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
 enum { EPI_STORE = 0, EPI_STORE2 = 1, EPI_CORRECT = 2 };
 
 struct Tables {
-  int dim, M, Q, Mp, Qp, N, P, S, B, LB;
-  int d_sel, f_sel, source_time;
+  int dim, M, Q, Mp, Qp, N, P, S, B, LB;  // S, N: the largest steps per slice and steps
+  int d_sel, f_sel, source_time, tune;
   double d_param, T;
   const double* xq;
   const double* wq;
@@ -135,8 +141,8 @@ __device__ inline double coef_f(const Tables& tb, const double* inst, double x, 
   return 0.0;
 }
 
-// fine time level t_m = T m / N
-__device__ inline double t_level(const Tables& tb, long m) { return (tb.T * (double)m) / (double)tb.N; }
+// fine time level t_m = T m / N (N: the instance's number of fine steps)
+__device__ inline double t_level(const Tables& tb, long m, double N) { return (tb.T * (double)m) / N; }
 
 // Where a unit's data lives and which time level / step size it uses.
 struct UnitView {
@@ -149,6 +155,8 @@ struct UnitView {
   long m_src;        // fine index of the new time level (source_time = 1)
   int tau_slot;      // IS_TAU or IS_TAUC
   long slot;         // trajectory slot (MODE_FINE)
+  int Sb;            // the instance's fine steps per slice
+  double Nb;         // the instance's fine steps, P Sb
 };
 
 __device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int u) {
@@ -156,28 +164,34 @@ __device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int 
   const long vecP = (long)(tb.P + 1) * tb.Mp;
   if (a.mode == MODE_FINE) {
     v.b = u / a.nP;
+    v.Sb = (int)tb.inst[(long)v.b * NSCAL + IS_SB];
+    v.Nb = (double)tb.P * (double)v.Sb;
     v.n = a.n_lo + u % a.nP;
     v.slot = (long)v.b * a.trajP + (v.n - a.trajN0);
     v.y = a.traj + v.slot * (long)(tb.S + 1) * tb.Mp;
     v.L = a.r - 1;
     v.z = a.Z + v.b * vecP;
     v.nz = v.n;
-    v.m_prev = (long)v.n * tb.S + a.r - 1;
+    v.m_prev = (long)v.n * v.Sb + a.r - 1;
     v.m_src = v.m_prev + 1;
     v.tau_slot = IS_TAU;
   } else if (a.mode == MODE_COARSE) {
     v.b = u;
+    v.Sb = (int)tb.inst[(long)v.b * NSCAL + IS_SB];
+    v.Nb = (double)tb.P * (double)v.Sb;
     v.n = a.n;
     v.slot = u;
     v.y = a.Z + v.b * vecP;
     v.L = a.n;
     v.z = nullptr;
     v.nz = 0;
-    v.m_prev = (long)a.n * tb.S;
-    v.m_src = (long)(a.n + 1) * tb.S;
+    v.m_prev = (long)a.n * v.Sb;
+    v.m_src = (long)(a.n + 1) * v.Sb;
     v.tau_slot = IS_TAUC;
   } else {
     v.b = u;
+    v.Sb = tb.S;
+    v.Nb = (double)tb.N;
     v.n = 0;
     v.slot = u;
     v.y = a.traj + (long)v.b * (tb.N + 1) * tb.Mp;
@@ -191,10 +205,28 @@ __device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int 
   return v;
 }
 
+// Where the new value x of entry k of unit u goes.  Fine steps: the trajectory row `out` at
+// every step of the unit and, at the instance's last step of the slice (r == Sb), the slice
+// end `gold` as well when it is set.  Other steps: by kind (STORE, STORE2 = also gold,
+// CORRECT = the parareal update F_old + (x - G_old), then G_old = x).
+__device__ inline void epi_store(const StepArgs& a, const Epilogue& ep, int u, long slot,
+                                 bool last_fine, int k, double x) {
+  if (ep.kind == EPI_CORRECT) {
+    const double go = ep.gold[(long)u * ep.gold_stride + k];
+    ep.out[(long)u * ep.out_stride + k] = ep.fold[(long)u * ep.fold_stride + k] + (x - go);
+    ep.gold[(long)u * ep.gold_stride + k] = x;
+    return;
+  }
+  ep.out[slot * ep.out_stride + k] = x;
+  const bool g = (a.mode == MODE_FINE) ? last_fine : (ep.kind == EPI_STORE2);
+  if (g && ep.gold) ep.gold[(long)u * ep.gold_stride + k] = x;
+}
+
 // ---- launchers (implemented in the .hip files) ----
 hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
                          double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
-                         const double* alpha_dev, hipStream_t s);
+                         const double* alpha_dev, const int32_t* Mb, const int32_t* Sb,
+                         hipStream_t s);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
@@ -226,6 +258,8 @@ hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* 
                              long dst_stride, int rows_per_unit, int units, hipStream_t s);
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
-                            hipStream_t s);
+                            int32_t* conv, double conv_tol, hipStream_t s);
+hipError_t launch_fill_int(int32_t* x, int n, int32_t v, hipStream_t s);
+hipError_t launch_stamp(int64_t* t, hipStream_t s);
 
 }  // namespace l1pr

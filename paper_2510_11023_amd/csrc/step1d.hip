@@ -27,8 +27,8 @@ __global__ __launch_bounds__(256) void k_eval1d(Tables tb, StepArgs a) {
   double* sg = sm + Mp;  // w_q f_q       [Qp]
   const UnitView v = decode_unit(tb, a, u);
   const double* ins = tb.inst + (long)v.b * NSCAL;
-  const double tD = t_level(tb, v.m_prev);
-  const double tf = tb.source_time ? t_level(tb, v.m_src) : tD;
+  const double tD = t_level(tb, v.m_prev, v.Nb);
+  const double tf = tb.source_time ? t_level(tb, v.m_src, v.Nb) : tD;
 
   for (int k = tid; k < Mp; k += blockDim.x) sc[k] = v.y[(long)v.L * Mp + k];
   __syncthreads();
@@ -153,6 +153,10 @@ __global__ __launch_bounds__(256) void k_solve1d(Tables tb, StepArgs a, Epilogue
   double* sP = sL + 16 * 17;     // panel           [Mp][17]
   double* sred = sP + Mp * 17;   // partial sums    [256]
 
+  if (a.mode == MODE_FINE) {  // past the instance's last step of the slice: nothing to do
+    const int b = u / a.nP;
+    if (a.r > (int)tb.inst[(long)b * NSCAL + IS_SB]) return;
+  }
   for (int k = tid; k < Mp; k += blockDim.x) sb[k] = a.rhs[(long)u * Mp + k];
   __syncthreads();
 
@@ -270,22 +274,9 @@ __global__ __launch_bounds__(256) void k_solve1d(Tables tb, StepArgs a, Epilogue
   }
 
   // epilogue
-  long slot = u;
-  if (a.mode == MODE_FINE) {
-    const int b = u / a.nP, n = a.n_lo + u % a.nP;
-    slot = (long)b * a.trajP + (n - a.trajN0);
-  }
-  for (int k = tid; k < Mp; k += blockDim.x) {
-    const double x = sb[k];
-    if (ep.kind == EPI_CORRECT) {
-      const double go = ep.gold[(long)u * ep.gold_stride + k];
-      ep.out[(long)u * ep.out_stride + k] = ep.fold[(long)u * ep.fold_stride + k] + (x - go);
-      ep.gold[(long)u * ep.gold_stride + k] = x;
-    } else {
-      ep.out[slot * ep.out_stride + k] = x;
-      if (ep.kind == EPI_STORE2) ep.gold[(long)u * ep.gold_stride + k] = x;
-    }
-  }
+  const UnitView v = decode_unit(tb, a, u);
+  const bool last = (a.mode == MODE_FINE) && (a.r == v.Sb);
+  for (int k = tid; k < Mp; k += blockDim.x) epi_store(a, ep, u, v.slot, last, k, sb[k]);
 }
 
 // ------------------------------------------------------------------------ launchers
@@ -409,7 +400,7 @@ hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* 
 // reduction (one work-group per instance).
 __global__ __launch_bounds__(256) void k_increment(const double* Znew, const double* Zold, int rows,
                                                    int Mp, double* incr_out, int incr_stride, int k,
-                                                   double* incr_k) {
+                                                   double* incr_k, int32_t* conv, double conv_tol) {
   __shared__ double sd[256], su[256];
   const int b = blockIdx.x, tid = threadIdx.x;
   const long per = (long)rows * Mp;
@@ -435,13 +426,35 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
     const double rel = su[0] > 0.0 ? sqrt(sd[0]) / sqrt(su[0]) : sqrt(sd[0]);
     if (incr_out) incr_out[(long)b * incr_stride + k] = rel;
     incr_k[b] = rel;
+    if (conv && conv[b] < 0 && rel <= conv_tol) conv[b] = k + 1;
   }
 }
 
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
-                            hipStream_t s) {
-  k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k);
+                            int32_t* conv, double conv_tol, hipStream_t s) {
+  k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k, conv,
+                                conv_tol);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(int32_t* x, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+hipError_t launch_fill_int(int32_t* x, int n, int32_t v, hipStream_t s) {
+  if (n > 0) k_fill_int<<<(n + 255) / 256, 256, 0, s>>>(x, n, v);
+  return hipGetLastError();
+}
+
+// the device's constant-rate wall clock, written by one thread (a vector store)
+__global__ void k_stamp(int64_t* t) {
+  if (threadIdx.x == 0) t[0] = (int64_t)wall_clock64();
+}
+
+hipError_t launch_stamp(int64_t* t, hipStream_t s) {
+  k_stamp<<<1, 64, 0, s>>>(t);
   return hipGetLastError();
 }
 

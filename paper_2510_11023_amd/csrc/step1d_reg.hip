@@ -227,7 +227,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   // wave index as a scalar: tile ownership and every per-slot branch stay on the scalar unit
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int Mp = tb.Mp, M = tb.M, nt = Mp / 16;
+  const int Mp = tb.Mp, nt = Mp / 16;
   const RegLds LO = reg_lds(Mp);
   double* sb = lds + LO.sb;
   double* sWA = lds + LO.sWA;
@@ -236,9 +236,14 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   const int lr = lane >> 4, lc = lane & 15;
 
   const int b = (a.mode == MODE_FINE) ? u / a.nP : u;
-  const double tau = tb.inst[(long)b * NSCAL + ((a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU)];
+  const double* ins = tb.inst + (long)b * NSCAL;
+  // past the instance's last fine step of the slice (uneven batches): nothing to do
+  if (a.mode == MODE_FINE && a.r > (int)ins[IS_SB]) return;
+  // the instance's own modes: entries k >= Mb are identity rows with zero right-hand side
+  const int Mb = (int)ins[IS_MB];
+  const double tau = ins[(a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU];
   for (int k = tid; k < Mp; k += RT)
-    sb[k] = hist[(long)u * Mp + k] + tau * F[(long)u * Mp + k];
+    sb[k] = (k < Mb) ? hist[(long)u * Mp + k] + tau * F[(long)u * Mp + k] : 0.0;
 
   // slot (I, K) element v of lane l holds A[16 I + l%16][16 K + l/16 + 4v]
   if (SRC == SRC_MOMENTS) {
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       for (int e = 0; e < 4; ++e) {
         const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
         double val = (k == l) ? 1.0 : 0.0;
-        if (k < M && l < M) {
+        if (k < Mb && l < Mb) {
           const int dkl = k > l ? k - l : l - k;
           const double Kkl = ((double)(k + 1) * (double)(l + 1)) * pi2 * (sm[dkl] + sm[k + l + 2]);
           val += tau * Kkl;
@@ -273,8 +278,10 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       slot_tile(s, wave, nt, tI, tK);
       if (tI < 0) continue;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        acc[s][e] = A[(long)(tI * 16 + lc) * Mp + tK * 16 + lr + 4 * e];
+      for (int e = 0; e < 4; ++e) {
+        const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
+        acc[s][e] = (k < Mb && l < Mb) ? A[(long)k * Mp + l] : ((k == l) ? 1.0 : 0.0);
+      }
     }
   }
 
@@ -469,22 +476,9 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   __syncthreads();
 
   // --------------------------------------------------------------- epilogue
-  long slot = u;
-  if (a.mode == MODE_FINE) {
-    const int b = u / a.nP, n = a.n_lo + u % a.nP;
-    slot = (long)b * a.trajP + (n - a.trajN0);
-  }
-  for (int k = tid; k < Mp; k += RT) {
-    const double x = sb[k];
-    if (ep.kind == EPI_CORRECT) {
-      const double go = ep.gold[(long)u * ep.gold_stride + k];
-      ep.out[(long)u * ep.out_stride + k] = ep.fold[(long)u * ep.fold_stride + k] + (x - go);
-      ep.gold[(long)u * ep.gold_stride + k] = x;
-    } else {
-      ep.out[slot * ep.out_stride + k] = x;
-      if (ep.kind == EPI_STORE2) ep.gold[(long)u * ep.gold_stride + k] = x;
-    }
-  }
+  const UnitView v = decode_unit(tb, a, u);
+  const bool last = (a.mode == MODE_FINE) && (a.r == v.Sb);
+  for (int k = tid; k < Mp; k += RT) epi_store(a, ep, u, v.slot, last, k, sb[k]);
 }
 
 bool reg_path_ok(int Mp, int Qp) {

@@ -70,21 +70,26 @@ __global__ void k_cosq(int Q, int Qp, int Jp, const double* xq, double* cosq) {
   cosq[idx] = (q < Q) ? cos((j * kPi) * xq[q]) : 0.0;
 }
 
-__global__ void k_inst_scalars(int B, int N, int P, int S, double T, const double* alpha,
-                               double* inst) {
+// Per-instance scalars.  Mb, Sb (nullable): the instance's own modes and fine steps per
+// slice in an uneven batch (entries outside 1..M, 1..S are clamped); its number of fine
+// steps is P Sb.
+__global__ void k_inst_scalars(int B, int M, int P, int S, double T, const double* alpha,
+                               const int32_t* Mb, const int32_t* Sb, double* inst) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const double a = alpha[b];
+  const int m = Mb ? min(max(Mb[b], 1), M) : M;
+  const int sb = Sb ? min(max(Sb[b], 1), S) : S;
   const double g2 = tgamma(2.0 - a);
   double* o = inst + (long)b * NSCAL;
   o[IS_ALPHA] = a;
-  o[IS_TAU] = pow(T / (double)N, a) * g2;
+  o[IS_TAU] = pow(T / (double)((long)P * sb), a) * g2;
   o[IS_TAUC] = pow(T / (double)P, a) * g2;
-  o[IS_SFAC] = pow((double)S, -a);
+  o[IS_SFAC] = pow((double)sb, -a);
   o[IS_G1A] = tgamma(1.0 + a);
   o[IS_G3A] = tgamma(3.0 - a);
-  o[6] = 0.0;
-  o[7] = 0.0;
+  o[IS_MB] = (double)m;
+  o[IS_SB] = (double)sb;
 }
 
 // bw[b][j] = b_j for j < LB
@@ -95,15 +100,22 @@ __global__ void k_weights(int B, int LB, const double* alpha, double* bw) {
   bw[idx] = l1_weight((double)j, alpha[b]);
 }
 
-// bhyb[b][m*S + r-1] = b_{m + r/S}, m < P, 1 <= r <= S, with m + r/S formed as (m S + r)/S.
-__global__ void k_hybrid_weights(int B, int P, int S, const double* alpha, double* bhyb) {
+// bhyb[b][m*S + r-1] = b_{m + r/Sb}, m < P, 1 <= r <= Sb (the instance's own steps per
+// slice, from inst), with m + r/Sb formed as (m Sb + r)/Sb; entries r > Sb are unused (0).
+__global__ void k_hybrid_weights(int B, int P, int S, const double* alpha, const double* inst,
+                                 double* bhyb) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long per = (long)P * S;
   if (idx >= (long)B * per) return;
   const int b = (int)(idx / per);
   const long rem = idx % per;
   const int m = (int)(rem / S), r = (int)(rem % S) + 1;
-  const double x = (double)((long)m * S + r) / (double)S;
+  const int sb = (int)inst[(long)b * NSCAL + IS_SB];
+  if (r > sb) {
+    bhyb[idx] = 0.0;
+    return;
+  }
+  const double x = (double)((long)m * sb + r) / (double)sb;
   bhyb[idx] = l1_weight(x, alpha[b]);
 }
 
@@ -119,7 +131,8 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t s) {
 
 hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
                          double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
-                         const double* alpha_dev, hipStream_t s) {
+                         const double* alpha_dev, const int32_t* Mb, const int32_t* Sb,
+                         hipStream_t s) {
   const int T = 256;
   k_gauss_legendre<<<(tb.Qp + T - 1) / T, T, 0, s>>>(tb.Q, tb.Qp, xq, wq);
   const long nb = (long)tb.Qp * tb.Mp;
@@ -128,12 +141,12 @@ hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, 
     const long nc = (long)tb.Qp * (2 * tb.Mp + 1);
     k_cosq<<<(unsigned)((nc + T - 1) / T), T, 0, s>>>(tb.Q, tb.Qp, 2 * tb.Mp + 1, xq, cosq);
   }
-  k_inst_scalars<<<(tb.B + T - 1) / T, T, 0, s>>>(tb.B, tb.N, tb.P, tb.S, tb.T, alpha_dev, inst);
+  k_inst_scalars<<<(tb.B + T - 1) / T, T, 0, s>>>(tb.B, tb.M, tb.P, tb.S, tb.T, alpha_dev, Mb, Sb, inst);
   const long nw = (long)tb.B * tb.LB;
   k_weights<<<(unsigned)((nw + T - 1) / T), T, 0, s>>>(tb.B, tb.LB, alpha_dev, bw);
   const long nh = (long)tb.B * tb.P * tb.S;
   if (bhyb && nh > 0)
-    k_hybrid_weights<<<(unsigned)((nh + T - 1) / T), T, 0, s>>>(tb.B, tb.P, tb.S, alpha_dev, bhyb);
+    k_hybrid_weights<<<(unsigned)((nh + T - 1) / T), T, 0, s>>>(tb.B, tb.P, tb.S, alpha_dev, inst, bhyb);
   return hipGetLastError();
 }
 

@@ -19,9 +19,9 @@ ASSEMBLY_GEMM = 1      # stiffness as the quadrature GEMM dphi^T diag(w D) dphi 
 
 def make_problem(dim=1, modes=32, quad=64, steps=256, slices=8, alpha=0.5, T=1.0, d_sel=0,
                  d_param=1.0, f_sel=0, history=0, source_time=0,
-                 assembly=ASSEMBLY_MOMENTS) -> Problem:
+                 assembly=ASSEMBLY_MOMENTS, tune=0) -> Problem:
     return Problem(dim, modes, quad, steps, slices, alpha, T, d_sel, d_param, f_sel, history,
-                   source_time, assembly)
+                   source_time, assembly, tune)
 
 
 def nmodes(p: Problem) -> int:
@@ -158,3 +158,85 @@ def solve_parareal(p: Problem, u0: torch.Tensor, max_iter: int, tol: float = 0.0
     return PararealResult(U=U, iters=k, status=st,
                           incr=None if incr is None else incr[:, :k],
                           iterates=None if its is None else its[: k + 1])
+
+
+# ---------------------------------------------------------------- uneven batches
+
+def _uneven(modes, spp, alpha):
+    """Descriptor and the device tensors it points to (kept alive by the caller)."""
+    keep = []
+
+    def dev(x, dtype):
+        if x is None:
+            return None
+        t = x if isinstance(x, torch.Tensor) else torch.tensor(list(x), dtype=dtype)
+        t = t.to(device="cuda", dtype=dtype).contiguous()
+        keep.append(t)
+        return ctypes.c_void_p(t.data_ptr())
+
+    d = _lib.Uneven(dev(modes, torch.int32), dev(spp, torch.int32), dev(alpha, torch.float64))
+    return d, keep
+
+
+def solve_serial_uneven(p: Problem, u0: torch.Tensor, modes=None, spp=None, alpha=None,
+                        workspace=None):
+    """Serial (hybrid) solve of an uneven batch: per-instance modes M_b, fine steps per slice
+    S_b and order (device arrays or sequences).  Returns U [B][P+1][M]."""
+    _check_u0(p, u0)
+    B = u0.shape[0]
+    ws = workspace if workspace is not None else _workspace(p, B, _lib.OP_SERIAL, u0.device)[0]
+    U = torch.empty((B, p.slices + 1, nmodes(p)), dtype=torch.float64, device=u0.device)
+    d, keep = _uneven(modes, spp, alpha)
+    st = _lib.lib().l1pr_solve_serial_uneven(ctypes.byref(p), B, ctypes.byref(d), _ptr(u0), _ptr(U),
+                                             _ptr(ws), ws.numel(), _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_solve_serial_uneven")
+    del keep
+    return U
+
+
+def solve_parareal_uneven(p: Problem, u0: torch.Tensor, sweeps: int, modes=None, spp=None,
+                          alpha=None, conv_tol: float = 0.0, workspace=None, out=None,
+                          conv=None, stamps=None, incr=None):
+    """Parareal over an uneven batch with `sweeps` sweeps and no host synchronisation.
+    Returns (U, conv, stamps): conv[b] = first sweep whose increment is <= conv_tol (-1 if
+    none), stamps[k] = device wall clock at the end of sweep k (k = 0: initial coarse sweep)."""
+    _check_u0(p, u0)
+    B = u0.shape[0]
+    dev = u0.device
+    ws = workspace if workspace is not None else _workspace(p, B, _lib.OP_PARAREAL, dev)[0]
+    U = out if out is not None else torch.empty((B, p.slices + 1, nmodes(p)), dtype=torch.float64,
+                                                device=dev)
+    conv = conv if conv is not None else torch.empty(B, dtype=torch.int32, device=dev)
+    stamps = stamps if stamps is not None else torch.zeros(sweeps + 1, dtype=torch.int64, device=dev)
+    d, keep = _uneven(modes, spp, alpha)
+    st = _lib.lib().l1pr_solve_parareal_uneven(ctypes.byref(p), B, ctypes.byref(d), _ptr(u0),
+                                               _ptr(U), sweeps, float(conv_tol), _ptr(conv),
+                                               _ptr(stamps), _ptr(incr), _ptr(ws), ws.numel(),
+                                               _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_solve_parareal_uneven")
+    del keep
+    return U, conv, stamps
+
+
+def autotune(p: Problem, batch: int, workspace=None) -> int:
+    """Fastest GEMM variant bits for the fine sweep of `batch` instances (see l1pr_problem.tune)."""
+    ws = workspace if workspace is not None else _workspace(p, batch, _lib.OP_PARAREAL, "cuda")[0]
+    out = ctypes.c_int32(0)
+    st = _lib.lib().l1pr_autotune(ctypes.byref(p), batch, _ptr(ws), ws.numel(), _stream(),
+                                  ctypes.byref(out))
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_autotune")
+    return int(out.value)
+
+
+def device_stamp(t: torch.Tensor):
+    """Device wall clock into t[0] (int64) when the current stream reaches this point."""
+    st = _lib.lib().l1pr_device_stamp(_ptr(t), _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_device_stamp")
+
+
+def wall_clock_khz() -> int:
+    return int(_lib.lib().l1pr_wall_clock_khz())

@@ -35,6 +35,26 @@ C4_TRAIN_ALPHA_SEED = 4242
 C4_EVAL_ALPHA_SEED = 2424
 
 
+# config 5: uneven batch of 256 instances, P = 64 slices, each with its own modes
+# M ~ U{64..256}, fine steps per slice S ~ U{8..64} (N = 64 S) and alpha ~ U(0.2, 1);
+# D = 1 + sin^2(u)/2 and the manufactured source of config 1 (with the instance's alpha),
+# u0 = sin(pi x).  Instances are grouped by padded mode count roundup16(M); a group uses
+# Q = 2 roundup16(M) Gauss points.
+C5 = dict(dim=1, slices=64, alpha=0.5, T=1.0, d_sel=1, d_param=1.0, f_sel=1, history=0,
+          source_time=0)
+C5_COUNT = 256
+C5_SEED = 5
+
+
+def c5_instances(count: int = C5_COUNT, seed: int = C5_SEED):
+    """(modes, steps per slice, alpha) arrays of the uneven batch."""
+    rng = np.random.default_rng(seed)
+    modes = rng.integers(64, 257, size=count)
+    spp = rng.integers(8, 65, size=count)
+    alpha = rng.uniform(0.2, 1.0, size=count)
+    return modes, spp, alpha
+
+
 def with_(base: dict, **kw) -> dict:
     d = dict(base)
     d.update(kw)
