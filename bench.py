@@ -62,9 +62,9 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "6a1c276b0eee114a02ebf4f02f97d07cb5195deef956fb1ca1af70ebcd5c3158",
-                  "fetch_kib": 8678, "write_kib": 10452, "fetch_factor": 2.0, "write_factor": 1.0,
-                  "bytes_per_launch": (2 * 8678 + 10452) * 1024}
+TRAFFIC_RECORD = {"sha256": "4f4096f4255a90b4249030619771481a205f009aeca64c2447c199ff9e58f76d",
+                  "fetch_kib": 8759, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+                  "bytes_per_launch": (2 * 8759 + 4096) * 1024}
 
 
 def log(msg):
