@@ -32,7 +32,7 @@ constexpr int kMaxMp1D = 400;
 struct Layout {
   size_t total = 0;
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
-  size_t g, mom, F;
+  size_t g, mom, F, C2, T2;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -43,9 +43,11 @@ size_t take(size_t& cur, size_t bytes) {
 
 bool valid(const l1pr_problem* p) {
   if (!p) return false;
-  if (p->dim != 1) return false;  // the GPU path covers 1D
+  if (p->dim != 1 && p->dim != 2) return false;
   if (p->modes < 1 || p->quad < p->modes) return false;
-  if (roundup(p->modes, 16) > kMaxMp1D) return false;
+  if (p->dim == 1 && roundup(p->modes, 16) > kMaxMp1D) return false;
+  if (p->dim == 2 && (p->modes > 64 || roundup(p->modes * p->modes, 16) > kMaxMp1D)) return false;
+  if (p->dim == 2 && p->assembly != 0) return false;  // 2D forms the stiffness from moments
   if (p->steps < 1 || p->slices < 1 || p->steps % p->slices != 0) return false;
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return false;
   if (!(p->T > 0.0) || !std::isfinite(p->T)) return false;
@@ -62,9 +64,11 @@ bool valid(const l1pr_problem* p) {
 
 void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.dim = p->dim;
-  tb.M = p->modes;
+  tb.M1 = p->modes;
+  tb.M1p = roundup(p->modes, 16);
+  tb.M = p->dim == 1 ? p->modes : p->modes * p->modes;
   tb.Q = p->quad;
-  tb.Mp = roundup(p->modes, 16);
+  tb.Mp = roundup(tb.M, 16);
   tb.Qp = roundup(p->quad, 16);
   tb.N = p->steps;
   tb.P = p->slices;
@@ -78,14 +82,16 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.d_param = p->d_param;
   tb.T = p->T;
   const size_t D = sizeof(double);
-  const size_t Mp = tb.Mp, Qp = tb.Qp, P = tb.P, S = tb.S, N = tb.N;
+  const size_t Mp = tb.Mp, Qp = tb.Qp, P = tb.P, S = tb.S, N = tb.N, M1p = tb.M1p;
+  const size_t Jp = 2 * M1p + 1;
+  const bool two = p->dim == 2;
   size_t cur = 0;
   L.xq = take(cur, D * Qp);
   L.wq = take(cur, D * Qp);
-  L.phi = take(cur, D * Qp * Mp);
-  L.phiT = take(cur, D * Qp * Mp);
-  L.dphi = take(cur, D * Qp * Mp);
-  L.cosq = take(cur, D * Qp * (2 * Mp + 1));
+  L.phi = take(cur, D * Qp * M1p);
+  L.phiT = take(cur, D * Qp * M1p);
+  L.dphi = take(cur, D * Qp * M1p);
+  L.cosq = take(cur, D * Qp * Jp);
   L.inst = take(cur, D * B * NSCAL);
   L.bw = take(cur, D * B * tb.LB);
   L.bhyb = take(cur, D * B * P * S);
@@ -102,12 +108,15 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
     units = B;
     L.traj = take(cur, D * B * ((p->history == 1 ? N : S) + 1) * Mp);
   }
-  L.d = take(cur, D * units * Qp);
+  const size_t nq = two ? Qp * Qp : Qp;  // quadrature points per unit
+  L.d = take(cur, D * units * nq);
   L.rhs = take(cur, D * units * Mp);
   L.A = take(cur, D * units * Mp * Mp);
-  L.g = take(cur, D * units * Qp);
-  L.mom = take(cur, D * units * (2 * Mp + 1));
+  L.g = take(cur, D * units * nq);
+  L.mom = take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
   L.F = take(cur, D * units * Mp);
+  L.C2 = two ? take(cur, D * units * Mp) : 0;
+  L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
   L.incrk = take(cur, D * B);
   L.total = cur;
 }
@@ -160,7 +169,7 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.bhyb = c.ptr(c.L.bhyb);
   tb.cosq = c.ptr(c.L.cosq);
   c.reg = reg_path_ok(tb.Mp, tb.Qp);
-  c.moments = c.reg && p->assembly == 0;
+  c.moments = c.reg && p->assembly == 0 && p->dim == 1;
   const double* alpha_dev = c.ptr(c.L.alpha);
   if (un.alpha)  // device array of the caller (nothing is copied, so the call can be captured)
     alpha_dev = un.alpha;
@@ -227,6 +236,24 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 // Mp > 256: evaluation, quadrature-GEMM assembly and the blocked factorisation through
 //   device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
+  if (c.tb.dim == 2) {
+    // separable products (lagged state at the Gauss points, D, f, load vector, cosine
+    // moments), the system from the moments, the history sums, then the factorisation
+    L1PR_TRY(timed("products2d", a, units, c.s, [&] {
+      return launch_step2d_products(c.tb, a, units, a.C2, a.T2, a.mom, c.s);
+    }));
+    L1PR_TRY(timed("assemble2d", a, units, c.s, [&] { return launch_assemble2d(c.tb, a, units, a.mom, c.s); }));
+    L1PR_TRY(timed("history", a, units, c.s, [&] { return launch_history(c.tb, a, units, a.rhs, c.s); }));
+    if (c.reg) {
+      L1PR_TRY(timed("chol", a, units, c.s, [&] {
+        return launch_chol_reg(c.tb, a, e, units, nullptr, a.F, a.rhs, c.s);
+      }));
+    } else {
+      L1PR_TRY(timed("rhs", a, units, c.s, [&] { return launch_form_rhs(c.tb, a, units, c.s); }));
+      L1PR_TRY(timed("solve", a, units, c.s, [&] { return launch_solve(c.tb, a, e, units, c.s); }));
+    }
+    return L1PR_OK;
+  }
   if (c.reg) {
     // GEMM variants.  Coarse steps (one unit per instance) take the skinny tiles for both
     // products.  Fine and full-history steps take the variants in the problem's tuning bits
@@ -262,6 +289,8 @@ StepArgs base_args(const Ctx& c) {
   a.g = c.ptr(c.L.g);
   a.mom = c.ptr(c.L.mom);
   a.F = c.ptr(c.L.F);
+  a.C2 = c.L.C2 ? c.ptr(c.L.C2) : nullptr;
+  a.T2 = c.L.T2 ? c.ptr(c.L.T2) : nullptr;
   return a;
 }
 
@@ -613,7 +642,7 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
     Ctx c;
     l1pr_status st = setup(&q, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
-    if (!c.reg || q.history != 0) {
+    if (!c.reg || q.history != 0 || q.dim != 1) {  // no variants to choose between
       *tune_out = 0;
       return L1PR_OK;
     }

@@ -37,7 +37,9 @@ enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
 enum { EPI_STORE = 0, EPI_STORE2 = 1, EPI_CORRECT = 2 };
 
 struct Tables {
-  int dim, M, Q, Mp, Qp, N, P, S, B, LB;  // S, N: the largest steps per slice and steps
+  // M, Mp: coefficients per instance (M^2 in 2D) and their padded count; M1, M1p: modes per
+  // direction (the basis tables' width); Q, Qp: Gauss points per direction
+  int dim, M, Q, Mp, Qp, M1, M1p, N, P, S, B, LB;  // S, N: the largest steps per slice and steps
   int d_sel, f_sel, source_time, tune;
   double d_param, T;
   const double* xq;
@@ -61,12 +63,14 @@ struct StepArgs {
   double* traj; // MODE_FINE: slots [B*trajP][S+1][Mp]; MODE_FULL: [B][N+1][Mp]
   int trajP, trajN0;
   const double* Z;  // slice-end sequence [B][P+1][Mp]
-  double* d;        // [units][Qp]   w_q D_q
+  double* d;        // [units][Qp]   w_q D_q   (2D: [units][Qp][Qp])
   double* rhs;      // [units][Mp]   right-hand side (history sums on the batched path)
   double* A;        // [units][Mp][Mp]
   double* g;        // [units][Qp]   w_q f_q
-  double* mom;      // [units][2 Mp + 1] cosine moments
+  double* mom;      // [units][2 Mp + 1] cosine moments (2D: [units][Jp][Jp], Jp = 2 M1p + 1)
   double* F;        // [units][Mp]   load vector
+  double* C2;       // 2D: [units][Mp] lagged states
+  double* T2;       // 2D: [units][Qp Jp] intermediate products
 };
 
 struct Epilogue {
@@ -175,32 +179,23 @@ __device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int 
     v.m_prev = (long)v.n * v.Sb + a.r - 1;
     v.m_src = v.m_prev + 1;
     v.tau_slot = IS_TAU;
-  } else if (a.mode == MODE_COARSE) {
-    v.b = u;
-    v.Sb = (int)tb.inst[(long)v.b * NSCAL + IS_SB];
-    v.Nb = (double)tb.P * (double)v.Sb;
-    v.n = a.n;
-    v.slot = u;
-    v.y = a.Z + v.b * vecP;
-    v.L = a.n;
-    v.z = nullptr;
-    v.nz = 0;
-    v.m_prev = (long)a.n * v.Sb;
-    v.m_src = (long)(a.n + 1) * v.Sb;
-    v.tau_slot = IS_TAUC;
   } else {
+    // coarse steps (one unit per instance, on the slice-end sequence) and full-history
+    // steps (one unit per instance, on the whole fine trajectory) differ only in these
+    // selects; one branch keeps the mode test from splitting into a switch
+    const bool coarse = a.mode == MODE_COARSE;
     v.b = u;
-    v.Sb = tb.S;
-    v.Nb = (double)tb.N;
-    v.n = 0;
+    v.Sb = coarse ? (int)tb.inst[(long)v.b * NSCAL + IS_SB] : tb.S;
+    v.Nb = coarse ? (double)tb.P * (double)v.Sb : (double)tb.N;
+    v.n = coarse ? a.n : 0;
     v.slot = u;
-    v.y = a.traj + (long)v.b * (tb.N + 1) * tb.Mp;
-    v.L = a.m;
+    v.y = coarse ? a.Z + v.b * vecP : a.traj + (long)v.b * (tb.N + 1) * tb.Mp;
+    v.L = coarse ? a.n : a.m;
     v.z = nullptr;
     v.nz = 0;
-    v.m_prev = a.m;
-    v.m_src = a.m + 1;
-    v.tau_slot = IS_TAU;
+    v.m_prev = coarse ? (long)a.n * v.Sb : (long)a.m;
+    v.m_src = coarse ? (long)(a.n + 1) * v.Sb : (long)a.m + 1;
+    v.tau_slot = coarse ? IS_TAUC : IS_TAU;
   }
   return v;
 }
@@ -227,6 +222,12 @@ hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, 
                          double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
                          const double* alpha_dev, const int32_t* Mb, const int32_t* Sb,
                          hipStream_t s);
+// 2D steps (gemm2d.hip)
+hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units, double* Cbuf,
+                                  double* T, double* mom, hipStream_t s);
+hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, const double* mom,
+                             hipStream_t s);
+hipError_t launch_form_rhs(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);

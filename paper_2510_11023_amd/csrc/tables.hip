@@ -135,11 +135,12 @@ hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, 
                          hipStream_t s) {
   const int T = 256;
   k_gauss_legendre<<<(tb.Qp + T - 1) / T, T, 0, s>>>(tb.Q, tb.Qp, xq, wq);
-  const long nb = (long)tb.Qp * tb.Mp;
-  k_basis<<<(unsigned)((nb + T - 1) / T), T, 0, s>>>(tb.M, tb.Q, tb.Mp, tb.Qp, xq, phi, phiT, dphi);
+  // basis tables per direction: M1 modes padded to M1p (M1 = M in 1D)
+  const long nb = (long)tb.Qp * tb.M1p;
+  k_basis<<<(unsigned)((nb + T - 1) / T), T, 0, s>>>(tb.M1, tb.Q, tb.M1p, tb.Qp, xq, phi, phiT, dphi);
   if (cosq) {
-    const long nc = (long)tb.Qp * (2 * tb.Mp + 1);
-    k_cosq<<<(unsigned)((nc + T - 1) / T), T, 0, s>>>(tb.Q, tb.Qp, 2 * tb.Mp + 1, xq, cosq);
+    const long nc = (long)tb.Qp * (2 * tb.M1p + 1);
+    k_cosq<<<(unsigned)((nc + T - 1) / T), T, 0, s>>>(tb.Q, tb.Qp, 2 * tb.M1p + 1, xq, cosq);
   }
   k_inst_scalars<<<(tb.B + T - 1) / T, T, 0, s>>>(tb.B, tb.M, tb.P, tb.S, tb.T, alpha_dev, Mb, Sb, inst);
   const long nw = (long)tb.B * tb.LB;

@@ -159,6 +159,41 @@ def test_nonlinear_assembly_vs_adaptive_integration(orc, d_sel, f_sel):
     assert np.allclose(K, K.T, rtol=0, atol=1e-12)
 
 
+def test_nonlinear_assembly_2d_vs_adaptive_integration(orc):
+    """2D: K_kl = int int D(u) grad phi_k . grad phi_l and F_k = int int f(u) phi_k with the
+    tensor basis phi_(k1 k2) = 2 sin(k1 pi x) sin(k2 pi y), against scipy's adaptive 2D
+    integrator (D = 1 + exp(-u^2)/2, f = sin u, the configuration-3 coefficients)."""
+    M = 2
+    p = orc.problem(dim=2, modes=M, quad=40, d_sel=3, f_sel=3)
+    c = np.array([0.3, -0.15, 0.1, 0.05])  # k = k1 M + k2
+    t = 0.25
+    s2, pi = math.sqrt(2), math.pi
+
+    def phi(k, x, y):
+        k1, k2 = divmod(k, M)
+        return 2 * math.sin((k1 + 1) * pi * x) * math.sin((k2 + 1) * pi * y)
+
+    def grad(k, x, y):
+        k1, k2 = divmod(k, M)
+        a1, a2 = (k1 + 1) * pi, (k2 + 1) * pi
+        return (2 * a1 * math.cos(a1 * x) * math.sin(a2 * y), 2 * a2 * math.sin(a1 * x) * math.cos(a2 * y))
+
+    def u(x, y):
+        return sum(c[k] * phi(k, x, y) for k in range(M * M))
+
+    K, F = orc.galerkin(p, c, t, t)
+    opts = dict(epsabs=1e-12, epsrel=1e-12)
+    for k in (0, 1, 3):
+        Fk = si.dblquad(lambda y, x: math.sin(u(x, y)) * phi(k, x, y), 0, 1, 0, 1, **opts)[0]
+        assert abs(F[k] - Fk) < 1e-10, (k, F[k], Fk)
+        for l in (0, 2, 3):
+            def integrand(y, x):
+                gk, gl = grad(k, x, y), grad(l, x, y)
+                return (1 + 0.5 * math.exp(-u(x, y) ** 2)) * (gk[0] * gl[0] + gk[1] * gl[1])
+            Kkl = si.dblquad(integrand, 0, 1, 0, 1, **opts)[0]
+            assert abs(K[k, l] - Kkl) < 1e-9 * max(1.0, abs(Kkl)), (k, l, K[k, l], Kkl)
+
+
 def test_step_system_is_spd(orc):
     """I + tau K is symmetric positive definite (Section 2.1: the system is uniquely
     solvable)."""
