@@ -77,7 +77,9 @@ enum { L1PR_F_ZERO = 0,
 
 typedef struct {
   int32_t dim;          /* 1 or 2 */
-  int32_t modes;        /* M per direction, >= 1 */
+  int32_t modes;        /* M per direction, >= 1; at most 1024 in 1D and 64 in 2D (M^2
+                           coefficients; more than 256 go through the device-memory
+                           factorisation) */
   int32_t quad;         /* Q per direction, >= M */
   int32_t steps;        /* N fine steps, N % P == 0 */
   int32_t slices;       /* P parareal slices (coarse steps) */
@@ -96,12 +98,14 @@ typedef struct {
                               sine basis; the same quadrature sum, 2M+1 moments instead of
                               M^2 dot products), M <= 256; larger M uses 1
                            1: quadrature GEMM dphi^T diag(w D) dphi on FP64 MFMA */
-  int32_t tune;         /* GEMM variants of the fine and full-history steps (bit 0: 64 x 64
-                           tiles for the lagged-state product instead of 16 x 16 split-K
-                           tiles; bit 1: 16 x 16 split-K tiles for the projections instead of
-                           64 x 64); 0 is the default, l1pr_autotune measures the best.  The
-                           variants sum in different orders, so runs compared bit for bit
-                           must use the same value. */
+  int32_t tune;         /* variants of the fine and full-history steps (bit 0: 64 x 64 tiles
+                           for the lagged-state product instead of 16 x 16 split-K tiles;
+                           bit 1: 16 x 16 split-K tiles for the projections instead of 64 x 64;
+                           bit 2: 128-column blocks instead of 256 in the device-memory
+                           factorisation of systems with more than 256 coefficients); 0 is
+                           the default, l1pr_autotune measures the best.  The variants sum in
+                           different orders, so runs compared bit for bit must use the same
+                           value. */
 } l1pr_problem;
 
 /* Operation codes for l1pr_workspace_bytes. */

@@ -23,16 +23,15 @@
 
 namespace l1pr {
 
-size_t solve_lds_bytes(int Mp);
-
 namespace {
 
-constexpr int kMaxMp1D = 400;
+constexpr int kMaxModes1D = 1024;  // the 1D evaluation kernel stages Mp + Qp doubles in LDS
+constexpr int kMaxModes2D = 64;
 
 struct Layout {
   size_t total = 0;
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
-  size_t g, mom, F, C2, T2;
+  size_t g, mom, F, C2, T2, q;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -45,8 +44,9 @@ bool valid(const l1pr_problem* p) {
   if (!p) return false;
   if (p->dim != 1 && p->dim != 2) return false;
   if (p->modes < 1 || p->quad < p->modes) return false;
-  if (p->dim == 1 && roundup(p->modes, 16) > kMaxMp1D) return false;
-  if (p->dim == 2 && (p->modes > 64 || roundup(p->modes * p->modes, 16) > kMaxMp1D)) return false;
+  if (p->dim == 1 && (p->modes > kMaxModes1D || roundup(p->modes, 16) + roundup(p->quad, 16) > 8192))
+    return false;
+  if (p->dim == 2 && p->modes > kMaxModes2D) return false;
   if (p->dim == 2 && p->assembly != 0) return false;  // 2D forms the stiffness from moments
   if (p->steps < 1 || p->slices < 1 || p->steps % p->slices != 0) return false;
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return false;
@@ -58,7 +58,7 @@ bool valid(const l1pr_problem* p) {
   if (p->source_time != 0 && p->source_time != 1) return false;
   if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
   if (p->assembly != 0 && p->assembly != 1) return false;
-  if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY)) return false;
+  if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY | TUNE_NB128)) return false;
   return true;
 }
 
@@ -79,6 +79,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.f_sel = p->f_sel;
   tb.source_time = p->source_time;
   tb.tune = p->tune;
+  tb.nb = (p->tune & TUNE_NB128) ? 128 : 256;
   tb.d_param = p->d_param;
   tb.T = p->T;
   const size_t D = sizeof(double);
@@ -117,6 +118,9 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.F = take(cur, D * units * Mp);
   L.C2 = two ? take(cur, D * units * Mp) : 0;
   L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
+  // back-substitution partial sums of the device-memory factorisation
+  const size_t nblk = (Mp + tb.nb - 1) / tb.nb;
+  L.q = reg_path_ok(tb.Mp, tb.Qp) ? 0 : take(cur, D * units * nblk * tb.nb);
   L.incrk = take(cur, D * B);
   L.total = cur;
 }
@@ -233,8 +237,8 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 //   and for the moments and load vector, a streaming kernel for the history sums, then the
 //   register-resident factorisation and solve (stiffness from the moments, or from the
 //   quadrature-GEMM assembly kernel when assembly = 1).
-// Mp > 256: evaluation, quadrature-GEMM assembly and the blocked factorisation through
-//   device memory.
+// Mp > 256: evaluation (1D) or the separable products (2D), the assembly, and the blocked
+//   factorisation through device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
   if (c.tb.dim == 2) {
     // separable products (lagged state at the Gauss points, D, f, load vector, cosine
@@ -250,7 +254,9 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
       }));
     } else {
       L1PR_TRY(timed("rhs", a, units, c.s, [&] { return launch_form_rhs(c.tb, a, units, c.s); }));
-      L1PR_TRY(timed("solve", a, units, c.s, [&] { return launch_solve(c.tb, a, e, units, c.s); }));
+      L1PR_TRY(timed("blk_solve", a, units, c.s, [&] {
+        return launch_blk_solve(c.tb, a, e, units, c.ptr(c.L.q), c.s);
+      }));
     }
     return L1PR_OK;
   }
@@ -276,7 +282,9 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
   }
   L1PR_TRY(timed("eval", a, units, c.s, [&] { return launch_eval(c.tb, a, units, c.s); }));
   L1PR_TRY(timed("assemble", a, units, c.s, [&] { return launch_assemble(c.tb, a, units, c.s); }));
-  L1PR_TRY(timed("solve", a, units, c.s, [&] { return launch_solve(c.tb, a, e, units, c.s); }));
+  L1PR_TRY(timed("blk_solve", a, units, c.s, [&] {
+    return launch_blk_solve(c.tb, a, e, units, c.ptr(c.L.q), c.s);
+  }));
   return L1PR_OK;
 }
 

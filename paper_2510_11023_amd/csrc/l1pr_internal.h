@@ -28,7 +28,7 @@ enum { IS_ALPHA = 0, IS_TAU, IS_TAUC, IS_SFAC, IS_G1A, IS_G3A, IS_MB, IS_SB, NSC
 
 // tuning bits (l1pr_problem.tune): GEMM variant of the lagged-state product and of the
 // projections in fine and full-history steps
-enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2 };
+enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2, TUNE_NB128 = 4 };
 
 // kinds of step
 enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
@@ -41,6 +41,7 @@ struct Tables {
   // direction (the basis tables' width); Q, Qp: Gauss points per direction
   int dim, M, Q, Mp, Qp, M1, M1p, N, P, S, B, LB;  // S, N: the largest steps per slice and steps
   int d_sel, f_sel, source_time, tune;
+  int nb;  // column block of the device-memory factorisation (Mp > 256)
   double d_param, T;
   const double* xq;
   const double* wq;
@@ -231,8 +232,12 @@ hipError_t launch_form_rhs(const Tables& tb, const StepArgs& a, int units, hipSt
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
-hipError_t launch_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
-                        hipStream_t s);
+// blocked factorisation and solve through device memory (chol_blk.hip): A and rhs of the
+// step arguments are overwritten; q is scratch of units * ceil(Mp / nb) * nb doubles
+hipError_t launch_blk_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                            double* q, hipStream_t s);
+hipError_t launch_blk_diag(const Tables& tb, const StepArgs& a, int units, double* A, double* rhs,
+                           int r0, int w, hipStream_t s);
 bool reg_path_ok(int Mp, int Qp);
 // skinny: 16 x 16 tiles with a split reduction (few units) instead of 64 x 64 tiles.  Both
 // give every output as a fixed-order sum over its own row, but the two orders differ, so

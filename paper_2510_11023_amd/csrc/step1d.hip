@@ -2,14 +2,14 @@
 //
 // A "unit" is one system to solve at this step: an (instance, slice) pair of the fine
 // sweep, an instance of the coarse sweep, or an instance of the full-history sweep.
-// Each step is three launches over all units:
+// For systems too large for the register-resident kernel (Mp > 256) a step is:
 //   k_eval1d     u_q = sum_k phi_k(x_q) c_k at the lagged state, d_q = w_q D(x_q,t,u_q),
 //                g_q = w_q f(x_q,t,u_q), the load F = phi^T g, the L1 history sums and the
 //                right-hand side rhs = hist + tau F            (Sections 2.1 and 2.2)
 //   k_assemble1d A = I + tau dphi^T diag(d) dphi, lower tiles only, FP64 MFMA 16x16x4
-//   k_solve1d    A = L L^T (blocked right-looking Cholesky, MFMA trailing updates),
-//                forward and backward substitution, then the epilogue that stores the new
-//                state (or applies the parareal correction F_old + (G_new - G_old)).
+// then the blocked factorisation and solve through device memory (chol_blk.hip), whose
+// epilogue stores the new state (or applies the parareal correction F_old + (G_new - G_old)).
+// This file also holds the small packing, copy and bookkeeping kernels.
 // The arithmetic of a unit never depends on the other units of the launch, so a unit's
 // result is bit-for-bit the same in a serial sweep and in a parareal sweep.
 #include "l1pr_internal.h"
@@ -134,151 +134,6 @@ __global__ __launch_bounds__(256) void k_assemble1d(Tables tb, StepArgs a) {
       }
 }
 
-// ----------------------------------------------------------------------------- solve
-// One work-group (4 waves) per unit.  Right-looking Cholesky by 16-column blocks:
-//   (1) wave 0 factors the 16x16 diagonal block in registers (one row per lane, values
-//       exchanged by shuffles) and solves its part of L y = rhs;
-//   (2) every thread takes one row of the panel below it: L_ij = A_ij L_jj^-T, and updates
-//       its entry of the right-hand side;
-//   (3) the trailing lower tiles are updated, A_IK -= L_Ij L_Kj^T, by MFMA 16x16x4 with the
-//       panel staged in LDS.
-// Then L^T x = y by 16-row blocks.  The lower triangle of A is overwritten by L.
-__global__ __launch_bounds__(256) void k_solve1d(Tables tb, StepArgs a, Epilogue ep) {
-  extern __shared__ double sm[];
-  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int Mp = tb.Mp, nt = Mp / 16;
-  double* A = a.A + (long)u * Mp * Mp;
-  double* sb = sm;               // rhs -> y -> x   [Mp]
-  double* sL = sb + Mp;          // diagonal block  [16][17]
-  double* sP = sL + 16 * 17;     // panel           [Mp][17]
-  double* sred = sP + Mp * 17;   // partial sums    [256]
-
-  if (a.mode == MODE_FINE) {  // past the instance's last step of the slice: nothing to do
-    const int b = u / a.nP;
-    if (a.r > (int)tb.inst[(long)b * NSCAL + IS_SB]) return;
-  }
-  for (int k = tid; k < Mp; k += blockDim.x) sb[k] = a.rhs[(long)u * Mp + k];
-  __syncthreads();
-
-  for (int j = 0; j < nt; ++j) {
-    const int j0 = 16 * j;
-    if (wave == 0) {
-      const int r = lane & 15;
-      double v[16];
-#pragma unroll
-      for (int s = 0; s < 16; ++s) v[s] = (s <= r) ? A[(long)(j0 + r) * Mp + j0 + s] : 0.0;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const double dcc = __shfl(v[c], c, 16);
-        const double dd = sqrt(dcc);
-        const double inv = 1.0 / dd;
-        if (r == c) v[c] = dd;
-        else if (r > c) v[c] = v[c] * inv;
-#pragma unroll
-        for (int s = c + 1; s < 16; ++s) {
-          const double lsc = __shfl(v[c], s, 16);
-          if (r >= s) v[s] -= v[c] * lsc;
-        }
-      }
-      // y_j = L_jj^{-1} b_j
-      double yv = sb[j0 + r];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const double yc = __shfl(yv / v[c], c, 16);
-        if (r == c) yv = yc;
-        else if (r > c) yv -= v[c] * yc;
-      }
-      if (lane < 16) {
-        sb[j0 + r] = yv;
-#pragma unroll
-        for (int s = 0; s < 16; ++s) sL[r * 17 + s] = (s <= r) ? v[s] : 0.0;
-#pragma unroll
-        for (int s = 0; s < 16; ++s)
-          if (s <= r) A[(long)(j0 + r) * Mp + j0 + s] = v[s];
-      }
-    }
-    __syncthreads();
-
-    const int rows = Mp - j0 - 16;
-    for (int t = tid; t < rows; t += blockDim.x) {
-      const int i = j0 + 16 + t;
-      double x[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) x[c] = A[(long)i * Mp + j0 + c];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double s = x[c];
-#pragma unroll
-        for (int p = 0; p < c; ++p) s -= x[p] * sL[c * 17 + p];
-        x[c] = s / sL[c * 17 + c];
-      }
-      double bi = sb[i];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        A[(long)i * Mp + j0 + c] = x[c];
-        sP[t * 17 + c] = x[c];
-        bi -= x[c] * sb[j0 + c];
-      }
-      sb[i] = bi;
-    }
-    __syncthreads();
-
-    const int ntr = nt - j - 1;
-    const int ntiles = ntr * (ntr + 1) / 2;
-    for (int tt = wave; tt < ntiles; tt += 4) {
-      int I = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-      while ((I + 1) * (I + 2) / 2 <= tt) ++I;
-      while (I * (I + 1) / 2 > tt) --I;
-      const int K = tt - I * (I + 1) / 2;
-      const int gi = (j + 1 + I) * 16, gk = (j + 1 + K) * 16;
-      d4 acc;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[e] = A[(long)(gi + (lane >> 4) + 4 * e) * Mp + gk + (lane & 15)];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int kc = 4 * kk + (lane >> 4);
-        const double aop = -sP[(I * 16 + (lane & 15)) * 17 + kc];
-        const double bop = sP[(K * 16 + (lane & 15)) * 17 + kc];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) A[(long)(gi + (lane >> 4) + 4 * e) * Mp + gk + (lane & 15)] = acc[e];
-    }
-    __syncthreads();
-  }
-
-  // L^T x = y, last block first
-  for (int j = nt - 1; j >= 0; --j) {
-    const int j0 = 16 * j;
-    {
-      const int c = tid & 15, part = tid >> 4;
-      double acc = 0.0;
-      for (int i = j0 + 16 + part; i < Mp; i += 16) acc += A[(long)i * Mp + j0 + c] * sb[i];
-      sred[part * 16 + c] = acc;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const int r = lane & 15;
-      double s = sb[j0 + r];
-      for (int p = 0; p < 16; ++p) s -= sred[p * 16 + r];
-#pragma unroll
-      for (int cc = 15; cc >= 0; --cc) {
-        const double lcc = A[(long)(j0 + cc) * Mp + j0 + cc];
-        const double xc = __shfl(s / lcc, cc, 16);
-        if (r == cc) s = xc;
-        else if (r < cc) s -= A[(long)(j0 + cc) * Mp + j0 + r] * xc;
-      }
-      if (lane < 16) sb[j0 + r] = s;
-    }
-    __syncthreads();
-  }
-
-  // epilogue
-  const UnitView v = decode_unit(tb, a, u);
-  const bool last = (a.mode == MODE_FINE) && (a.r == v.Sb);
-  for (int k = tid; k < Mp; k += blockDim.x) epi_store(a, ep, u, v.slot, last, k, sb[k]);
-}
-
 // ------------------------------------------------------------------------ launchers
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s) {
   const size_t lds = sizeof(double) * (tb.Mp + tb.Qp);
@@ -293,14 +148,6 @@ hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipSt
   if (TB == 64) k_assemble1d<64><<<grid, 256, 0, s>>>(tb, a);
   else if (TB == 32) k_assemble1d<32><<<grid, 256, 0, s>>>(tb, a);
   else k_assemble1d<16><<<grid, 64, 0, s>>>(tb, a);
-  return hipGetLastError();
-}
-
-size_t solve_lds_bytes(int Mp) { return sizeof(double) * (Mp + 16 * 17 + (size_t)Mp * 17 + 256); }
-
-hipError_t launch_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
-                        hipStream_t s) {
-  k_solve1d<<<units, 256, solve_lds_bytes(tb.Mp), s>>>(tb, a, e);
   return hipGetLastError();
 }
 

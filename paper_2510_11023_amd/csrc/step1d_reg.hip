@@ -219,72 +219,15 @@ struct DiagFactor {
   BETWEEN(11) DF.step<12>(lane); BETWEEN(12) DF.step<13>(lane); BETWEEN(13)                \
   DF.step<14>(lane); BETWEEN(14) DF.step<15>(lane); BETWEEN(15)
 
-template <int SRC>
-__global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue ep,
-                                                 const double* mom, const double* F,
-                                                 const double* hist) {
-  extern __shared__ double lds[];
-  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-  // wave index as a scalar: tile ownership and every per-slot branch stay on the scalar unit
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int Mp = tb.Mp, nt = Mp / 16;
-  const RegLds LO = reg_lds(Mp);
-  double* sb = lds + LO.sb;
-  double* sWA = lds + LO.sWA;
-  double* sP = lds + LO.big;
-  d4 acc[RNS];
-  const int lr = lane >> 4, lc = lane & 15;
-
-  const int b = (a.mode == MODE_FINE) ? u / a.nP : u;
-  const double* ins = tb.inst + (long)b * NSCAL;
-  // past the instance's last fine step of the slice (uneven batches): nothing to do
-  if (a.mode == MODE_FINE && a.r > (int)ins[IS_SB]) return;
-  // the instance's own modes: entries k >= Mb are identity rows with zero right-hand side
-  const int Mb = (int)ins[IS_MB];
-  const double tau = ins[(a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU];
-  for (int k = tid; k < Mp; k += RT)
-    sb[k] = (k < Mb) ? hist[(long)u * Mp + k] + tau * F[(long)u * Mp + k] : 0.0;
-
-  // slot (I, K) element v of lane l holds A[16 I + l%16][16 K + l/16 + 4v]
-  if (SRC == SRC_MOMENTS) {
-    const int Jm = 2 * Mp + 1;
-    double* sm = sP;
-    for (int j = tid; j < Jm; j += RT) sm[j] = mom[(long)u * Jm + j];
-    __syncthreads();
-    const double pi2 = kPi * kPi;
-#pragma unroll
-    for (int s = 0; s < RNS; ++s) {
-      int tI, tK;
-      slot_tile(s, wave, nt, tI, tK);
-      if (tI < 0) continue;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
-        double val = (k == l) ? 1.0 : 0.0;
-        if (k < Mb && l < Mb) {
-          const int dkl = k > l ? k - l : l - k;
-          const double Kkl = ((double)(k + 1) * (double)(l + 1)) * pi2 * (sm[dkl] + sm[k + l + 2]);
-          val += tau * Kkl;
-        }
-        acc[s][e] = val;
-      }
-    }
-    __syncthreads();  // the moments share LDS with the panel
-  } else {
-    const double* A = a.A + (long)u * Mp * Mp;
-#pragma unroll
-    for (int s = 0; s < RNS; ++s) {
-      int tI, tK;
-      slot_tile(s, wave, nt, tI, tK);
-      if (tI < 0) continue;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
-        acc[s][e] = (k < Mb && l < Mb) ? A[(long)k * Mp + l] : ((k == l) ? 1.0 : 0.0);
-      }
-    }
-  }
-
+// Right-looking Cholesky of the nt x nt tile lower triangle that the waves hold in `acc`
+// (transposed tiles, slot ownership as in slot_tile), with the forward substitution of the
+// right-hand side sb[0, Mp) alongside; ends with every slot back in the accumulator layout of
+// the untransposed tile: L_IK off the diagonal, L_jj^-1 on it, and y = L^-1 b in sb.
+__device__ __attribute__((always_inline)) inline void factor_tiles(d4 (&acc)[RNS], double* sb,
+                                                                   double* sWA, double* sP,
+                                                                   int nt, int Mp, int wave,
+                                                                   int tid) {
+  const int lane = tid & 63, lr = lane >> 4, lc = lane & 15;
   // ------------------------------------------------------------ factorisation
   {
     int wd, sdg;
@@ -387,8 +330,6 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
 
   // ---- every slot back to the accumulator layout of the untransposed tile: L_IK off the
   // diagonal, X_j = W_j^T = L_jj^-1 on it; per-wave scratch in the panel space
-  int* tok = reinterpret_cast<int*>(lds + LO.prog);
-  if (tid < 16) tok[tid] = 0;
   {
     double* scr = sP + wave * (16 * 17);
 #pragma unroll
@@ -406,6 +347,78 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       SLOT_FENCE();
     }
   }
+  __syncthreads();
+}
+
+template <int SRC>
+__global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue ep,
+                                                 const double* mom, const double* F,
+                                                 const double* hist) {
+  extern __shared__ double lds[];
+  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar: tile ownership and every per-slot branch stay on the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Mp = tb.Mp, nt = Mp / 16;
+  const RegLds LO = reg_lds(Mp);
+  double* sb = lds + LO.sb;
+  double* sWA = lds + LO.sWA;
+  double* sP = lds + LO.big;
+  d4 acc[RNS];
+  const int lr = lane >> 4, lc = lane & 15;
+
+  const int b = (a.mode == MODE_FINE) ? u / a.nP : u;
+  const double* ins = tb.inst + (long)b * NSCAL;
+  // past the instance's last fine step of the slice (uneven batches): nothing to do
+  if (a.mode == MODE_FINE && a.r > (int)ins[IS_SB]) return;
+  // the instance's own modes: entries k >= Mb are identity rows with zero right-hand side
+  const int Mb = (int)ins[IS_MB];
+  const double tau = ins[(a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU];
+  for (int k = tid; k < Mp; k += RT)
+    sb[k] = (k < Mb) ? hist[(long)u * Mp + k] + tau * F[(long)u * Mp + k] : 0.0;
+
+  // slot (I, K) element v of lane l holds A[16 I + l%16][16 K + l/16 + 4v]
+  if (SRC == SRC_MOMENTS) {
+    const int Jm = 2 * Mp + 1;
+    double* sm = sP;
+    for (int j = tid; j < Jm; j += RT) sm[j] = mom[(long)u * Jm + j];
+    __syncthreads();
+    const double pi2 = kPi * kPi;
+#pragma unroll
+    for (int s = 0; s < RNS; ++s) {
+      int tI, tK;
+      slot_tile(s, wave, nt, tI, tK);
+      if (tI < 0) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
+        double val = (k == l) ? 1.0 : 0.0;
+        if (k < Mb && l < Mb) {
+          const int dkl = k > l ? k - l : l - k;
+          const double Kkl = ((double)(k + 1) * (double)(l + 1)) * pi2 * (sm[dkl] + sm[k + l + 2]);
+          val += tau * Kkl;
+        }
+        acc[s][e] = val;
+      }
+    }
+    __syncthreads();  // the moments share LDS with the panel
+  } else {
+    const double* A = a.A + (long)u * Mp * Mp;
+#pragma unroll
+    for (int s = 0; s < RNS; ++s) {
+      int tI, tK;
+      slot_tile(s, wave, nt, tI, tK);
+      if (tI < 0) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
+        acc[s][e] = (k < Mb && l < Mb) ? A[(long)k * Mp + l] : ((k == l) ? 1.0 : 0.0);
+      }
+    }
+  }
+
+  factor_tiles(acc, sb, sWA, sP, nt, Mp, wave, tid);
+  int* tok = reinterpret_cast<int*>(lds + LO.prog);
+  if (tid < 16) tok[tid] = 0;
   __syncthreads();
 
   // ------------------------------------------------------- back substitution
@@ -479,6 +492,121 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   const UnitView v = decode_unit(tb, a, u);
   const bool last = (a.mode == MODE_FINE) && (a.r == v.Sb);
   for (int k = tid; k < Mp; k += RT) epi_store(a, ep, u, v.slot, last, k, sb[k]);
+}
+
+// Diagonal block of the blocked factorisation through device memory: the w x w block at
+// (r0, r0) of unit u's matrix A (row stride Mp; w <= 256, a multiple of 16), already updated
+// by the panels to its left, is factored in registers as above, with the forward substitution
+// of the right-hand side block rhs[r0, r0 + w) (y over b).  The block is then replaced by the
+// full inverse X = L^-1 (lower triangle; within the diagonal 16 x 16 tiles the upper part is
+// exact zeros, the tiles above them keep stale values and are never read).  X is formed by
+// tile columns: X_cc = L_cc^-1 from the factorisation and, going down the column,
+//   X_Ic = -X_II sum_{J=c}^{I-1} L_IJ X_Jc,
+// wave w taking the columns w and nt-1-w (nt+1 tiles, the row ownership mirrored), with the
+// L tiles read back from the block after every wave has stored its own.
+__device__ inline void col_slot(int s, int wave, int nt, int& I, int& c) {
+  const int ca = wave, cb = nt - 1 - wave;
+  I = -1;
+  c = -1;
+  if (ca > cb) return;
+  if (s < nt - ca) {
+    c = ca;
+    I = ca + s;
+  } else if (ca < cb && s < nt - ca + wave + 1) {
+    c = cb;
+    I = cb + (s - (nt - ca));
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_blk_diag(Tables tb, StepArgs a, double* A, double* rhs,
+                                                 int r0, int w) {
+  extern __shared__ double lds[];
+  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int Mp = tb.Mp, nt = w / 16;
+  const RegLds LO = reg_lds(w);
+  double* sb = lds + LO.sb;
+  double* sWA = lds + LO.sWA;
+  double* sP = lds + LO.big;
+  d4 acc[RNS];
+  const int lr = lane >> 4, lc = lane & 15;
+  const int b = (a.mode == MODE_FINE) ? u / a.nP : u;
+  if (a.mode == MODE_FINE && a.r > (int)tb.inst[(long)b * NSCAL + IS_SB]) return;
+
+  double* blk = A + (long)u * Mp * Mp + (long)r0 * Mp + r0;
+  double* bu = rhs + (long)u * Mp + r0;
+  for (int k = tid; k < w; k += RT) sb[k] = bu[k];
+#pragma unroll
+  for (int s = 0; s < RNS; ++s) {
+    int tI, tK;
+    slot_tile(s, wave, nt, tI, tK);
+    if (tI < 0) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[s][e] = blk[(long)(tI * 16 + lc) * Mp + tK * 16 + lr + 4 * e];
+  }
+
+  factor_tiles(acc, sb, sWA, sP, nt, w, wave, tid);
+  for (int k = tid; k < w; k += RT) bu[k] = sb[k];
+
+  // L_IK and X_II = L_II^-1 back into the block (row-major 16-lane segments)
+#pragma unroll
+  for (int s = 0; s < RNS; ++s) {
+    int tI, tK;
+    slot_tile(s, wave, nt, tI, tK);
+    if (tI < 0) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = lr + 4 * v;
+      const double x = (tI == tK && r < lc) ? 0.0 : acc[s][v];
+      blk[(long)(tI * 16 + r) * Mp + tK * 16 + lc] = x;
+    }
+  }
+  __syncthreads();
+
+  // tile columns of X; A-operand reads of L_IJ and X_II: lane l takes T[l%16][4v + l/16]
+#pragma unroll
+  for (int s = 0; s < RNS; ++s) {
+    int I, c;
+    col_slot(s, wave, nt, I, c);
+    if (I < 0) continue;
+    if (I == c) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[s][v] = blk[(long)(c * 16 + lr + 4 * v) * Mp + c * 16 + lc];
+      continue;
+    }
+    d4 t = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s2 = 0; s2 < s; ++s2) {
+      int J, c2;
+      col_slot(s2, wave, nt, J, c2);
+      if (c2 != c) continue;  // J runs over c .. I-1: the earlier slots of the same column
+      const double* lt = blk + (long)(I * 16 + lc) * Mp + J * 16 + lr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) t = __builtin_amdgcn_mfma_f64_16x16x4f64(lt[4 * v], acc[s2][v], t, 0, 0, 0);
+    }
+    const double* xt = blk + (long)(I * 16 + lc) * Mp + I * 16 + lr;
+    d4 x = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x = __builtin_amdgcn_mfma_f64_16x16x4f64(-xt[4 * v], t[v], x, 0, 0, 0);
+    acc[s] = x;
+  }
+  __syncthreads();  // every L tile has been read
+#pragma unroll
+  for (int s = 0; s < RNS; ++s) {
+    int I, c;
+    col_slot(s, wave, nt, I, c);
+    if (I < 0 || I == c) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) blk[(long)(I * 16 + lr + 4 * v) * Mp + c * 16 + lc] = acc[s][v];
+  }
+}
+
+hipError_t launch_blk_diag(const Tables& tb, const StepArgs& a, int units, double* A, double* rhs,
+                           int r0, int w, hipStream_t s) {
+  if (w < 16 || w > RMAXMP || w % 16 != 0) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * reg_lds(w).total;
+  k_blk_diag<<<units, RT, lds, s>>>(tb, a, A, rhs, r0, w);
+  return hipGetLastError();
 }
 
 bool reg_path_ok(int Mp, int Qp) {
