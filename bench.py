@@ -37,6 +37,12 @@ The JSON line also carries:
                   4096 seeded serial trajectories (one-off, untimed but reported), then plain
                   and learned parareal are each run to 1e-8 of the serial solution on 64
                   held-out instances and timed.
+  config3_2d      the 2D workload: 64 x 64 tensor sine modes (4096 coefficients), 96 x 96 Gauss
+                  points, N = 2048, P = 128, alpha = 0.6, D = 1 + exp(-u^2)/2, f = sin u: one
+                  fine sweep over all 128 slices (16 steps of 128 systems of size 4096 through
+                  the blocked device-memory factorisation), with its FP64 rate against the
+                  78.6 TFLOP/s peak (M^3/3 + M^2/2 + M/6 + 2 M^2 flops per system); the serial
+                  solve; plain parareal run to 1e-8 of the serial solution.
   cpu_baseline    the CPU oracle (plain serial C) timed on this host's cores on a bounded
                   sample: the first slice (64 fine steps) of 16 instances of the alpha = 0.3
                   batch, one instance per thread.
@@ -278,6 +284,74 @@ def uneven_batch(l1, torch, W, dev):
             "max_rel_err_vs_serial": err, "convergence": "increment <= 1e-8 per instance"}
 
 
+def config3_2d(l1, torch, W, dev, with_parareal=True):
+    """Config 3 (2D): fine-sweep throughput of the blocked device-memory factorisation, the
+    serial solve, and plain parareal to 1e-8 of the serial solution."""
+    from paper_2510_11023_amd import _lib
+
+    kw = dict(W.C3)
+    M1, N, P = kw["modes"], kw["steps"], kw["slices"]
+    Md, S = M1 * M1, N // P
+    p = l1.make_problem(**kw)
+    u0 = torch.tensor(W.u0_random_2d(M1, 0)[None], device=dev)
+    ws = l1.parareal_workspace(p, 1, dev)
+    log(f"config 3: workspace {ws.numel() / 2**30:.1f} GiB")
+    # one fine sweep over all P slices from the coarse initial guess (P units per step)
+    Z = l1.solve_parareal(p, u0, 0, tol=0.0, want_iterates=True, workspace=ws).iterates[0]
+    Z = Z.contiguous()
+    l1.fine_apply(p, Z, workspace=ws)
+    torch.cuda.synchronize()
+    _lib.profile_start()
+    t0 = time.perf_counter()
+    l1.fine_apply(p, Z, workspace=ws)
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t0
+    st = _lib.profile_stop()
+    n_s, tot_s = st.get(f"blk_solve/fine/{P}", (0, 0.0))
+    per_unit = Md ** 3 / 3 + Md ** 2 / 2 + Md / 6 + 2 * Md ** 2  # Cholesky + two triangular solves
+    out = {"workload": f"2D, {M1}x{M1} modes (Md={Md}), {kw['quad']}x{kw['quad']} Gauss points, N={N}, "
+                       f"P={P} (S={S}), alpha={kw['alpha']}, D=1+exp(-u^2)/2, f=sin(u), "
+                       f"u0 c_k1k2 ~ N(0,(k1^2+k2^2)^-1.5) seed 0",
+           "fine_sweep_ms": round(t_sweep * 1e3, 1),
+           "fine_sweep_mode_steps_per_s": P * S * Md / t_sweep,
+           "fine_sweep_tflops": round(P * S * per_unit / t_sweep / 1e12, 2)}
+    if n_s:
+        avg = tot_s / n_s / 1e3
+        ach = P * per_unit / avg / 1e12
+        out["solve_roofline"] = {"bound": "mfma", "kernel": f"blocked factorisation and solve "
+                                 f"(k_blk_diag, k_blk_panel, k_blk_trail, k_blk_bs_*), {P} units per step",
+                                 "achieved": round(ach, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(ach / PEAK_FP64_TFLOPS, 4), "avg_step_ms": round(avg * 1e3, 2),
+                                 "flops_per_step": int(P * per_unit)}
+    share = {k: round(v[1] / sum(x[1] for x in st.values()), 4) for k, v in st.items()}
+    out["fine_sweep_share"] = share
+    log(f"config 3: fine sweep {t_sweep * 1e3:.0f} ms ({out['fine_sweep_tflops']} TFLOP/s)")
+    ws_s = torch.empty(l1.workspace_bytes(p, 1, 0), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Us, _ = l1.solve_serial(p, u0, workspace=ws_s)
+    torch.cuda.synchronize()
+    t_ser = time.perf_counter() - t0
+    out["serial_ms"] = round(t_ser * 1e3, 1)
+    out["serial_mode_steps_per_s"] = N * Md / t_ser
+    log(f"config 3: serial {t_ser * 1e3:.0f} ms")
+    del ws_s
+    if with_parareal:
+        ks, e = find_kstar(l1, p, u0, Us, ws, 14)
+        rec = {"kstar": ks, "rel_err_by_sweep": [float(f"{v:.3e}") for v in e]}
+        if ks is not None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U = l1.solve_parareal(p, u0, ks, tol=0.0, want_incr=False, workspace=ws).U
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t0
+            rec.update({"ms": round(tp * 1e3, 1), "mode_steps_per_s": N * Md / tp,
+                        "achieved_rel_err": rel_err_max(U, Us)})
+        out["parareal_plain"] = rec
+        log(f"config 3: parareal k*={ks} " + (f"{rec.get('ms')} ms" if ks is not None else ""))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,9 +360,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernels"], default="full",
+    ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--mode", choices=["full", "kernels", "kernels2d"], default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
-                         "device copy (for hardware-counter runs); prints no JSON line")
+                         "device copy (for hardware-counter runs); kernels2d: one fine sweep of "
+                         "the 2D workload (128 slices) and the same copy; neither prints a JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; a run on several GPUs is not supported "
@@ -316,6 +392,20 @@ def main():
     ws_par = torch.empty(l1.workspace_bytes(p0, B, 1), dtype=torch.uint8, device=dev)
     ws_ser = torch.empty(l1.workspace_bytes(p0, B, 0), dtype=torch.uint8, device=dev)
     log(f"workspace: parareal {ws_par.numel() / 2**30:.2f} GiB, serial {ws_ser.numel() / 2**20:.0f} MiB")
+
+    if args.mode == "kernels2d":
+        kw2 = dict(W.C3)
+        p2 = l1.make_problem(**kw2)
+        u2 = torch.tensor(W.u0_random_2d(kw2["modes"], 0)[None], device=dev)
+        ws2 = l1.parareal_workspace(p2, 1, dev)
+        Z2 = l1.solve_parareal(p2, u2, 0, tol=0.0, want_iterates=True, workspace=ws2).iterates[0]
+        l1.fine_apply(p2, Z2.contiguous(), workspace=ws2)
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("kernels2d mode done")
+        return
 
     if args.mode == "kernels":
         # one coarse sweep + one fine sweep + one correction sweep, then a plain copy of
@@ -441,6 +531,10 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(l1, torch, W, dev)
 
+    two_d = None
+    if not args.no_2d:
+        two_d = config3_2d(l1, torch, W, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -478,6 +572,7 @@ def main():
         "gemm_assembly": gemm,
         "learned_vs_plain": learned,
         "uneven_batch": uneven,
+        "config3_2d": two_d,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -58,7 +58,8 @@ bool valid(const l1pr_problem* p) {
   if (p->source_time != 0 && p->source_time != 1) return false;
   if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
   if (p->assembly != 0 && p->assembly != 1) return false;
-  if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY | TUNE_NB128)) return false;
+  if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY | TUNE_NB128 | TUNE_TRAIL64))
+    return false;
   return true;
 }
 

@@ -139,14 +139,15 @@ __global__ __launch_bounds__(256) void k_proj_gemm1d(Tables tb, int units, const
     }
 }
 
-// One work-group per unit, one thread per mode: coalesced rows of the trajectory and of the
-// slice-end sequence, loads issued four rows ahead of the sequential (ascending-i) sum.
+// Work-groups (unit, block of 256 coefficients), one thread per coefficient: coalesced rows of
+// the trajectory and of the slice-end sequence, loads issued four rows ahead of the sequential
+// (ascending-i) sum.
 __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double* hist) {
   const int u = blockIdx.x;
   const UnitView v = decode_unit(tb, a, u);
   const double* bw = tb.bw + (long)v.b * tb.LB;
   const int Mp = tb.Mp;
-  for (int k = threadIdx.x; k < Mp; k += blockDim.x) {
+  for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < Mp; k += blockDim.x * gridDim.y) {
     const double* y = v.y + k;
     double acc = 0.0;
     double prev = y[0];
@@ -297,7 +298,7 @@ hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const
 hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
                           hipStream_t s) {
   const int threads = tb.Mp < 256 ? roundup(tb.Mp, 64) : 256;
-  k_history1d<<<units, threads, 0, s>>>(tb, a, hist);
+  k_history1d<<<dim3(units, (tb.Mp + threads - 1) / threads), threads, 0, s>>>(tb, a, hist);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ enum { IS_ALPHA = 0, IS_TAU, IS_TAUC, IS_SFAC, IS_G1A, IS_G3A, IS_MB, IS_SB, NSC
 
 // tuning bits (l1pr_problem.tune): GEMM variant of the lagged-state product and of the
 // projections in fine and full-history steps
-enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2, TUNE_NB128 = 4 };
+enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2, TUNE_NB128 = 4, TUNE_TRAIL64 = 8 };
 
 // kinds of step
 enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };

@@ -502,8 +502,8 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
 // exact zeros, the tiles above them keep stale values and are never read).  X is formed by
 // tile columns: X_cc = L_cc^-1 from the factorisation and, going down the column,
 //   X_Ic = -X_II sum_{J=c}^{I-1} L_IJ X_Jc,
-// wave w taking the columns w and nt-1-w (nt+1 tiles, the row ownership mirrored), with the
-// L tiles read back from the block after every wave has stored its own.
+// wave w taking the columns w and nt-1-w (nt+1 tiles, the row ownership mirrored), one
+// tile-row I at a time with row I of L staged in LDS after every wave has stored its tiles.
 __device__ inline void col_slot(int s, int wave, int nt, int& I, int& c) {
   const int ca = wave, cb = nt - 1 - wave;
   I = -1;
@@ -563,34 +563,48 @@ __global__ __launch_bounds__(RT) void k_blk_diag(Tables tb, StepArgs a, double* 
   }
   __syncthreads();
 
-  // tile columns of X; A-operand reads of L_IJ and X_II: lane l takes T[l%16][4v + l/16]
+  // tile columns of X, one tile-row of L at a time: at step I the work-group copies row I of
+  // the stored block (L_IJ for J < I, X_II) into LDS in A-operand order
+  // (sR[(J * 4 + v) * 64 + l] = T_J[l%16][4v + l/16]), then each wave extends its columns c < I
+  // by X_Ic = -X_II sum_{J=c}^{I-1} L_IJ X_Jc; B operands are the wave's own X_Jc tiles.
+  double* sR = sP;
 #pragma unroll
   for (int s = 0; s < RNS; ++s) {
     int I, c;
     col_slot(s, wave, nt, I, c);
-    if (I < 0) continue;
-    if (I == c) {
+    if (I != c || I < 0) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[s][v] = blk[(long)(c * 16 + lr + 4 * v) * Mp + c * 16 + lc];
-      continue;
-    }
-    d4 t = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s2 = 0; s2 < s; ++s2) {
-      int J, c2;
-      col_slot(s2, wave, nt, J, c2);
-      if (c2 != c) continue;  // J runs over c .. I-1: the earlier slots of the same column
-      const double* lt = blk + (long)(I * 16 + lc) * Mp + J * 16 + lr;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) t = __builtin_amdgcn_mfma_f64_16x16x4f64(lt[4 * v], acc[s2][v], t, 0, 0, 0);
-    }
-    const double* xt = blk + (long)(I * 16 + lc) * Mp + I * 16 + lr;
-    d4 x = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x = __builtin_amdgcn_mfma_f64_16x16x4f64(-xt[4 * v], t[v], x, 0, 0, 0);
-    acc[s] = x;
+    for (int v = 0; v < 4; ++v) acc[s][v] = blk[(long)(c * 16 + lr + 4 * v) * Mp + c * 16 + lc];
   }
-  __syncthreads();  // every L tile has been read
+  for (int I = 1; I < nt; ++I) {
+    for (int e = tid; e < (I + 1) * 256; e += RT) {
+      const int J = e >> 8, r = (e >> 4) & 15, cc = e & 15;
+      sR[(J * 4 + (cc >> 2)) * 64 + r + 16 * (cc & 3)] = blk[(long)(I * 16 + r) * Mp + J * 16 + cc];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < RNS; ++s) {
+      int Is, c;
+      col_slot(s, wave, nt, Is, c);
+      if (Is != I || c >= I) continue;  // wave-uniform
+      d4 t = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < s; ++s2) {
+        int J, c2;
+        col_slot(s2, wave, nt, J, c2);
+        if (c2 != c) continue;  // J runs over c .. I-1: the earlier slots of the same column
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(sR[(J * 4 + v) * 64 + lane], acc[s2][v], t, 0, 0, 0);
+      }
+      d4 x = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        x = __builtin_amdgcn_mfma_f64_16x16x4f64(-sR[(I * 4 + v) * 64 + lane], t[v], x, 0, 0, 0);
+      acc[s] = x;
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int s = 0; s < RNS; ++s) {
     int I, c;

@@ -50,6 +50,8 @@ CASES = [
     ("2d_M24_nb256", dict(W.C3, modes=24, quad=30, steps=4, slices=2), 0, [3, 4]),
     # 2D: Mp 336 = 128 + 128 + 80
     ("2d_M18_nb128", dict(W.C3, modes=18, quad=20, steps=4, slices=2, alpha=0.45), 4, [5]),
+    # 2D with the 64 x 64 trailing-update tiles (tune bit 3): Mp 576 = 256 + 256 + 64
+    ("2d_M24_trail64", dict(W.C3, modes=24, quad=30, steps=4, slices=2), 8, [7]),
     # 2D full history through the blocked path
     ("2d_M17_full", dict(W.C3, modes=17, quad=20, steps=6, slices=2, history=1), 0, [6]),
 ]
