@@ -137,9 +137,10 @@ def learned_vs_plain(l1, torch, W, dev):
     model = LearnedCoarse(M, seed=0)
     ta = W.alphas_uniform(ntrain, W.C4_TRAIN_ALPHA_SEED)
     u0t = torch.tensor(W.u0_batch_1d(M, W.C4_TRAIN_SEEDS), device=dev)
-    x, t = training_data(p, u0t, ta, model)
+    x, t = training_data(p, u0t, ta, model, sweeps=W.C4_TRAIN_SWEEPS)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    nsamples = x.shape[0]
     model.set_stats(x, t)
     t0 = time.perf_counter()
     losses = model.train(x, t, epochs=epochs, batch=1024, lr=1e-3, seed=0)
@@ -155,7 +156,8 @@ def learned_vs_plain(l1, torch, W, dev):
     ws = l1.parareal_workspace(p, B, dev, learned=True)
     out = {"workload": f"1D, M={M}, Q={kw['quad']}, N={N}, P={P}, D=1+1/(1+u^2), f=0.1u(1-u), "
                        f"{B} held-out instances with alpha~U(0.2,1); network 3x512 SiLU, "
-                       f"trained on {ntrain} seeded serial trajectories ({ntrain * P} samples)",
+                       f"trained on {ntrain} seeded serial trajectories and their first "
+                       f"{W.C4_TRAIN_SWEEPS} plain parareal iterates ({nsamples} samples)",
            "train": {"data_s": round(t_data, 2), "train_s": round(t_train, 2), "epochs": epochs,
                      "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}}
     for name, extra in (("plain", {}), ("learned", {"coarse": l1.COARSE_LEARNED, "mlp_params": model.params})):

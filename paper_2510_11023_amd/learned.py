@@ -1,7 +1,11 @@
 """Learned coarse propagator: residual MLP G_L,n = G_n + r(G_n, alpha, n/P).
 
 Training pairs come from the solver itself: serial (fine) solutions C* of seeded instances,
-x = [G_n(C*_0..C*_n) ; alpha ; n/P] and target t = C*_{n+1} - G_n(C*_0..C*_n).  Every
+x = [G_n(C*_0..C*_n) ; alpha ; n/P] and target t = C*_{n+1} - G_n(C*_0..C*_n), and optionally
+the states that plain parareal visits on its way there: for its iterates U^k (k < sweeps),
+x = [G_n(U^k_0..U^k_n) ; alpha ; n/P] and t = F_n(U^k_0..U^k_n) - G_n(U^k_0..U^k_n), the very
+difference a sweep adds to the coarse value.  Parareal contracts by how well G follows F near
+the iterates, not only on the converged trajectory.  Every
 arithmetic step (serial solves, coarse steps, features, statistics, forward/backward, Adam)
 runs in the HIP library; this module allocates buffers, draws the seeded initial weights and
 the per-epoch sample order on the host, and sequences the calls.
@@ -15,7 +19,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .solver import _ptr, _stream, coarse_apply, solve_serial
+from .solver import _ptr, _stream, coarse_apply, fine_apply, solve_parareal, solve_serial
 
 
 def _check(st, what):
@@ -155,19 +159,35 @@ class LearnedCoarse:
         return losses.view(epochs, nb).mean(dim=1).cpu().numpy()
 
 
-def training_data(p, u0: torch.Tensor, alphas, model: LearnedCoarse, chunk: int = 1024):
-    """Serial solutions of the instances (per-instance alpha), the plain coarse step on every
-    slice of them, and the training pairs.  Returns (x, t)."""
+def training_data(p, u0: torch.Tensor, alphas, model: LearnedCoarse, chunk: int = 1024,
+                  sweeps: int = 0):
+    """Training pairs: the serial solutions of the instances (per-instance alpha) with the plain
+    coarse step on every slice, then, for k < sweeps, the plain parareal iterates U^k with
+    F_n(U^k) - G_n(U^k) as target.  Returns (x, t): per chunk of instances, the serial pairs,
+    then those of U^0, U^1, ...; rows b*P + n within each block."""
     xs, ts = [], []
     B = u0.shape[0]
     for b0 in range(0, B, chunk):
         b1 = min(B, b0 + chunk)
         al = [float(a) for a in alphas[b0:b1]]
+        ad = torch.tensor(al, dtype=torch.float64, device=u0.device)
         Z, _ = solve_serial(p, u0[b0:b1], alpha=al)
         G = coarse_apply(p, Z, alpha=al)
-        ad = torch.tensor(al, dtype=torch.float64, device=u0.device)
         x, t = model.features(p, Z, G, ad)
         xs.append(x)
         ts.append(t)
         del Z, G
+        if sweeps > 0:
+            its = solve_parareal(p, u0[b0:b1], sweeps, tol=0.0, alpha=al, want_iterates=True,
+                                 want_incr=False).iterates
+            for k in range(min(sweeps, its.shape[0])):
+                U = its[k].contiguous()
+                G = coarse_apply(p, U, alpha=al)
+                F = fine_apply(p, U, alpha=al)
+                Zf = torch.cat([U[:, :1], F], dim=1).contiguous()  # row n+1 = F_n(U)
+                x, t = model.features(p, Zf, G, ad)
+                xs.append(x)
+                ts.append(t)
+                del U, G, F, Zf
+            del its
     return torch.cat(xs), torch.cat(ts)

@@ -33,6 +33,8 @@ C4_TRAIN_SEEDS = range(0, 4096)
 C4_EVAL_SEEDS = range(100000, 100064)
 C4_TRAIN_ALPHA_SEED = 4242
 C4_EVAL_ALPHA_SEED = 2424
+# training pairs also from the first plain parareal iterates U^0 .. U^2 of each training instance
+C4_TRAIN_SWEEPS = 3
 
 
 # config 5: uneven batch of 256 instances, P = 64 slices, each with its own modes

@@ -172,6 +172,38 @@ def test_mlp_training_reduces_loss(gpu):
     assert losses[-1] < 0.2 * losses[0], losses
 
 
+def test_iterate_training_pairs_match_oracle(gpu, orc):
+    """Pairs from the plain parareal iterates: for U^0 (the initial coarse sweep) the inputs
+    are G_n(U^0) and the targets F_n(U^0) - G_n(U^0), against the oracle's coarse and fine
+    propagators composed slice by slice (targets are stored in FP32)."""
+    from paper_2510_11023_amd.learned import LearnedCoarse, training_data
+
+    kw = SMALL
+    P, M = kw["slices"], kw["modes"]
+    al = [0.45, 0.8]
+    u0 = W.u0_batch_1d(M, [31, 32])
+    pg = gpu.make_problem(**kw)
+    model = LearnedCoarse(M, seed=3)
+    x0, t0 = training_data(pg, dev(u0), al, model)
+    x, t = training_data(pg, dev(u0), al, model, sweeps=1)
+    assert x.shape[0] == 2 * x0.shape[0] == 2 * len(al) * P
+    assert torch.equal(x[: x0.shape[0]], x0) and torch.equal(t[: t0.shape[0]], t0)
+    xi, ti = x[x0.shape[0]:].double().cpu().numpy(), t[t0.shape[0]:].double().cpu().numpy()
+    for b, a in enumerate(al):
+        po = orc.problem(**W.with_(kw, alpha=a))
+        U = np.zeros((P + 1, M))
+        U[0] = u0[b]
+        for n in range(P):
+            U[n + 1] = orc.coarse_G(po, n, U[: n + 1])
+        for n in range(P):
+            G = orc.coarse_G(po, n, U[: n + 1])
+            F = orc.fine_F(po, n, U[: n + 1])
+            r = b * P + n
+            assert np.linalg.norm(xi[r, :M] - G) <= 1e-6 * np.linalg.norm(G), (b, n)
+            assert abs(xi[r, M] - a) <= 1e-7 and abs(xi[r, M + 1] - n / P) <= 1e-7
+            assert np.linalg.norm(ti[r] - (F - G)) <= 1e-5 * max(np.linalg.norm(F - G), 1e-30), (b, n)
+
+
 # -------------------------------------------------------------- learned parareal
 
 def _trained(gpu, kw, alphas, seeds, epochs=3):
