@@ -64,6 +64,8 @@ def lib():
         L.oracle_f.argtypes = [pp] + [ctypes.c_double] * 4
         L.oracle_f.restype = ctypes.c_double
         L.oracle_galerkin.argtypes = [pp, dp, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.oracle_galerkin_rows.argtypes = [pp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32), dp, dp]
         L.oracle_step.argtypes = [pp, dp, ctypes.c_double, ctypes.c_double, dp, ctypes.c_double, dp]
         L.oracle_coarse_G.argtypes = [pp, ctypes.c_int32, dp, dp]
         L.oracle_fine_F.argtypes = [pp, ctypes.c_int32, dp, dp, dp]
@@ -125,6 +127,19 @@ def galerkin(p, c, tD, tf):
     K = np.zeros((Md, Md))
     F = np.zeros(Md)
     _check(lib().oracle_galerkin(ctypes.byref(p), _ptr(c), tD, tf, _ptr(K), _ptr(F)), "galerkin")
+    return K, F
+
+
+def galerkin_rows(p, c, tD, tf, rows):
+    """Rows `rows` of K and the whole load F (the same sums as galerkin, row by row)."""
+    Md = nmodes(p)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    K = np.zeros((len(r), Md))
+    F = np.zeros(Md)
+    _check(lib().oracle_galerkin_rows(ctypes.byref(p), _ptr(c), tD, tf, len(r),
+                                      r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(K),
+                                      _ptr(F)), "galerkin_rows")
     return K, F
 
 

@@ -242,6 +242,76 @@ int oracle_galerkin(const oracle_problem* p, const double* c, double tD, double 
   return 0;
 }
 
+/* Selected rows of the same Galerkin sums: Krows[i][l] = K_{rows[i], l} for the nrows listed
+   rows, and the whole load F.  Same quadrature points, same order and the same expressions
+   per basis value as oracle_galerkin (the products of the separable factors are formed in
+   the order basis_at forms them), so each row equals that row of oracle_galerkin bit for
+   bit; the per-direction sines and cosines are evaluated once per point instead of once per
+   basis function, which makes single rows affordable at large mode counts. */
+int oracle_galerkin_rows(const oracle_problem* p, const double* c, double tD, double tf,
+                         int32_t nrows, const int32_t* rows, double* Krows, double* F) {
+  if (oracle_validate(p)) return -1;
+  const double pi = ORACLE_PI;
+  int Q = p->quad, Md = nmodes(p), M = p->modes;
+  for (int i = 0; i < nrows; i++)
+    if (rows[i] < 0 || rows[i] >= Md) return -1;
+  double* xq = (double*)malloc(sizeof(double) * Q);
+  double* wq = (double*)malloc(sizeof(double) * Q);
+  double* val = (double*)malloc(sizeof(double) * Md);
+  double* gx = (double*)malloc(sizeof(double) * Md);
+  double* gy = (double*)malloc(sizeof(double) * Md);
+  double* sx = (double*)malloc(sizeof(double) * M);
+  double* cx = (double*)malloc(sizeof(double) * M);
+  double* sy = (double*)malloc(sizeof(double) * M);
+  double* cy = (double*)malloc(sizeof(double) * M);
+  oracle_gauss_legendre01(Q, xq, wq);
+  memset(Krows, 0, sizeof(double) * (size_t)nrows * Md);
+  memset(F, 0, sizeof(double) * Md);
+  int Q2 = p->dim == 1 ? 1 : Q;
+  for (int q1 = 0; q1 < Q; q1++) {
+    for (int q2 = 0; q2 < Q2; q2++) {
+      double X = xq[q1];
+      double Y = p->dim == 1 ? 0.0 : xq[q2];
+      double W = p->dim == 1 ? wq[q1] : wq[q1] * wq[q2];
+      if (p->dim == 1) {
+        basis_at(p, X, Y, val, gx, gy);
+      } else {
+        for (int k = 0; k < M; k++) {
+          double a = (k + 1) * pi;
+          sx[k] = sin(a * X); cx[k] = cos(a * X);
+          sy[k] = sin(a * Y); cy[k] = cos(a * Y);
+        }
+        for (int k1 = 0; k1 < M; k1++) {
+          for (int k2 = 0; k2 < M; k2++) {
+            int k = k1 * M + k2;
+            double a1 = (k1 + 1) * pi, a2 = (k2 + 1) * pi;
+            val[k] = 2.0 * sx[k1] * sy[k2];
+            gx[k] = 2.0 * a1 * cx[k1] * sy[k2];
+            gy[k] = 2.0 * a2 * sx[k1] * cy[k2];
+          }
+        }
+      }
+      double u = 0.0;
+      for (int k = 0; k < Md; k++) u += c[k] * val[k];
+      double Dq = oracle_D(p, X, Y, tD, u);
+      double fq = oracle_f(p, X, Y, tf, u);
+      for (int k = 0; k < Md; k++) F[k] += W * fq * val[k];
+      for (int i = 0; i < nrows; i++) {
+        int k = rows[i];
+        double* Kk = Krows + (size_t)i * Md;
+        double ak = W * Dq * gx[k], bk = W * Dq * gy[k];
+        if (p->dim == 1) {
+          for (int l = 0; l < Md; l++) Kk[l] += ak * gx[l];
+        } else {
+          for (int l = 0; l < Md; l++) Kk[l] += ak * gx[l] + bk * gy[l];
+        }
+      }
+    }
+  }
+  free(xq); free(wq); free(val); free(gx); free(gy); free(sx); free(cx); free(sy); free(cy);
+  return 0;
+}
+
 /* Gaussian elimination with partial pivoting; A (n x n, row-major) is destroyed and
    the solution overwrites b. */
 static int solve_dense(int n, double* A, double* b) {

@@ -63,6 +63,11 @@ double oracle_f(const oracle_problem* p, double x, double y, double t, double u)
 int    oracle_galerkin(const oracle_problem* p, const double* c, double tD, double tf,
                        double* K, double* F);
 
+/* The rows `rows[0..nrows)` of K (Krows [nrows][Md]) and the whole load F, equal to those of
+   oracle_galerkin bit for bit (for sampled checks at sizes where the whole K is too slow). */
+int    oracle_galerkin_rows(const oracle_problem* p, const double* c, double tD, double tf,
+                            int32_t nrows, const int32_t* rows, double* Krows, double* F);
+
 /* One semi-implicit step: solve (I + tau K(c_prev)) c = hist + tau F(c_prev). */
 int    oracle_step(const oracle_problem* p, const double* c_prev, double tD, double tf,
                    const double* hist, double tau, double* c_out);

@@ -91,3 +91,41 @@ def test_2d_coarse_and_fine_apply(gpu, orc):
     for n in range(P):
         assert rel(G[0, n], orc.coarse_G(po, n, Z[0, : n + 1])) <= TOL
         assert rel(F[0, n], orc.fine_F(po, n, Z[0, : n + 1])) <= TOL
+
+
+# ------------------------------------------------- full size (config 3: 64 x 64 modes), sampled
+
+def test_full_size_first_step_rows_match_oracle(gpu, orc):
+    """One step of the config-3 step size at full size (4096 coefficients, 96 x 96 points)
+    through the blocked factorisation: on sampled rows, the GPU state c1 satisfies the step's
+    equation c1 + tau K(c0) c1 = c0 + tau F(c0) with the oracle's own rows of K and load F."""
+    import math
+
+    T = 1.0 / 2048  # one step of N = 2048 on (0, 1)
+    kw = c3(steps=1, slices=1, T=T)
+    pg, po = gpu.make_problem(**kw), orc.problem(**kw)
+    c0 = W.u0_random_2d(kw["modes"], 0)
+    _, tr = gpu.solve_serial(pg, torch.tensor(c0[None], device="cuda"), want_traj=True)
+    c1 = tr[0, 1].cpu().numpy()
+    tau = T ** kw["alpha"] * math.gamma(2.0 - kw["alpha"])
+    Md = kw["modes"] ** 2
+    rows = sorted({0, 1, 63, 64, Md - 1, *np.random.default_rng(17).choice(Md, 11, replace=False).tolist()})
+    Kr, F = orc.galerkin_rows(po, c0, 0.0, 0.0, rows)
+    for i, k in enumerate(rows):
+        lhs = c1[k] + tau * (Kr[i] @ c1)
+        rhs = c0[k] + tau * F[k]
+        scale = abs(c1[k]) + tau * (np.abs(Kr[i]) @ np.abs(c1)) + abs(c0[k]) + tau * abs(F[k])
+        assert abs(lhs - rhs) <= TOL * scale, (k, abs(lhs - rhs) / scale)
+
+
+def test_full_size_parareal_exact(gpu):
+    """Full mode count (64 x 64), short horizon: the first k+1 slice ends of iterate k equal the
+    serial solution bit for bit, and all of them after P sweeps."""
+    kw = c3(steps=16, slices=4, T=16.0 / 2048)
+    pg = gpu.make_problem(**kw)
+    u0 = torch.tensor(W.u0_random_2d(kw["modes"], 1)[None], device="cuda")
+    Us, _ = gpu.solve_serial(pg, u0)
+    r = gpu.solve_parareal(pg, u0, 4, tol=0.0, want_iterates=True)
+    for k in range(5):
+        assert torch.equal(r.iterates[k][:, : k + 1], Us[:, : k + 1]), k
+    assert torch.equal(r.U, Us)

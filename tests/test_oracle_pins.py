@@ -507,3 +507,17 @@ def test_parareal_linear_scalar_binomial_closed_form(orc, S):
         for n in range(P + 1):
             ref = sum(math.comb(n, j) * (fm - g) ** j * g ** (n - j) for j in range(min(kk, n) + 1)) * u0
             assert its[kk][n, 0] == pytest.approx(ref, rel=1e-13, abs=1e-17), (kk, n)
+
+
+def test_galerkin_rows_equal_full_galerkin_rows(orc):
+    """The row-sampled Galerkin sums (used for sampled checks at full 2D size) are the same sums
+    as the full ones, bit for bit, in 1D and 2D, for nonlinear D and f."""
+    from paper_2510_11023_amd import workloads as W
+
+    for kw, c in ((dict(W.C2, modes=24, quad=36, steps=8, slices=2), W.u0_batch_1d(24, [5])[0]),
+                  (dict(W.C3, modes=7, quad=11, steps=8, slices=2), W.u0_random_2d(7, 5))):
+        p = orc.problem(**kw)
+        K, F = orc.galerkin(p, c, 0.25, 0.25)
+        rows = [0, 3, len(c) - 1, len(c) // 2]
+        Kr, Fr = orc.galerkin_rows(p, c, 0.25, 0.25, rows)
+        assert np.array_equal(Kr, K[rows]) and np.array_equal(Fr, F), kw["dim"]
