@@ -26,6 +26,11 @@ namespace l1pr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// LDS row stride of the staged 16-column chunks: an MFMA operand read takes 16 rows x 4
+// columns (lane l: row l%16, column l/16); with 18 doubles per row the 32 lanes of each half
+// of a 64-bit read fall on 64 distinct banks (17 would put two lanes on some banks).
+constexpr int TKP = 18;
+
 __device__ inline bool unit_idle(const Tables& tb, const StepArgs& a, int u) {
   if (a.mode != MODE_FINE) return false;
   const int b = u / a.nP;
@@ -48,8 +53,8 @@ __device__ inline int panel_tile(int v, int y) {
 
 __global__ __launch_bounds__(256) void k_blk_panel(Tables tb, StepArgs a, double* A, double* rhs,
                                                    int r0, int w) {
-  __shared__ double sA[64][17];
-  __shared__ double sX[256][17];
+  __shared__ double sA[64][TKP];
+  __shared__ double sX[256][TKP];
   __shared__ double sred[4][64];
   const int u = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -168,6 +173,7 @@ __global__ __launch_bounds__(256) void k_blk_panel(Tables tb, StepArgs a, double
 // sends to one XCD (every 8th) take a contiguous run of (unit, tile) pairs, row by row: they
 // share panel rows in that XCD's L2.
 constexpr int TB = 128, TK = 16, TT = 512, NXCD = 8;
+static_assert(TKP >= TK, "chunk rows hold TK columns");
 
 __device__ inline int xcd_remap(int id, int total) {
   const int q = total / NXCD, rem = total % NXCD, x = id % NXCD, k = id / NXCD;
@@ -176,8 +182,8 @@ __device__ inline int xcd_remap(int id, int total) {
 
 __global__ __launch_bounds__(TT, 4) void k_blk_trail(Tables tb, StepArgs a, double* A, int r0, int w,
                                                   int ntile) {
-  __shared__ double sI[TB][TK + 1];
-  __shared__ double sK[TB][TK + 1];
+  __shared__ double sI[TB][TKP];
+  __shared__ double sK[TB][TKP];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
@@ -264,8 +270,8 @@ constexpr int TB64 = 64;
 
 __global__ __launch_bounds__(256) void k_blk_trail64(Tables tb, StepArgs a, double* A, int r0, int w,
                                                      int ntile) {
-  __shared__ double sI[TB64][TK + 1];
-  __shared__ double sK[TB64][TK + 1];
+  __shared__ double sI[TB64][TKP];
+  __shared__ double sK[TB64][TKP];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
