@@ -39,13 +39,13 @@ def dev(a):
 
 # (name, problem keywords, tune bits, seeds); padded sizes and block splits in the names
 CASES = [
-    # 1D, quadrature-GEMM assembly: Mp 400 = 256 + 144.  The step sizes keep cond(A) below
-    # 1e5, as at the benchmark sizes: the blocks are applied through explicit triangular
-    # inverses, whose error is of order cond(A) eps (normwise); at cond 1e6 (N = 8) that is
-    # 1e-10 in one step, where triangular substitution stays near 1e-12.
-    ("1d_M400_nb256", W.with_(W.C2, modes=400, quad=420, steps=64, slices=2, alpha=0.9), 0, [21]),
+    # 1D, quadrature-GEMM assembly: Mp 400 = 256 + 144.  The horizon T = 0.1 keeps cond(A)
+    # near 1e4: the blocks are applied through explicit triangular inverses, whose error is
+    # of order cond(A) eps (normwise); at cond 1e6 (T = 1, N = 8) that is 1e-10 in one step,
+    # where triangular substitution stays near 1e-12.
+    ("1d_M400_nb256", W.with_(W.C2, modes=400, quad=420, steps=64, slices=2, alpha=0.9, T=0.1), 0, [21]),
     # 1D: Mp 304 = 128 + 128 + 48
-    ("1d_M300_nb128", W.with_(W.C2, modes=300, quad=330, steps=48, slices=3, alpha=0.9), 4, [23]),
+    ("1d_M300_nb128", W.with_(W.C2, modes=300, quad=330, steps=48, slices=3, alpha=0.9, T=0.1), 4, [23]),
     # 2D: Mp 576 = 256 + 256 + 64
     ("2d_M24_nb256", dict(W.C3, modes=24, quad=30, steps=4, slices=2), 0, [3, 4]),
     # 2D: Mp 336 = 128 + 128 + 80
