@@ -68,9 +68,9 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "4f4096f4255a90b4249030619771481a205f009aeca64c2447c199ff9e58f76d",
-                  "fetch_kib": 8759, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
-                  "bytes_per_launch": (2 * 8759 + 4096) * 1024}
+TRAFFIC_RECORD = {"sha256": "9c41e59dba6be68e7f9f91b1df183b0ebeed7885e1a3bd3eade8656511ab74f9",
+                  "fetch_kib": 8765, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+                  "bytes_per_launch": (2 * 8765 + 4096) * 1024}
 
 
 def log(msg):
