@@ -68,7 +68,7 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "9c41e59dba6be68e7f9f91b1df183b0ebeed7885e1a3bd3eade8656511ab74f9",
+TRAFFIC_RECORD = {"sha256": "f5a15efb9da8f3b2b9bfc5fd6e3ad5d043aa733e2e23886215e87764f805df8f",
                   "fetch_kib": 8765, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": (2 * 8765 + 4096) * 1024}
 

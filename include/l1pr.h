@@ -102,7 +102,9 @@ typedef struct {
                            for the lagged-state product instead of 16 x 16 split-K tiles;
                            bit 1: 16 x 16 split-K tiles for the projections instead of 64 x 64;
                            bit 2: 128-column blocks instead of 256 in the device-memory
-                           factorisation of systems with more than 256 coefficients); 0 is
+                           factorisation of systems with more than 256 coefficients;
+                           bit 3: 64 x 64 instead of 128 x 128 tiles in its trailing
+                           update); 0 is
                            the default, l1pr_autotune measures the best.  The variants sum in
                            different orders, so runs compared bit for bit must use the same
                            value. */
@@ -213,14 +215,39 @@ l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
                                        int64_t* stamps, double* incr, void* ws, size_t ws_bytes,
                                        void* stream);
 
+/* Heterogeneous batch: `count` problems, each with its own parameters and one instance (its
+ * own alpha is probs[i].alpha), solved as groups of problems that share launches, one group
+ * after another on the stream:
+ *  - 1D problems with history 0 and roundup16(modes) <= 256 are grouped by (roundup16(modes),
+ *    quad, slices, T, d_sel, d_param, f_sel, source_time, assembly, tune) and run as an uneven
+ *    batch (each with its own modes, fine steps per slice steps/slices and order);
+ *  - every other problem is grouped with the problems equal to it up to alpha.
+ * Each problem's result equals its own l1pr_solve_serial / l1pr_solve_parareal run bit for bit.
+ *   op     : L1PR_OP_SERIAL (the serial solutions) or L1PR_OP_PARAREAL (min(sweeps, P_i) plain
+ *            parareal sweeps, no tolerance test, no host synchronisation per sweep)
+ *   u0     : device; problem i's initial coefficients at u0 + u0_off[i] (Md_i values)
+ *   U      : device; problem i's slice ends at U + U_off[i] ((P_i + 1) x Md_i values, row-major)
+ *   u0_off, U_off : host int64 [count], offsets in doubles
+ *   ws     : device workspace, ws_bytes >= l1pr_batch_workspace_bytes(probs, count, op)
+ * Returns EINVAL (and launches nothing) if a problem, op or sweeps is invalid (parareal needs
+ * history 0 in every problem).  The grouping
+ * and the per-instance tables are host work with pageable copies: the call is not meant for
+ * graph capture (the uneven entry points above are). */
+size_t      l1pr_batch_workspace_bytes(const l1pr_problem* probs, int32_t count, int32_t op);
+l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t op, int32_t sweeps,
+                             const double* u0, const int64_t* u0_off, double* U,
+                             const int64_t* U_off, void* ws, size_t ws_bytes, void* stream);
+
 /* Rate of the device wall clock that l1pr_solve_parareal_uneven stamps, in kHz (-1 on
  * error); for the current device. */
 int64_t     l1pr_wall_clock_khz(void);
 /* Writes the device wall clock to t (device int64) when the stream reaches this point. */
 l1pr_status l1pr_device_stamp(int64_t* t, void* stream);
 
-/* Measures the GEMM variants of a fine step of `batch` instances x P slices (the parareal
- * fine sweep) and writes the fastest as tune bits (0 for problems without a choice).
+/* Measures the variants of a fine step of `batch` instances x P slices (the parareal fine
+ * sweep) and writes the fastest as tune bits: the GEMM tiles for systems of at most 256
+ * coefficients (bits 0, 1), the block width and trailing-update tiles of the blocked
+ * factorisation beyond (bits 2, 3); 0 for problems without a choice.
  * Needs a parareal workspace (ws_bytes >= l1pr_workspace_bytes(p, batch, L1PR_OP_PARAREAL));
  * synchronises the stream. */
 l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t ws_bytes,

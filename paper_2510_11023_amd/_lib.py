@@ -127,6 +127,12 @@ def lib():
                                                  ctypes.c_double, vp, vp, vp, vp, ctypes.c_size_t,
                                                  vp]
         L.l1pr_solve_parareal_uneven.restype = ctypes.c_int
+        L.l1pr_batch_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32]
+        L.l1pr_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.l1pr_solve_batch.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64), vp,
+                                       ctypes.POINTER(ctypes.c_int64), vp, ctypes.c_size_t, vp]
+        L.l1pr_solve_batch.restype = ctypes.c_int
         L.l1pr_device_stamp.argtypes = [vp, vp]
         L.l1pr_device_stamp.restype = ctypes.c_int
         L.l1pr_wall_clock_khz.argtypes = []

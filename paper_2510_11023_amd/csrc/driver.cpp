@@ -651,11 +651,57 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
     Ctx c;
     l1pr_status st = setup(&q, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
-    if (!c.reg || q.history != 0 || q.dim != 1) {  // no variants to choose between
+    const Tables& tb = c.tb;
+    if (!c.reg) {
+      // blocked factorisation: block width (256 / 128) and trailing tiles (128 / 64), timed on
+      // a fine step's systems (B P units, set to the identity before each factorisation; the
+      // kernels' work does not depend on the values)
+      hipEvent_t e0, e1;
+      L1PR_TRY(hipEventCreate(&e0));
+      L1PR_TRY(hipEventCreate(&e1));
+      const int units = tb.B * tb.P;
+      float best = 1e30f;
+      int32_t best_t = 0;
+      for (int32_t t : {0, (int32_t)TUNE_NB128, (int32_t)TUNE_TRAIL64, (int32_t)(TUNE_NB128 | TUNE_TRAIL64)}) {
+        c.tb.tune = t;
+        c.tb.nb = (t & TUNE_NB128) ? 128 : 256;  // the layout's scratch covers both widths
+        StepArgs a = base_args(c);
+        a.mode = MODE_FINE;
+        a.r = 1;
+        a.nP = tb.P;
+        a.traj = c.ptr(c.L.traj);
+        a.trajP = tb.P;
+        a.Z = c.ptr(c.L.Z0);
+        Epilogue e{};
+        e.kind = EPI_STORE;
+        e.out = c.ptr(c.L.traj) + tb.Mp;  // row 1 of every slot
+        e.out_stride = (long)(tb.S + 1) * tb.Mp;
+        float total = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+          L1PR_TRY(launch_identity(a.A, units, tb.Mp, c.s));
+          L1PR_TRY(launch_fill(a.rhs, (long)units * tb.Mp, 0.0, c.s));
+          L1PR_TRY(hipEventRecord(e0, c.s));
+          L1PR_TRY(launch_blk_solve(c.tb, a, e, units, c.ptr(c.L.q), c.s));
+          L1PR_TRY(hipEventRecord(e1, c.s));
+          L1PR_TRY(hipEventSynchronize(e1));
+          float ms = 0.f;
+          L1PR_TRY(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) total += ms;  // the first run warms up
+        }
+        if (total < best) {
+          best = total;
+          best_t = t;
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      *tune_out = best_t;
+      return L1PR_OK;
+    }
+    if (q.history != 0 || q.dim != 1) {  // no variants to choose between
       *tune_out = 0;
       return L1PR_OK;
     }
-    const Tables& tb = c.tb;
     const long vecP = (long)(tb.P + 1) * tb.Mp;
     double* Z = c.ptr(c.L.Z0);
     L1PR_TRY(launch_fill(Z, (long)tb.B * vecP, 0.0, c.s));
@@ -827,6 +873,164 @@ const char* l1pr_status_string(l1pr_status s) {
     case L1PR_ENONFINITE: return "non-finite parareal increment";
   }
   return "unknown status";
+}
+
+}  // extern "C"
+
+namespace {
+
+// One group of a heterogeneous batch: the problem it runs as, its members, and whether it
+// runs as an uneven batch.
+struct BatchGroup {
+  l1pr_problem p;
+  bool uneven;
+  std::vector<int> members;
+};
+
+int batch_md(const l1pr_problem& p) { return p.dim == 1 ? p.modes : p.modes * p.modes; }
+
+bool uneven_capable(const l1pr_problem& p) {
+  return p.dim == 1 && p.history == 0 && roundup(p.modes, 16) <= 256;
+}
+
+// Groups in order of first appearance; members in input order.
+std::vector<BatchGroup> batch_groups(const l1pr_problem* probs, int count) {
+  std::vector<BatchGroup> g;
+  for (int i = 0; i < count; ++i) {
+    const l1pr_problem& q = probs[i];
+    const bool un = uneven_capable(q);
+    int found = -1;
+    for (size_t k = 0; k < g.size() && found < 0; ++k) {
+      const l1pr_problem& r = probs[g[k].members[0]];
+      if (g[k].uneven != un) continue;
+      bool same = q.dim == r.dim && q.quad == r.quad && q.slices == r.slices && q.T == r.T &&
+                  q.d_sel == r.d_sel && q.d_param == r.d_param && q.f_sel == r.f_sel &&
+                  q.history == r.history && q.source_time == r.source_time &&
+                  q.assembly == r.assembly && q.tune == r.tune;
+      if (un) same = same && roundup(q.modes, 16) == roundup(r.modes, 16);
+      else same = same && q.modes == r.modes && q.steps == r.steps;
+      if (same) found = (int)k;
+    }
+    if (found < 0) {
+      BatchGroup ng;
+      ng.p = q;
+      ng.uneven = un;
+      g.push_back(ng);
+      found = (int)g.size() - 1;
+    }
+    BatchGroup& G = g[found];
+    G.members.push_back(i);
+    if (un) {  // the group runs at its largest modes and steps per slice
+      G.p.modes = std::max(G.p.modes, q.modes);
+      G.p.steps = std::max(G.p.steps / G.p.slices, q.steps / q.slices) * G.p.slices;
+    }
+  }
+  return g;
+}
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Workspace of one group: its solver workspace, then the packed inputs and outputs, then the
+// uneven per-instance arrays.
+struct GroupWs {
+  size_t solver, u0p, Up, modes, spp, alpha, total;
+};
+
+GroupWs group_ws(const BatchGroup& G, int op) {
+  const int B = (int)G.members.size(), Md = batch_md(G.p);
+  GroupWs w;
+  w.solver = al256(l1pr_workspace_bytes(&G.p, B, op));
+  w.u0p = w.solver;
+  w.Up = w.u0p + al256(sizeof(double) * (size_t)B * Md);
+  w.modes = w.Up + al256(sizeof(double) * (size_t)B * (G.p.slices + 1) * Md);
+  w.spp = w.modes + al256(sizeof(int32_t) * (size_t)B);
+  w.alpha = w.spp + al256(sizeof(int32_t) * (size_t)B);
+  w.total = w.alpha + al256(sizeof(double) * (size_t)B);
+  return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t l1pr_batch_workspace_bytes(const l1pr_problem* probs, int32_t count, int32_t op) {
+  if (!probs || count < 0 || (op != L1PR_OP_SERIAL && op != L1PR_OP_PARAREAL)) return 0;
+  for (int i = 0; i < count; ++i)
+    if (!valid(&probs[i]) || (op == L1PR_OP_PARAREAL && probs[i].history != 0)) return 0;
+  size_t mx = 256;
+  for (const BatchGroup& G : batch_groups(probs, count)) mx = std::max(mx, group_ws(G, op).total);
+  return mx;
+}
+
+l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t op, int32_t sweeps,
+                             const double* u0, const int64_t* u0_off, double* U,
+                             const int64_t* U_off, void* ws, size_t ws_bytes, void* stream) {
+  try {
+    if (!probs || count < 0 || (op != L1PR_OP_SERIAL && op != L1PR_OP_PARAREAL) || sweeps < 0)
+      return L1PR_EINVAL;
+    if (count == 0) return L1PR_OK;
+    if (!u0 || !u0_off || !U || !U_off || !ws) return L1PR_EINVAL;
+    for (int i = 0; i < count; ++i)
+      if (!valid(&probs[i]) || u0_off[i] < 0 || U_off[i] < 0 ||
+          (op == L1PR_OP_PARAREAL && probs[i].history != 0))
+        return L1PR_EINVAL;
+    const std::vector<BatchGroup> groups = batch_groups(probs, count);
+    for (const BatchGroup& G : groups)
+      if (group_ws(G, op).total > ws_bytes) return L1PR_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    for (const BatchGroup& G : groups) {
+      const int B = (int)G.members.size(), Md = batch_md(G.p), P = G.p.slices;
+      const GroupWs w = group_ws(G, op);
+      double* u0p = reinterpret_cast<double*>(base + w.u0p);
+      double* Up = reinterpret_cast<double*>(base + w.Up);
+      // gather the initial coefficients, zero above each member's own modes
+      L1PR_TRY(launch_fill(u0p, (long)B * Md, 0.0, s));
+      std::vector<int32_t> modes(B), spp(B);
+      std::vector<double> alpha(B);
+      for (int b = 0; b < B; ++b) {
+        const l1pr_problem& q = probs[G.members[b]];
+        modes[b] = q.modes;
+        spp[b] = q.steps / q.slices;
+        alpha[b] = q.alpha;
+        L1PR_TRY(hipMemcpyAsync(u0p + (long)b * Md, u0 + u0_off[G.members[b]],
+                                sizeof(double) * batch_md(q), hipMemcpyDeviceToDevice, s));
+      }
+      const int k = std::min(sweeps, P);
+      l1pr_status st;
+      if (G.uneven) {
+        int32_t* dm = reinterpret_cast<int32_t*>(base + w.modes);
+        int32_t* ds = reinterpret_cast<int32_t*>(base + w.spp);
+        double* da = reinterpret_cast<double*>(base + w.alpha);
+        // pageable sources: each copy is staged before hipMemcpyAsync returns
+        L1PR_TRY(hipMemcpyAsync(dm, modes.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+        L1PR_TRY(hipMemcpyAsync(ds, spp.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
+        L1PR_TRY(hipMemcpyAsync(da, alpha.data(), sizeof(double) * B, hipMemcpyHostToDevice, s));
+        l1pr_uneven desc{dm, ds, da};
+        st = (op == L1PR_OP_SERIAL)
+                 ? l1pr_solve_serial_uneven(&G.p, B, &desc, u0p, Up, base, w.solver, stream)
+                 : l1pr_solve_parareal_uneven(&G.p, B, &desc, u0p, Up, k, 0.0, nullptr, nullptr,
+                                              nullptr, base, w.solver, stream);
+      } else {
+        st = (op == L1PR_OP_SERIAL)
+                 ? l1pr_solve_serial(&G.p, B, alpha.data(), u0p, Up, nullptr, base, w.solver, stream)
+                 : l1pr_solve_parareal(&G.p, B, alpha.data(), u0p, Up, k, 0.0, nullptr, nullptr,
+                                       nullptr, base, w.solver, stream);
+      }
+      if (st != L1PR_OK) return st;
+      // scatter each member's slice ends (its own Md columns of every row)
+      for (int b = 0; b < B; ++b) {
+        const l1pr_problem& q = probs[G.members[b]];
+        const size_t mdq = (size_t)batch_md(q);
+        L1PR_TRY(hipMemcpy2DAsync(U + U_off[G.members[b]], sizeof(double) * mdq,
+                                  Up + (long)b * (P + 1) * Md, sizeof(double) * Md,
+                                  sizeof(double) * mdq, P + 1, hipMemcpyDeviceToDevice, s));
+      }
+    }
+    return L1PR_OK;
+  } catch (...) {
+    return L1PR_EHIP;
+  }
 }
 
 }  // extern "C"

@@ -230,6 +230,7 @@ hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, con
                              hipStream_t s);
 hipError_t launch_form_rhs(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
+hipError_t launch_identity(double* A, int units, int n, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 // blocked factorisation and solve through device memory (chol_blk.hip): A and rhs of the

@@ -124,6 +124,20 @@ __global__ void k_fill(double* x, long n, double v) {
   if (i < n) x[i] = v;
 }
 
+// A[u] = I for `units` matrices of order n (grid-stride)
+__global__ void k_identity(double* A, long total, int n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    const long e = i % ((long)n * n);
+    A[i] = (e / n == e % n) ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_identity(double* A, int units, int n, hipStream_t s) {
+  const long total = (long)units * n * n;
+  if (total > 0) k_identity<<<4096, 256, 0, s>>>(A, total, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s) {
   if (n > 0) k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
   return hipGetLastError();

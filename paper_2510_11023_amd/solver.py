@@ -7,6 +7,7 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -229,6 +230,38 @@ def autotune(p: Problem, batch: int, workspace=None) -> int:
     if st != _lib.OK:
         raise _lib.L1prError(st, "l1pr_autotune")
     return int(out.value)
+
+
+def solve_batch(problems, u0s, parareal_sweeps: int | None = None, workspace=None):
+    """Heterogeneous batch: problems[i] (each with its own parameters and alpha) from u0s[i]
+    (device float64 [Md_i]).  Serial solutions, or parareal_sweeps plain parareal sweeps.
+    Returns a list of slice-end tensors [P_i + 1, Md_i] (views of one output buffer)."""
+    n = len(problems)
+    if n != len(u0s):
+        raise ValueError("one initial vector per problem")
+    arr = (Problem * max(n, 1))(*problems)
+    sizes = [nmodes(p) for p in problems]
+    outs = [(p.slices + 1) * m for p, m in zip(problems, sizes)]
+    for u, m in zip(u0s, sizes):
+        if not (u.is_cuda and u.dtype == torch.float64 and u.numel() == m):
+            raise ValueError("each u0 must be a float64 device vector of the problem's size")
+    dev = u0s[0].device if n else torch.device("cuda")
+    u0_off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64) if n else np.zeros(0, np.int64)
+    U_off = np.concatenate([[0], np.cumsum(outs)[:-1]]).astype(np.int64) if n else np.zeros(0, np.int64)
+    u0 = torch.cat([u.reshape(-1) for u in u0s]) if n else torch.zeros(1, dtype=torch.float64, device=dev)
+    U = torch.empty(max(int(sum(outs)), 1), dtype=torch.float64, device=dev)
+    op = _lib.OP_SERIAL if parareal_sweeps is None else _lib.OP_PARAREAL
+    nb = int(_lib.lib().l1pr_batch_workspace_bytes(arr, n, op))
+    if nb == 0:
+        raise _lib.L1prError(_lib.EINVAL, "l1pr_batch_workspace_bytes")
+    ws = workspace if workspace is not None else torch.empty(nb, dtype=torch.uint8, device=dev)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    st = _lib.lib().l1pr_solve_batch(arr, n, op, int(parareal_sweeps or 0), _ptr(u0),
+                                     u0_off.ctypes.data_as(i64), _ptr(U), U_off.ctypes.data_as(i64),
+                                     _ptr(ws), ws.numel() * ws.element_size(), _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_solve_batch")
+    return [U[o:o + k].view(p.slices + 1, m) for o, k, p, m in zip(U_off, outs, problems, sizes)]
 
 
 def device_stamp(t: torch.Tensor):

@@ -102,3 +102,19 @@ def test_blocked_parareal_exact_after_P_sweeps(gpu, dim):
     for k in range(P + 1):
         assert torch.equal(r.iterates[k][:, : k + 1], Us[:, : k + 1]), k
     assert torch.equal(r.U, Us)
+
+
+def test_autotune_blocked_variants(gpu, orc):
+    """The autotuner chooses among the blocked factorisation's variants (block width, trailing
+    tiles); the chosen problem still matches the oracle and parareal stays exact."""
+    kw = dict(W.C3, modes=18, quad=20, steps=6, slices=3)
+    p = gpu.make_problem(**kw)
+    t = gpu.autotune(p, 2)
+    assert t in (0, 4, 8, 12), t
+    p.tune = t
+    u0 = u0_for(kw, [12, 13])
+    Us, _ = gpu.solve_serial(p, dev(u0))
+    for b in range(2):
+        assert rel(Us[b].cpu().numpy(), orc.solve_serial(orc.problem(**kw), u0[b])) <= TOL
+    r = gpu.solve_parareal(p, dev(u0), kw["slices"], tol=0.0)
+    assert torch.equal(r.U, Us)
