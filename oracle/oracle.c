@@ -486,7 +486,55 @@ int oracle_solve_serial(const oracle_problem* p, const double* u0, double* U, do
   return rc;
 }
 
-/* Parareal (Section 2.2 and its flowchart).  Initial coarse sweep
+/* Full-history fine propagator (the full-history variant of parareal; not in the paper, whose
+   fine step uses the coarse grid for the history before the slice).  S fine steps on
+   [T_n, T_{n+1}] from c_0 = C_n with the uniform L1 history over the whole fine grid:
+     c_r + tau K(c_{r-1}) c_r = c_{m} - sum_{j=1}^{m} b_{m+1-j} (x_j - x_{j-1}) + tau F(c_{r-1}),
+   m = nS + r - 1, where x_j is the current slice's own state for j >= nS (x_{nS} = C_n) and,
+   before it, the fine trajectory of the previous parareal iterate: prev [P][S+1][Md] holds,
+   for every slice q, the states at its fine levels 0..S, and x_j = prev[q][j - qS] with
+   q = (j-1)/S for 1 <= j < nS, x_0 = prev[0][0] (= u0).  Writes the slice's states to
+   slot_out [S+1][Md] and its end to out. */
+static int fine_F_full(const oracle_problem* p, int n, const double* C, const double* prev,
+                       double* out, double* slot_out) {
+  int Md = nmodes(p), S = p->steps / p->slices;
+  double a = p->alpha;
+  double tau = tau_of(p, p->T / (double)p->steps);
+  double* c = slot_out;
+  double* hist = (double*)malloc(sizeof(double) * Md);
+  memcpy(c, C + (size_t)n * Md, sizeof(double) * Md);
+  long nS = (long)n * S;
+  int rc = 0;
+  for (int r = 1; r <= S && rc == 0; r++) {
+    long m = nS + r - 1;
+    for (int k = 0; k < Md; k++) {
+      double acc = 0.0;
+      double xprev = (n == 0) ? c[k] : prev[k];
+      for (long j = 1; j <= m; j++) {
+        double xj;
+        if (j >= nS) {
+          xj = c[(size_t)(j - nS) * Md + k];
+        } else {
+          long q = (j - 1) / S;
+          xj = prev[((size_t)q * (S + 1) + (size_t)(j - q * S)) * Md + k];
+        }
+        acc += oracle_bweight((double)(m + 1 - j), a) * (xj - xprev);
+        xprev = xj;
+      }
+      hist[k] = c[(size_t)(r - 1) * Md + k] - acc;
+    }
+    double tD = t_fine(p, m);
+    double tf = p->source_time ? t_fine(p, m + 1) : tD;
+    rc = oracle_step(p, c + (size_t)(r - 1) * Md, tD, tf, hist, tau, c + (size_t)r * Md);
+  }
+  if (rc == 0) memcpy(out, c + (size_t)S * Md, sizeof(double) * Md);
+  free(hist);
+  return rc;
+}
+
+/* Parareal (Section 2.2 and its flowchart); history = 1 runs the full-history variant (fine
+   propagator fine_F_full above, fixed point the uniform L1 solution of oracle_solve_serial
+   with history = 1).  Initial coarse sweep
    U^0_{n+1} = G_n(U^0_0..U^0_n); then for k = 0, 1, ...:
      parallel stage:   G_old(n) = G_n(U^k_0..U^k_n),  F_old(n) = F_n(U^k_0..U^k_n);
      sequential sweep: G_new(n) = G_n(U^{k+1}_0..U^{k+1}_n),
@@ -496,8 +544,9 @@ int oracle_solve_serial(const oracle_problem* p, const double* u0, double* U, do
 int oracle_solve_parareal(const oracle_problem* p, const double* u0, double* U,
                           int32_t max_iter, double tol, double* U_iters, double* incr,
                           int32_t* iters) {
-  if (oracle_validate(p) || p->history != 0 || max_iter < 0) return -1;
-  int Md = nmodes(p), P = p->slices;
+  if (oracle_validate(p) || max_iter < 0) return -1;
+  int Md = nmodes(p), P = p->slices, S = p->steps / p->slices;
+  int full = p->history == 1;
   size_t V = (size_t)(P + 1) * Md;
   double* Uk = (double*)malloc(sizeof(double) * V);
   double* Uk1 = (double*)malloc(sizeof(double) * V);
@@ -508,10 +557,29 @@ int oracle_solve_parareal(const oracle_problem* p, const double* u0, double* U,
   memcpy(Uk, u0, sizeof(double) * Md);
   for (int n = 0; n < P && rc == 0; n++) rc = oracle_coarse_G(p, n, Uk, Uk + (size_t)(n + 1) * Md);
   if (U_iters) memcpy(U_iters, Uk, sizeof(double) * V);
+  /* full history: the previous iterate's fine trajectory, slot by slot; before the first
+     sweep the linear interpolation of the coarse iterate over each slice */
+  size_t slotsz = (size_t)(S + 1) * Md;
+  double* prev = full ? (double*)malloc(sizeof(double) * (size_t)P * slotsz) : NULL;
+  double* cur = full ? (double*)malloc(sizeof(double) * (size_t)P * slotsz) : NULL;
+  if (full)
+    for (int q = 0; q < P; q++)
+      for (int t = 0; t <= S; t++)
+        for (int k = 0; k < Md; k++) {
+          double a0 = Uk[(size_t)q * Md + k], a1 = Uk[(size_t)(q + 1) * Md + k];
+          prev[(size_t)q * slotsz + (size_t)t * Md + k] = a0 + ((double)t / (double)S) * (a1 - a0);
+        }
   for (int k = 0; k < max_iter && rc == 0; k++) {
     for (int n = 0; n < P && rc == 0; n++) {
       rc = oracle_coarse_G(p, n, Uk, Gold + (size_t)n * Md);
-      if (rc == 0) rc = oracle_fine_F(p, n, Uk, Fold + (size_t)n * Md, NULL);
+      if (rc == 0)
+        rc = full ? fine_F_full(p, n, Uk, prev, Fold + (size_t)n * Md, cur + (size_t)n * slotsz)
+                  : oracle_fine_F(p, n, Uk, Fold + (size_t)n * Md, NULL);
+    }
+    if (full) {
+      double* t = prev;
+      prev = cur;
+      cur = t;
     }
     memcpy(Uk1, u0, sizeof(double) * Md);
     for (int n = 0; n < P && rc == 0; n++) {
@@ -536,6 +604,6 @@ int oracle_solve_parareal(const oracle_problem* p, const double* u0, double* U,
   }
   if (rc == 0) memcpy(U, Uk, sizeof(double) * V);
   if (iters) *iters = done;
-  free(Uk); free(Uk1); free(Gold); free(Fold); free(Gnew);
+  free(Uk); free(Uk1); free(Gold); free(Fold); free(Gnew); free(prev); free(cur);
   return rc;
 }

@@ -82,7 +82,9 @@ int    oracle_fine_F(const oracle_problem* p, int32_t n, const double* C, double
 /* Serial solve.  U: P+1 slice ends; traj: N+1 fine states (optional). */
 int    oracle_solve_serial(const oracle_problem* p, const double* u0, double* U, double* traj);
 
-/* Parareal.  U: final iterate (P+1 vectors).  U_iters: all iterates
+/* Parareal (history = 0: hybrid fine propagator; history = 1: full-history fine propagator
+   on the previous iterate's fine trajectory, fixed point = the uniform L1 serial solution).
+   U: final iterate (P+1 vectors).  U_iters: all iterates
    [max_iter+1][P+1][Md] (optional).  incr: relative increments [max_iter] (optional).
    *iters: number of fine sweeps done.  Returns 0. */
 int    oracle_solve_parareal(const oracle_problem* p, const double* u0, double* U,

@@ -521,3 +521,34 @@ def test_galerkin_rows_equal_full_galerkin_rows(orc):
         rows = [0, 3, len(c) - 1, len(c) // 2]
         Kr, Fr = orc.galerkin_rows(p, c, 0.25, 0.25, rows)
         assert np.array_equal(Kr, K[rows]) and np.array_equal(Fr, F), kw["dim"]
+
+
+def test_full_history_parareal_is_exact_against_uniform_l1(orc):
+    """Full-history parareal (fine steps on the previous iterate's whole fine trajectory): its
+    fixed point is the uniform L1 solution with full history.  After k sweeps the first k+1
+    slice ends equal that serial solution bit for bit, all of them after P sweeps; and the
+    error decreases at every sweep (a wrong weight index, a dropped boundary
+    term or a misplaced slice start breaks one of these)."""
+    from paper_2510_11023_amd import workloads as W
+
+    for kw in (dict(W.C2, modes=12, quad=24, steps=24, slices=4, alpha=0.4, history=1),
+               dict(W.C3, modes=3, quad=6, steps=12, slices=3, alpha=0.7, history=1),
+               dict(W.C2, modes=8, quad=16, steps=6, slices=6, alpha=0.5, history=1)):  # S = 1
+        p = orc.problem(**kw)
+        u0 = W.u0_batch_1d(kw["modes"], [9])[0] if kw["dim"] == 1 else W.u0_random_2d(kw["modes"], 9)
+        Us = orc.solve_serial(p, u0)
+        P = kw["slices"]
+        U, k, incr, its = orc.solve_parareal(p, u0, P, want_iterates=True)
+        assert k == P
+        for j in range(P + 1):
+            assert np.array_equal(its[j][: j + 1], Us[: j + 1]), (kw["dim"], j)
+        assert np.array_equal(U, Us)
+        err = [np.linalg.norm(its[j] - Us) / np.linalg.norm(Us) for j in range(P + 1)]
+        Uh = orc.solve_serial(orc.problem(**W.with_(kw, history=0)), u0)
+        if kw["steps"] == P:  # S = 1: the coarse step is the full-history fine step, and the
+            assert max(err) < 1e-14, err  # hybrid and full-history solutions coincide
+            assert np.linalg.norm(Uh - Us) <= 1e-14 * np.linalg.norm(Us)
+        else:
+            assert all(err[j + 1] < err[j] for j in range(P)) and err[P - 1] < 1e-2 * err[0], err
+            # it is not the hybrid solution: the two fixed points differ
+            assert np.linalg.norm(Uh - Us) > 1e-6 * np.linalg.norm(Us)
