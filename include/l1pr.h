@@ -89,7 +89,9 @@ typedef struct {
   double  d_param;      /* constant D for L1PR_D_CONST (> 0); the D of L1PR_F_MMS_SMOOTH */
   int32_t f_sel;        /* L1PR_F_*  */
   int32_t history;      /* 0: hybrid fine propagator (the paper's; parareal's fixed point)
-                           1: full uniform L1 over all N steps (serial only) */
+                           1: full uniform L1 over all N steps (serial; parareal with the plain
+                              coarse step, whose fine propagators then take the history of
+                              earlier slices from the previous iterate's fine trajectories) */
   int32_t source_time;  /* 0: f lagged to the previous level (the paper)
                            1: f at the new time level (only for u-independent f) */
   int32_t assembly;     /* how the stiffness sum_q w_q D_q phi_k'(x_q) phi_l'(x_q) is formed:
@@ -150,7 +152,15 @@ l1pr_status l1pr_fine_apply(const l1pr_problem* p, int32_t batch, const double* 
 enum { L1PR_COARSE_L1 = 0,       /* the coarse L1 step G of Section 2.1 */
        L1PR_COARSE_LEARNED = 1   /* G plus a learned residual correction (below) */ };
 
-/* Parareal solve of `batch` instances (hybrid history only), Section 2.2.
+/* Parareal solve of `batch` instances, Section 2.2.
+ * history = 0: the paper's hybrid fine propagator (coarse-grid history of earlier slices);
+ * the fixed point is l1pr_solve_serial with history 0.
+ * history = 1: full-history fine propagators: slice n's L1 history runs over the whole fine
+ * grid, the steps before nS taken from the previous iterate's fine trajectories (before the
+ * first sweep, the coarse iterate interpolated linearly over each slice); the fixed point is
+ * l1pr_solve_serial with history 1, reached bit for bit after P sweeps (the first k+1 slice
+ * ends after k sweeps).  Costs B*P*(2S+1)*Md doubles more workspace and one prefix launch
+ * per sweep.  Not with the learned coarse propagator, uneven batches or the batch call.
  *   max_iter : number of fine sweeps allowed, 0 <= max_iter <= P.
  *   tol      : > 0 stops after the sweep whose relative increment
  *              max_b ||U^{k+1}_b - U^k_b|| / ||U^{k+1}_b|| (Frobenius over all P+1 slice ends)

@@ -6,6 +6,8 @@
 //                   propagator of all B*P (instance, slice) units in lockstep (S steps,
 //                   units = B*P) followed by the sequential correction sweep (P steps,
 //                   units = B) and the increment reduction (Section 2.2, flowchart).
+//                   Full history: the fine sweep also reads the previous iterate's fine
+//                   trajectories (one prefix launch forms their share of every history sum).
 // Everything is enqueued on the caller's stream; nothing is allocated.
 #include <hip/hip_runtime.h>
 
@@ -32,6 +34,7 @@ struct Layout {
   size_t total = 0;
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
+  size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -75,7 +78,9 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.P = p->slices;
   tb.S = p->steps / p->slices;
   tb.B = B;
-  tb.LB = p->history == 1 ? p->steps + 1 : std::max(tb.S, tb.P) + 1;
+  // full history: b_0..b_N, plus 64 entries read (never used) by the prefix kernel's last
+  // step chunk
+  tb.LB = p->history == 1 ? p->steps + 1 + 64 : std::max(tb.S, tb.P) + 1;
   tb.d_sel = p->d_sel;
   tb.f_sel = p->f_sel;
   tb.source_time = p->source_time;
@@ -106,6 +111,10 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   if (para) {
     units = (size_t)B * P;
     L.traj = take(cur, D * units * (S + 1) * Mp);
+    if (p->history == 1) {
+      L.prev = take(cur, D * units * (S + 1) * Mp);
+      L.hp = take(cur, D * units * S * Mp);
+    }
   } else {
     units = B;
     L.traj = take(cur, D * B * ((p->history == 1 ? N : S) + 1) * Mp);
@@ -131,6 +140,7 @@ struct Ctx {
   Layout L;
   bool reg;      // register-resident step kernel (Mp <= 256)
   bool moments;  // stiffness from cosine moments, inside that kernel
+  bool full;     // parareal with full-history fine propagators
   char* ws;
   hipStream_t s;
   double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -151,7 +161,6 @@ struct Uneven {
 l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, void* ws,
                   size_t ws_bytes, void* stream, Ctx& c, const Uneven& un = Uneven()) {
   if (!valid(p) || B < 1 || !ws) return L1PR_EINVAL;
-  if (op == L1PR_OP_PARAREAL && p->history != 0) return L1PR_EINVAL;
   std::vector<double> al(B, p->alpha);
   if (alpha) {
     for (int b = 0; b < B; ++b) {
@@ -175,6 +184,7 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.cosq = c.ptr(c.L.cosq);
   c.reg = reg_path_ok(tb.Mp, tb.Qp);
   c.moments = c.reg && p->assembly == 0 && p->dim == 1;
+  c.full = op == L1PR_OP_PARAREAL && p->history == 1;
   const double* alpha_dev = c.ptr(c.L.alpha);
   if (un.alpha)  // device array of the caller (nothing is copied, so the call can be captured)
     alpha_dev = un.alpha;
@@ -401,12 +411,20 @@ l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e, const
   return L1PR_OK;
 }
 
-// All B*P fine propagators at once on the slice ends Z: traj[b*P + n][r] = c_{n,r}.
-l1pr_status fine_sweep(const Ctx& c, const double* Z) {
+// All B*P fine propagators at once on the slice ends Z: traj[b*P + n][r] = c_{n,r}.  With
+// prev set (full history), the history of slice n also runs over the earlier slices' states
+// in prev (the previous iterate's trajectories); their part of each sum is formed first, for
+// every (slice, step), into hp.
+l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double* prev) {
   const Tables& tb = c.tb;
   const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp;
   const long slotS = (long)(S + 1) * Mp;
-  double* traj = c.ptr(c.L.traj);
+  double* hp = prev ? c.ptr(c.L.hp) : nullptr;
+  if (prev) {
+    StepArgs a = base_args(c);
+    a.mode = MODE_FINE;
+    L1PR_TRY(timed("prefix", a, B * P, c.s, [&] { return launch_hist_prefix(tb, prev, hp, c.s); }));
+  }
   L1PR_TRY(launch_fill_slot0(tb, Z, traj, B, P, c.s));
   for (int r = 1; r <= S; ++r) {
     StepArgs a = base_args(c);
@@ -418,6 +436,8 @@ l1pr_status fine_sweep(const Ctx& c, const double* Z) {
     a.trajP = P;
     a.trajN0 = 0;
     a.Z = Z;
+    a.prev = prev;
+    a.hp = hp;
     Epilogue e{};  // row r, and row S at the instance's last step of the slice
     e.kind = EPI_STORE;
     e.out = traj + (long)r * Mp;
@@ -449,6 +469,8 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   double* Zk1 = c.ptr(c.L.Z1);
   double* Gold = c.ptr(c.L.Gold);
   double* traj = c.ptr(c.L.traj);
+  // full history: the previous iterate's fine trajectories (swapped with traj every sweep)
+  double* prev = c.full ? c.ptr(c.L.prev) : nullptr;
   double* incrk = c.ptr(c.L.incrk);
   const long iterStride = (long)B * (P + 1) * M;
 
@@ -467,13 +489,15 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   }
   if (U_iters) L1PR_TRY(launch_unpack(Zk, Mp, vecP, U_iters, M, (long)(P + 1) * M, P + 1, B, c.s));
   if (tr.stamps) L1PR_TRY(launch_stamp(tr.stamps, c.s));
+  // before the first sweep the history of earlier slices is the interpolated coarse iterate
+  if (prev) L1PR_TRY(launch_interp_slots(tb, Zk, prev, c.s));
 
   int done = 0;
   bool met = false;
   std::vector<double> h_incr(B);
   for (int k = 0; k < max_iter; ++k) {
     // parallel stage: F_old(n) = F_n(U^k_0..U^k_n) for all (b, n)
-    l1pr_status stf = fine_sweep(c, Zk);
+    l1pr_status stf = fine_sweep(c, Zk, traj, prev);
     if (stf != L1PR_OK) return stf;
     // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n))
     L1PR_TRY(launch_pack(u0, M, B, M, Zk1, Mp, vecP, c.s));
@@ -496,6 +520,7 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
       L1PR_TRY(launch_unpack(Zk1, Mp, vecP, U_iters + (long)(k + 1) * iterStride, M,
                              (long)(P + 1) * M, P + 1, B, c.s));
     std::swap(Zk, Zk1);
+    if (prev) std::swap(traj, prev);
     done = k + 1;
     if (done >= P) {
       met = true;
@@ -566,7 +591,7 @@ l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const d
     if (coarse != L1PR_COARSE_L1 && coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
     const bool learned = coarse == L1PR_COARSE_LEARNED;
     if (learned && (!mlp_params || ((uintptr_t)mlp_params & 255) || p->dim != 1 ||
-                    p->modes > kMlpMaxModes))
+                    p->modes > kMlpMaxModes || p->history != 0))
       return L1PR_EINVAL;
     Ctx c;
     l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
@@ -804,7 +829,7 @@ l1pr_status l1pr_fine_apply(const l1pr_problem* p, int32_t batch, const double* 
     const long vecP = (long)(P + 1) * Mp;
     double* Zp = c.ptr(c.L.Z0);
     L1PR_TRY(launch_unpack_pad(Z, M, (long)(P + 1) * M, Zp, Mp, vecP, P + 1, B, c.s));
-    st = fine_sweep(c, Zp);
+    st = fine_sweep(c, Zp, c.ptr(c.L.traj), nullptr);
     if (st != L1PR_OK) return st;
     // slot b*P + n, row S  ->  out[b][n]
     L1PR_TRY(launch_unpack(c.ptr(c.L.traj) + (long)S * Mp, Mp, (long)(S + 1) * Mp, out, M, M, 1,

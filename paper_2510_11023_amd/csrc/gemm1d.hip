@@ -147,7 +147,12 @@ __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double
   const UnitView v = decode_unit(tb, a, u);
   const double* bw = tb.bw + (long)v.b * tb.LB;
   const int Mp = tb.Mp;
+  const bool full_fine = a.mode == MODE_FINE && a.prev;
   for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < Mp; k += blockDim.x * gridDim.y) {
+    if (full_fine) {
+      hist[(long)u * Mp + k] = full_fine_history(tb, a, v, k);
+      continue;
+    }
     const double* y = v.y + k;
     double acc = 0.0;
     double prev = y[0];
@@ -155,15 +160,15 @@ __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double
     for (; i + 3 <= v.L; i += 4) {
       const double y1 = y[(long)i * Mp], y2 = y[(long)(i + 1) * Mp];
       const double y3 = y[(long)(i + 2) * Mp], y4 = y[(long)(i + 3) * Mp];
-      acc += bw[v.L + 1 - i] * (y1 - prev);
-      acc += bw[v.L - i] * (y2 - y1);
-      acc += bw[v.L - 1 - i] * (y3 - y2);
-      acc += bw[v.L - 2 - i] * (y4 - y3);
+      acc = fma(bw[v.L + 1 - i], y1 - prev, acc);
+      acc = fma(bw[v.L - i], y2 - y1, acc);
+      acc = fma(bw[v.L - 1 - i], y3 - y2, acc);
+      acc = fma(bw[v.L - 2 - i], y4 - y3, acc);
       prev = y4;
     }
     for (; i <= v.L; ++i) {
       const double yi = y[(long)i * Mp];
-      acc += bw[v.L + 1 - i] * (yi - prev);
+      acc = fma(bw[v.L + 1 - i], yi - prev, acc);
       prev = yi;
     }
     double h = y[(long)v.L * Mp] - acc;

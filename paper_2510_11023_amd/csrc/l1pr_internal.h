@@ -72,6 +72,11 @@ struct StepArgs {
   double* F;        // [units][Mp]   load vector
   double* C2;       // 2D: [units][Mp] lagged states
   double* T2;       // 2D: [units][Qp Jp] intermediate products
+  // full-history fine steps (MODE_FINE with prev set): the previous iterate's fine
+  // trajectories, slots [B*P][S+1][Mp] as traj, and the prefix sums over earlier slices,
+  // hp[B*P][S][Mp] (row r-1 of slot b*P + n for step r); both nullptr otherwise
+  const double* prev;
+  const double* hp;
 };
 
 struct Epilogue {
@@ -201,6 +206,38 @@ __device__ inline UnitView decode_unit(const Tables& tb, const StepArgs& a, int 
   return v;
 }
 
+// Full-history fine step r of slice n (Section 2.2 with the history taken over the whole
+// fine grid): y_m - sum_{j=1}^{m} b_{m+1-j} (x_j - x_{j-1}), m = nS + r - 1, where x_j for
+// j < nS are the previous iterate's fine states (row t = j - qS of slot q = (j-1)/S, x_0 =
+// slot 0 row 0) and x_j for j >= nS the slice's own states, row j - nS.  The terms j < nS
+// come first in the ascending sum and are known before the sweep, so their partial sum is
+// read from hp; the loop continues it with the same fma sequence as the full-history serial
+// step, which makes the result bit-for-bit that step's when the states agree.
+__device__ inline double full_fine_history(const Tables& tb, const StepArgs& a,
+                                           const UnitView& v, int k) {
+  const int S = tb.S, Mp = tb.Mp;
+  const long nS = (long)v.n * S, m = nS + a.r - 1;
+  const double* bw = tb.bw + (long)v.b * tb.LB;
+  const double* y = v.y + k;
+  double acc, xp;
+  int i = 0;
+  if (v.n == 0) {
+    acc = 0.0;
+    xp = y[0];
+    i = 1;
+  } else {
+    acc = a.hp[(v.slot * S + (a.r - 1)) * (long)Mp + k];
+    const long j = nS - 1, q = j > 0 ? (j - 1) / S : 0, t = j - q * S;
+    xp = a.prev[((v.slot - v.n + q) * (S + 1) + t) * (long)Mp + k];
+  }
+  for (; i < a.r; ++i) {
+    const double x = y[(long)i * Mp];
+    acc = fma(bw[m + 1 - (nS + i)], x - xp, acc);
+    xp = x;
+  }
+  return y[(long)(a.r - 1) * Mp] - acc;
+}
+
 // Where the new value x of entry k of unit u goes.  Fine steps: the trajectory row `out` at
 // every step of the unit and, at the instance's last step of the slice (r == Sb), the slice
 // end `gold` as well when it is set.  Other steps: by kind (STORE, STORE2 = also gold,
@@ -231,6 +268,9 @@ hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, con
 hipError_t launch_form_rhs(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
 hipError_t launch_identity(double* A, int units, int n, hipStream_t s);
+// full-history parareal (histfull.hip)
+hipError_t launch_interp_slots(const Tables& tb, const double* Z, double* prev, hipStream_t s);
+hipError_t launch_hist_prefix(const Tables& tb, const double* prev, double* hp, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 // blocked factorisation and solve through device memory (chol_blk.hip): A and rhs of the

@@ -49,10 +49,14 @@ __global__ __launch_bounds__(256) void k_eval1d(Tables tb, StepArgs a) {
   for (int k = tid; k < Mp; k += blockDim.x) {
     double F = 0.0;
     for (int q = 0; q < Qp; ++q) F += tb.phi[(long)q * Mp + k] * sg[q];
+    if (a.mode == MODE_FINE && a.prev) {
+      a.rhs[(long)u * Mp + k] = full_fine_history(tb, a, v, k) + tau * F;
+      continue;
+    }
     // in-sequence L1 history: y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1})
     double acc = 0.0;
     for (int i = 1; i <= v.L; ++i)
-      acc += bw[v.L + 1 - i] * (v.y[(long)i * Mp + k] - v.y[(long)(i - 1) * Mp + k]);
+      acc = fma(bw[v.L + 1 - i], v.y[(long)i * Mp + k] - v.y[(long)(i - 1) * Mp + k], acc);
     double h = v.y[(long)v.L * Mp + k] - acc;
     if (a.mode == MODE_FINE) {
       // coarse-grid history of the hybrid operator: S^-a sum_{i=1}^{n} b_{n-i+r/S} (C_i - C_{i-1})

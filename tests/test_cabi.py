@@ -54,6 +54,23 @@ def test_host_entry_points(L):
                                  1 << 30, None) == -1
 
 
+def test_full_history_parareal_workspace_and_limits(L):
+    """Full-history parareal keeps the previous iterate's trajectories and the prefix sums
+    (B*P*(2S+1)*Mp doubles more); the learned coarse propagator is refused with it."""
+    from paper_2510_11023_amd import make_problem, workloads as W
+
+    kw = W.with_(W.C2, modes=48, steps=120, slices=6)
+    B, P, S, Mp = 3, 6, 20, 48
+    hyb = L.l1pr_workspace_bytes(ctypes.byref(make_problem(**kw)), B, 1)
+    full = L.l1pr_workspace_bytes(ctypes.byref(make_problem(**W.with_(kw, history=1))), B, 1)
+    extra = B * P * (2 * S + 1) * Mp * 8
+    assert extra <= full - hyb <= extra + B * (120 + 65) * 8 + 3 * 256
+    u = ctypes.c_void_p(256)
+    ph = make_problem(**W.with_(kw, history=1))
+    assert L.l1pr_solve_parareal_ex(ctypes.byref(ph), B, None, u, u, 2, 0.0, 1, u, None, None,
+                                    None, u, 1 << 30, None) == -1
+
+
 def test_product_path_has_no_cpu_fallback():
     """The package never imports the oracle, and the binding raises if the library is missing."""
     pkg = os.path.join(ROOT, "paper_2510_11023_amd")
