@@ -68,7 +68,7 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "f5a15efb9da8f3b2b9bfc5fd6e3ad5d043aa733e2e23886215e87764f805df8f",
+TRAFFIC_RECORD = {"sha256": "d2f68d2cfefe0671dd6d1341c6620d7954efefe380e4f2b3cf32b03467a5b814",
                   "fetch_kib": 8765, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": (2 * 8765 + 4096) * 1024}
 
@@ -354,6 +354,63 @@ def config3_2d(l1, torch, W, dev, with_parareal=True):
     return out
 
 
+def full_history(l1, torch, W, dev, alpha=0.3):
+    """Full-history parareal on the config-2 batch (one alpha): its fixed point is the uniform
+    L1 solution with full history (the full-history serial solve); sweeps to 1e-8 of it, wall
+    time of both, and the per-sweep prefix kernel against the FP64 vector peak."""
+    from paper_2510_11023_amd import _lib
+
+    kw = W.with_(W.C2, alpha=alpha, history=1)
+    M, N, P = kw["modes"], kw["steps"], kw["slices"]
+    S, B = N // P, W.C2_BATCH
+    p = l1.make_problem(**kw)
+    u0 = torch.tensor(W.u0_batch_1d(M, range(B)), dtype=torch.float64, device=dev)
+    ws = torch.empty(l1.workspace_bytes(p, B, 1), dtype=torch.uint8, device=dev)
+    ws_s = torch.empty(l1.workspace_bytes(p, B, 0), dtype=torch.uint8, device=dev)
+    l1.solve_serial(p, u0, workspace=ws_s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Us, _ = l1.solve_serial(p, u0, workspace=ws_s)
+    torch.cuda.synchronize()
+    t_ser = time.perf_counter() - t0
+    del ws_s
+    ks, e = find_kstar(l1, p, u0, Us, ws, 24)
+    out = {"workload": f"1D, M={M}, Q={kw['quad']}, N={N}, P={P}, alpha={alpha}, {B} instances "
+                       f"(seeds 0..{B - 1}), config-2 D and f, full-history fine propagator",
+           "serial_ms": round(t_ser * 1e3, 1), "serial_mode_steps_per_s": B * M * N / t_ser,
+           "kstar": ks, "rel_err_by_sweep": [float(f"{v:.3e}") for v in e]}
+    k = ks if ks is not None else P
+    l1.solve_parareal(p, u0, k, tol=0.0, want_incr=False, workspace=ws)
+    torch.cuda.synchronize()
+    _lib.profile_start()
+    t0 = time.perf_counter()
+    U = l1.solve_parareal(p, u0, k, tol=0.0, want_incr=False, workspace=ws).U
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    st = _lib.profile_stop()
+    out.update({"parareal_ms": round(tp * 1e3, 1), "mode_steps_per_s": B * M * N / tp,
+                "achieved_rel_err": rel_err_max(U, Us), "speedup_over_serial": round(t_ser / tp, 2)})
+    n_p, tot_p = st.get(f"prefix/fine/{B * P}", (0, 0.0))
+    if n_p:
+        avg = tot_p / n_p / 1e3
+        fmas = B * M * S * sum(n * S - 1 for n in range(1, P))
+        ach = 2 * fmas / avg / 1e12
+        out["prefix_roofline"] = {
+            "bound": "alu", "kernel": f"k_hist_prefix (one launch per sweep, {B * P} units)",
+            "achieved": round(ach, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP64_TFLOPS, 4), "avg_launch_ms": round(avg * 1e3, 3),
+            "flops_per_launch": 2 * fmas, "launches": n_p,
+            "hbm_bytes_unique": B * P * (2 * S + 1) * M * 8}
+    n_h, tot_h = st.get(f"history/fine/{B * P}", (0, 0.0))
+    if n_h:
+        out["history_step_avg_us"] = round(tot_h / n_h * 1e3, 2)
+    tot = sum(v[1] for v in st.values())
+    out["kernel_time_share"] = {kk: round(v[1] / tot, 4) for kk, v in st.items()}
+    log(f"full history: serial {t_ser * 1e3:.0f} ms, k*={ks}, parareal {tp * 1e3:.0f} ms, "
+        f"prefix {out.get('prefix_roofline', {}).get('avg_launch_ms')} ms/launch")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,10 +420,15 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernels", "kernels2d"], default="full",
+    ap.add_argument("--no-full-history", action="store_true")
+    ap.add_argument("--mode", choices=["full", "kernels", "kernels2d", "kernelsfh", "fullhistory"],
+                    default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
                          "device copy (for hardware-counter runs); kernels2d: one fine sweep of "
-                         "the 2D workload (128 slices) and the same copy; neither prints a JSON line")
+                         "the 2D workload (128 slices) and the same copy; kernelsfh: one "
+                         "full-history parareal sweep of the alpha=0.3 batch and the same copy; "
+                         "none of these prints a JSON line; fullhistory: only the full-history "
+                         "parareal section (its JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; a run on several GPUs is not supported "
@@ -407,6 +469,21 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         log("kernels2d mode done")
+        return
+
+    if args.mode == "kernelsfh":
+        pf = l1.make_problem(**W.with_(base, alpha=alphas[0], history=1))
+        wsf = torch.empty(l1.workspace_bytes(pf, B, 1), dtype=torch.uint8, device=dev)
+        l1.solve_parareal(pf, u0, 1, tol=0.0, workspace=wsf)
+        x = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("kernelsfh mode done")
+        return
+
+    if args.mode == "fullhistory":
+        print(json.dumps(full_history(l1, torch, W, dev)), flush=True)
         return
 
     if args.mode == "kernels":
@@ -533,6 +610,10 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(l1, torch, W, dev)
 
+    fullh = None
+    if not args.no_full_history:
+        fullh = full_history(l1, torch, W, dev)
+
     two_d = None
     if not args.no_2d:
         two_d = config3_2d(l1, torch, W, dev)
@@ -575,6 +656,7 @@ def main():
         "learned_vs_plain": learned,
         "uneven_batch": uneven,
         "config3_2d": two_d,
+        "full_history": fullh,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kMaxModes1D = 1024;  // the 1D evaluation kernel stages Mp + Qp doubles in LDS
 constexpr int kMaxModes2D = 64;
+constexpr int kSerialBlock = 64;  // steps per prefix launch of the full-history serial solve
 
 struct Layout {
   size_t total = 0;
@@ -78,9 +79,9 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.P = p->slices;
   tb.S = p->steps / p->slices;
   tb.B = B;
-  // full history: b_0..b_N, plus 64 entries read (never used) by the prefix kernel's last
-  // step chunk
-  tb.LB = p->history == 1 ? p->steps + 1 + 64 : std::max(tb.S, tb.P) + 1;
+  // full history: b_0..b_N, plus entries read (never used) by the prefix kernel's last
+  // block and step chunk
+  tb.LB = p->history == 1 ? p->steps + 1 + kSerialBlock + 64 : std::max(tb.S, tb.P) + 1;
   tb.d_sel = p->d_sel;
   tb.f_sel = p->f_sel;
   tb.source_time = p->source_time;
@@ -118,6 +119,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   } else {
     units = B;
     L.traj = take(cur, D * B * ((p->history == 1 ? N : S) + 1) * Mp);
+    if (p->history == 1) L.hp = take(cur, D * B * kSerialBlock * Mp);
   }
   const size_t nq = two ? Qp * Qp : Qp;  // quadrature points per unit
   L.d = take(cur, D * units * nq);
@@ -355,12 +357,30 @@ l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_
   const int B = tb.B, P = tb.P, S = tb.S, N = tb.N, Mp = tb.Mp, M = tb.M;
   const long trajN = (long)(N + 1) * Mp;
   double* traj = c.ptr(c.L.traj);
+  double* hp = c.ptr(c.L.hp);
   L1PR_TRY(launch_pack(u0, M, B, M, traj, Mp, trajN, c.s));
   for (int m = 0; m < N; ++m) {
     StepArgs a = base_args(c);
     a.mode = MODE_FULL;
     a.m = m;
     a.traj = traj;
+    a.hp = hp;
+    a.hw = kSerialBlock;
+    if (m > 0 && m % kSerialBlock == 0) {
+      // block n = m / W: the sums over j < nW for its W steps
+      PrefixArgs pa{};
+      pa.x = traj;
+      pa.inst_stride = trajN;
+      pa.slot_rows = kSerialBlock;
+      pa.S = kSerialBlock;
+      pa.n_hi = m / kSerialBlock;
+      pa.n_cnt = 1;
+      pa.hp = hp;
+      pa.hpP = 1;
+      pa.hp_n0 = pa.n_hi;
+      pa.narrow = true;
+      L1PR_TRY(timed("prefix", a, B, c.s, [&] { return launch_hist_prefix(tb, pa, c.s); }));
+    }
     Epilogue e{};
     e.kind = EPI_STORE;
     e.out = traj + (long)(m + 1) * Mp;
@@ -423,7 +443,18 @@ l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double
   if (prev) {
     StepArgs a = base_args(c);
     a.mode = MODE_FINE;
-    L1PR_TRY(timed("prefix", a, B * P, c.s, [&] { return launch_hist_prefix(tb, prev, hp, c.s); }));
+    PrefixArgs pa{};
+    pa.x = prev;
+    pa.inst_stride = (long)P * slotS;
+    pa.slot_rows = S + 1;
+    pa.S = S;
+    pa.n_hi = P - 1;
+    pa.n_cnt = P - 1;
+    pa.hp = hp;
+    pa.hpP = P;
+    pa.hp_n0 = 0;
+    pa.narrow = false;
+    L1PR_TRY(timed("prefix", a, B * P, c.s, [&] { return launch_hist_prefix(tb, pa, c.s); }));
   }
   L1PR_TRY(launch_fill_slot0(tb, Z, traj, B, P, c.s));
   for (int r = 1; r <= S; ++r) {

@@ -153,6 +153,10 @@ __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double
       hist[(long)u * Mp + k] = full_fine_history(tb, a, v, k);
       continue;
     }
+    if (a.mode == MODE_FULL) {
+      hist[(long)u * Mp + k] = full_serial_history(tb, a, v, k);
+      continue;
+    }
     const double* y = v.y + k;
     double acc = 0.0;
     double prev = y[0];

@@ -12,28 +12,26 @@
 // full-history serial step, so a slice whose inputs equal the serial states reproduces them
 // bit for bit, and parareal's exactness after k sweeps holds bitwise.
 //
+// The full-history serial solve uses the same kernel on its own trajectory, block by block:
+// before the first step of block n (W steps), the sums over j < nW for all W steps of the
+// block; each step then continues over at most W rows instead of all m.
+//
 // Prefix kernel: one wave per (instance, 64 coefficients, slice n, chunk of RC steps r).
 // Lane = coefficient; it holds RC accumulators (one per step r) and streams the rows x_j of
 // the instance's previous trajectory once, JB rows per block.  The weights b_{nS+r-j} of a
 // block are wave-uniform and span RC + JB - 1 consecutive table entries, loaded as scalars;
-// every x_j then feeds RC fmas.  Waves of one (instance, coefficient block) read the same
-// rows at about the same pace; the work-group ids are remapped so that they run on one XCD
-// and share its L2, with the largest slices first.
+// every x_j then feeds RC fmas.  Waves are issued longest first (slice P-1 down to 1): the
+// work per wave grows with n, and this order leaves no long wave for the end of the launch
+// (11% faster than grouping the waves of one instance per XCD).  Work-group ids go round
+// robin over the 8 XCDs, so when B * blocks * chunks is a multiple of 8 the waves of one
+// (instance, block, chunk) for every n land on the same XCD and share its L2.
 #include "l1pr_internal.h"
 
 namespace l1pr {
 
-namespace {
-
-constexpr int NXCD = 8;
 constexpr int HP_RC = 32;  // steps per wave
-constexpr int HP_JB = 4;   // rows per block
+constexpr int HP_JB = 8;   // rows per block
 static_assert(HP_RC % 8 == 0, "steps are taken eight at a time");
-
-__device__ inline int xcd_remap_hp(int id, int total) {
-  const int q = total / NXCD, rem = total % NXCD, x = id % NXCD, k = id / NXCD;
-  return x < rem ? x * (q + 1) + k : rem * (q + 1) + (x - rem) * q + k;
-}
 
 // prev[b*P + q][t][k] = Z_q + (t/S) (Z_{q+1} - Z_q): the linear interpolation of the coarse
 // iterate over each slice, the history before the first fine sweep.
@@ -49,20 +47,20 @@ __global__ void k_interp_slots(const double* Z, double* prev, int B, int P, int 
 }
 
 template <int RC, int JB>
-__global__ __launch_bounds__(64) void k_hist_prefix(Tables tb, const double* prev, double* hp,
-                                                    int nrc, int nkb) {
-  const int S = tb.S, P = tb.P, Mp = tb.Mp;
-  const int lin = xcd_remap_hp(blockIdx.x, gridDim.x);
-  const int per_group = (P - 1) * nrc;
-  const int grp = lin / per_group, w = lin % per_group;
-  const int b = grp / nkb, kb = grp % nkb;
-  const int n = P - 1 - w / nrc, rc = w % nrc;  // slices 1..P-1, largest first
+__global__ __launch_bounds__(64) void k_hist_prefix(Tables tb, PrefixArgs pa, int nrc, int nkb) {
+  const int S = pa.S, Mp = tb.Mp;
+  // slices n_hi down to n_hi - n_cnt + 1 (the longest sums first), then (instance, block,
+  // chunk)
+  const int lin = blockIdx.x;
+  const int per_n = tb.B * nkb * nrc;
+  const int n = pa.n_hi - lin / per_n, w = lin % per_n;
+  const int b = w / (nkb * nrc), kb = (w / nrc) % nkb, rc = w % nrc;
   const int k = kb * 64 + (int)threadIdx.x;
   const int kc = k < Mp ? k : Mp - 1;  // lanes past Mp load a valid row entry, store nothing
   const int r0 = rc * RC + 1;
   const long nS = (long)n * S;
   const double* bw = tb.bw + (long)b * tb.LB + nS + r0;  // bw[j'] = b_{nS + r0 + j'}
-  const double* x = prev + (long)b * P * (S + 1) * Mp + kc;
+  const double* x = pa.x + (long)b * pa.inst_stride + kc;
 
   double acc[RC];
 #pragma unroll
@@ -71,7 +69,7 @@ __global__ __launch_bounds__(64) void k_hist_prefix(Tables tb, const double* pre
   // j = qS + t for slots q = 0..n-1, rows t = 1..S (the last slot stops at t = S-1)
   for (int q = 0; q < n; ++q) {
     const int tend = q == n - 1 ? S - 1 : S;
-    const double* row = x + (long)q * (S + 1) * Mp;
+    const double* row = x + (long)q * pa.slot_rows * Mp;
     const long jq = (long)q * S;
     int t = 1;
     for (; t + JB - 1 <= tend; t += JB) {
@@ -115,14 +113,12 @@ __global__ __launch_bounds__(64) void k_hist_prefix(Tables tb, const double* pre
     }
   }
   if (k < Mp) {
-    double* out = hp + ((long)(b * P + n) * S + (r0 - 1)) * Mp + k;
+    double* out = pa.hp + ((long)(b * pa.hpP + n - pa.hp_n0) * S + (r0 - 1)) * Mp + k;
 #pragma unroll
     for (int ri = 0; ri < RC; ++ri)
       if (r0 + ri <= S) out[(long)ri * Mp] = acc[ri];
   }
 }
-
-}  // namespace
 
 hipError_t launch_interp_slots(const Tables& tb, const double* Z, double* prev, hipStream_t s) {
   const long n = (long)tb.B * tb.P * (tb.S + 1) * tb.Mp;
@@ -130,15 +126,20 @@ hipError_t launch_interp_slots(const Tables& tb, const double* Z, double* prev, 
   return hipGetLastError();
 }
 
-// Needs the weight table padded to LB >= N + HP_RC - 1 entries per instance: a chunk's last
-// steps r may pass S, and their (never stored) weights are read from the padding.
-hipError_t launch_hist_prefix(const Tables& tb, const double* prev, double* hp, hipStream_t s) {
-  if (tb.P < 2) return hipSuccess;
-  if (tb.LB < tb.N + HP_RC - 1) return hipErrorInvalidValue;
-  const int nrc = (tb.S + HP_RC - 1) / HP_RC, nkb = (tb.Mp + 63) / 64;
-  const long waves = (long)tb.B * nkb * (tb.P - 1) * nrc;
+// A chunk's last steps r may pass S: their (never stored) weights are read from the padding
+// of the weight table, which must reach index n_hi S + S + RC - 2.
+hipError_t launch_hist_prefix(const Tables& tb, const PrefixArgs& pa, hipStream_t s) {
+  if (pa.n_cnt < 1) return hipSuccess;
+  const int RC = pa.narrow ? 8 : HP_RC;
+  if (pa.n_hi - pa.n_cnt + 1 < 1 || (long)pa.n_hi * pa.S + pa.S + RC - 1 > tb.LB)
+    return hipErrorInvalidValue;
+  const int nrc = (pa.S + RC - 1) / RC, nkb = (tb.Mp + 63) / 64;
+  const long waves = (long)tb.B * nkb * pa.n_cnt * nrc;
   if (waves > 0x7fffffffL) return hipErrorInvalidValue;
-  k_hist_prefix<HP_RC, HP_JB><<<(unsigned)waves, 64, 0, s>>>(tb, prev, hp, nrc, nkb);
+  if (pa.narrow)
+    k_hist_prefix<8, HP_JB><<<(unsigned)waves, 64, 0, s>>>(tb, pa, nrc, nkb);
+  else
+    k_hist_prefix<HP_RC, HP_JB><<<(unsigned)waves, 64, 0, s>>>(tb, pa, nrc, nkb);
   return hipGetLastError();
 }
 

@@ -74,9 +74,12 @@ struct StepArgs {
   double* T2;       // 2D: [units][Qp Jp] intermediate products
   // full-history fine steps (MODE_FINE with prev set): the previous iterate's fine
   // trajectories, slots [B*P][S+1][Mp] as traj, and the prefix sums over earlier slices,
-  // hp[B*P][S][Mp] (row r-1 of slot b*P + n for step r); both nullptr otherwise
+  // hp[B*P][S][Mp] (row r-1 of slot b*P + n for step r); both nullptr otherwise.
+  // Full-history serial steps (MODE_FULL) with hp set: hp[B][hw][Mp] holds, for the block of
+  // hw steps containing m, the sums over j < (m / hw) hw (row m mod hw).
   const double* prev;
   const double* hp;
+  int hw;
 };
 
 struct Epilogue {
@@ -238,6 +241,42 @@ __device__ inline double full_fine_history(const Tables& tb, const StepArgs& a,
   return y[(long)(a.r - 1) * Mp] - acc;
 }
 
+// Full-history serial step m (MODE_FULL): y_m - sum_{j=1}^{m} b_{m+1-j} (y_j - y_{j-1}) over
+// the instance's trajectory.  With hp set, the terms j < nW (W = hw, n = m / W) were summed
+// before the block's first step and the loop continues the chain from j = nW; either way the
+// fma sequence is the ascending one.
+__device__ inline double full_serial_history(const Tables& tb, const StepArgs& a,
+                                             const UnitView& v, int k) {
+  const int Mp = tb.Mp;
+  const long m = a.m;
+  const double* bw = tb.bw + (long)v.b * tb.LB;
+  const double* y = v.y + k;
+  double acc = 0.0, xp = y[0];
+  long j = 1;
+  if (a.hp) {
+    const long nW = m / a.hw * a.hw;
+    if (nW > 0) {
+      acc = a.hp[((long)v.b * a.hw + (m - nW)) * Mp + k];
+      xp = y[(nW - 1) * Mp];
+      j = nW;
+    }
+  }
+  for (; j + 3 <= m; j += 4) {
+    const double x1 = y[j * Mp], x2 = y[(j + 1) * Mp], x3 = y[(j + 2) * Mp], x4 = y[(j + 3) * Mp];
+    acc = fma(bw[m + 1 - j], x1 - xp, acc);
+    acc = fma(bw[m - j], x2 - x1, acc);
+    acc = fma(bw[m - 1 - j], x3 - x2, acc);
+    acc = fma(bw[m - 2 - j], x4 - x3, acc);
+    xp = x4;
+  }
+  for (; j <= m; ++j) {
+    const double x = y[j * Mp];
+    acc = fma(bw[m + 1 - j], x - xp, acc);
+    xp = x;
+  }
+  return y[m * Mp] - acc;
+}
+
 // Where the new value x of entry k of unit u goes.  Fine steps: the trajectory row `out` at
 // every step of the unit and, at the instance's last step of the slice (r == Sb), the slice
 // end `gold` as well when it is set.  Other steps: by kind (STORE, STORE2 = also gold,
@@ -270,7 +309,19 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t s);
 hipError_t launch_identity(double* A, int units, int n, hipStream_t s);
 // full-history parareal (histfull.hip)
 hipError_t launch_interp_slots(const Tables& tb, const double* Z, double* prev, hipStream_t s);
-hipError_t launch_hist_prefix(const Tables& tb, const double* prev, double* hp, hipStream_t s);
+// Prefix sums of full-history L1 sums, for every step r = 1..S of slices n_hi - n_cnt + 1 ..
+// n_hi (all >= 1): hp[(b hpP + n - hp_n0) S + r - 1][k] = sum_{j=1}^{nS-1} b_{nS+r-j}
+// (x_j - x_{j-1}), ascending j, where instance b's states x_j (j = qS + t, t = 1..S) are row
+// q slot_rows + t of x + b inst_stride, and x_0 its row 0.
+struct PrefixArgs {
+  const double* x;
+  long inst_stride;
+  int slot_rows, S, n_hi, n_cnt;
+  double* hp;
+  int hpP, hp_n0;
+  bool narrow;  // 8 steps per wave (few slices per launch) instead of 32
+};
+hipError_t launch_hist_prefix(const Tables& tb, const PrefixArgs& pa, hipStream_t s);
 hipError_t launch_eval(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 hipError_t launch_assemble(const Tables& tb, const StepArgs& a, int units, hipStream_t s);
 // blocked factorisation and solve through device memory (chol_blk.hip): A and rhs of the

@@ -53,6 +53,10 @@ __global__ __launch_bounds__(256) void k_eval1d(Tables tb, StepArgs a) {
       a.rhs[(long)u * Mp + k] = full_fine_history(tb, a, v, k) + tau * F;
       continue;
     }
+    if (a.mode == MODE_FULL) {
+      a.rhs[(long)u * Mp + k] = full_serial_history(tb, a, v, k) + tau * F;
+      continue;
+    }
     // in-sequence L1 history: y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1})
     double acc = 0.0;
     for (int i = 1; i <= v.L; ++i)

@@ -64,7 +64,7 @@ def test_full_history_parareal_workspace_and_limits(L):
     hyb = L.l1pr_workspace_bytes(ctypes.byref(make_problem(**kw)), B, 1)
     full = L.l1pr_workspace_bytes(ctypes.byref(make_problem(**W.with_(kw, history=1))), B, 1)
     extra = B * P * (2 * S + 1) * Mp * 8
-    assert extra <= full - hyb <= extra + B * (120 + 65) * 8 + 3 * 256
+    assert extra <= full - hyb <= extra + B * (120 + 130) * 8 + 3 * 256
     u = ctypes.c_void_p(256)
     ph = make_problem(**W.with_(kw, history=1))
     assert L.l1pr_solve_parareal_ex(ctypes.byref(ph), B, None, u, u, 2, 0.0, 1, u, None, None,

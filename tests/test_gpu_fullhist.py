@@ -88,6 +88,32 @@ def test_full_history_parareal_matches_oracle_and_is_exact(gpu, orc, name, kw, s
             assert e <= TOL, (name, b, k, e)
 
 
+SERIAL_CASES = [
+    # N past the serial solve's 64-step prefix blocks, with a ragged last block
+    ("1d_N200", W.with_(W.C2, modes=40, quad=60, steps=200, slices=5, alpha=0.45, **H), [24, 25]),
+    ("1d_M280_N130", W.with_(W.C2, modes=280, quad=300, steps=130, slices=2, alpha=0.6, T=0.1, **H), [26]),
+    ("2d_M6_N140", dict(W.C3, modes=6, quad=10, steps=140, slices=2, alpha=0.3, **H), [27]),
+]
+
+
+@pytest.mark.parametrize("name,kw,seeds", SERIAL_CASES, ids=[c[0] for c in SERIAL_CASES])
+def test_full_history_serial_blocks_match_oracle(gpu, orc, name, kw, seeds):
+    """The full-history serial solve sums each step's history as a per-block prefix (formed
+    before the block's first step) plus the rows since the block began; slice ends and the
+    whole trajectory match the oracle's direct sum to 1e-10."""
+    print(f"[fullhist serial] {name}", flush=True)
+    p = gpu.make_problem(**kw)
+    u0 = u0_for(kw, seeds)
+    U, tr = gpu.solve_serial(p, dev(u0), want_traj=True)
+    U, tr = U.cpu().numpy(), tr.cpu().numpy()
+    po = orc.problem(**kw)
+    for b in range(len(seeds)):
+        Uo, tro = orc.solve_serial(po, u0[b], want_traj=True)
+        assert rel(U[b], Uo) <= TOL, (name, b, rel(U[b], Uo))
+        per = [rel(tr[b][m], tro[m]) for m in range(tro.shape[0])]
+        assert max(per) <= 10 * TOL, (name, b, max(per))
+
+
 def test_full_history_fixed_point_is_not_the_hybrid_one(gpu):
     """The two variants converge to different discrete solutions (uniform L1 with full
     history vs the paper's hybrid propagator); each parareal reaches its own."""
