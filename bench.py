@@ -411,6 +411,54 @@ def full_history(l1, torch, W, dev, alpha=0.3):
     return out
 
 
+def paper_model(l1, torch, W, dev, sizes=((8, 8), (16, 16), (32, 32), (64, 64), (128, 128),
+                                               (128, 256))):
+    """The paper's model problem on the sine path (qualitative re-runs of its two figures):
+    - the error at t = T of parareal iterate k against the serial fine solution, with
+      2^8 coarse intervals of 2^5 fine steps, against the hybrid serial solution (parareal's
+      fixed point) and against the full-history serial solution (a different discrete
+      solution: the error then levels off at the gap between the two);
+    - serial and parareal (stop at increment <= 1e-10) wall time over the number of fine
+      steps N_t x M, with N_t coarse intervals of M fine steps."""
+    kw = dict(W.PAPER)
+    M = kw["modes"]
+    u0 = torch.tensor(W.u0_paper_1d(M)[None], dtype=torch.float64, device=dev)
+    p = l1.make_problem(**kw)
+    Us, _ = l1.solve_serial(p, u0)
+    Uf, _ = l1.solve_serial(l1.make_problem(**W.with_(kw, history=1)), u0)
+    res = l1.solve_parareal(p, u0, 12, tol=0.0, want_iterates=True)
+    its = res.iterates[:, 0, -1]
+    e_h = [float(f"{float((its[k] - Us[0, -1]).norm()):.3e}") for k in range(res.iters + 1)]
+    e_f = [float(f"{float((its[k] - Uf[0, -1]).norm()):.3e}") for k in range(res.iters + 1)]
+    out = {"workload": f"paper model: D=1+u, f=sin(pi x)e^-t, u0=x^4(1-x)^4, alpha=0.5, T=1, "
+                       f"{M} sine modes, Q={kw['quad']}",
+           "error_vs_iteration": {"N_t": kw["slices"], "M": kw["steps"] // kw["slices"],
+                                  "vs_hybrid_serial": e_h, "vs_full_history_serial": e_f,
+                                  "gap_hybrid_full_at_T": float(f"{float((Us[0, -1] - Uf[0, -1]).norm()):.3e}")}}
+    runs = []
+    for Nt, Ms in sizes:
+        q = l1.make_problem(**W.with_(kw, slices=Nt, steps=Nt * Ms))
+        l1.solve_serial(q, u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Uq, _ = l1.solve_serial(q, u0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        l1.solve_parareal(q, u0, Nt, tol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = l1.solve_parareal(q, u0, Nt, tol=1e-10)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        runs.append({"N_t": Nt, "M": Ms, "fine_steps": Nt * Ms, "serial_ms": round(ts * 1e3, 2),
+                     "parareal_ms": round(tp * 1e3, 2), "sweeps": r.iters,
+                     "speedup": round(ts / tp, 2), "rel_err": rel_err_max(r.U, Uq)})
+        log(f"paper model N_t={Nt} M={Ms}: serial {ts * 1e3:.1f} ms, parareal {tp * 1e3:.1f} ms "
+            f"({r.iters} sweeps)")
+    out["runtime_vs_fine_steps"] = runs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -421,6 +469,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-full-history", action="store_true")
+    ap.add_argument("--no-paper-model", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernels", "kernels2d", "kernelsfh", "fullhistory"],
                     default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
@@ -610,6 +659,10 @@ def main():
     if not args.no_uneven:
         uneven = uneven_batch(l1, torch, W, dev)
 
+    paper = None
+    if not args.no_paper_model:
+        paper = paper_model(l1, torch, W, dev)
+
     fullh = None
     if not args.no_full_history:
         fullh = full_history(l1, torch, W, dev)
@@ -657,6 +710,7 @@ def main():
         "uneven_batch": uneven,
         "config3_2d": two_d,
         "full_history": fullh,
+        "paper_model": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -48,6 +48,14 @@ C5_COUNT = 256
 C5_SEED = 5
 
 
+# the paper's model problem (its numerical examples): D = 1 + u, f = sin(pi x) e^-t,
+# u0 = x^4 (1-x)^4, alpha = 0.5, on (0, 1); T = 1 (not stated there).  Its error-vs-iteration
+# run uses 2^8 coarse intervals of 2^5 fine steps and 2^4 spatial unknowns (here: 16 sine
+# modes, 24 Gauss points)
+PAPER = dict(dim=1, modes=16, quad=24, steps=256 * 32, slices=256, alpha=0.5, T=1.0, d_sel=4,
+             d_param=1.0, f_sel=4, history=0, source_time=0)
+
+
 def c5_instances(count: int = C5_COUNT, seed: int = C5_SEED):
     """(modes, steps per slice, alpha) arrays of the uneven batch."""
     rng = np.random.default_rng(seed)
@@ -67,6 +75,18 @@ def u0_sine_mode(M: int) -> np.ndarray:
     """Coefficients of u0 = sin(pi x): sqrt(2) sin(pi x) / sqrt(2)."""
     c = np.zeros(M)
     c[0] = 1.0 / math.sqrt(2.0)
+    return c
+
+
+def u0_paper_1d(M: int) -> np.ndarray:
+    """Sine coefficients of u0 = x^4 (1-x)^4, k = 1..M, in closed form.  Integrating by parts
+    (p(0) = p(1) = p''(0) = p''(1) = 0, p(1-x) = p(x)), sqrt(2) int_0^1 p(x) sin(k pi x) dx
+    = sqrt(2) (1 - (-1)^k) (p''''(0)/a^5 - p^(6)(0)/a^7 + p^(8)(0)/a^9), a = k pi, with
+    p''''(0) = 24, p^(6)(0) = 4320, p^(8)(0) = 40320; zero for even k."""
+    c = np.zeros(M)
+    for k in range(1, M + 1, 2):
+        a = k * math.pi
+        c[k - 1] = 2.0 * math.sqrt(2.0) * (24.0 / a ** 5 - 4320.0 / a ** 7 + 40320.0 / a ** 9)
     return c
 
 

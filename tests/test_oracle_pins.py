@@ -552,3 +552,24 @@ def test_full_history_parareal_is_exact_against_uniform_l1(orc):
             assert all(err[j + 1] < err[j] for j in range(P)) and err[P - 1] < 1e-2 * err[0], err
             # it is not the hybrid solution: the two fixed points differ
             assert np.linalg.norm(Uh - Us) > 1e-6 * np.linalg.norm(Us)
+
+
+def test_paper_u0_coefficients_closed_form():
+    """The paper's initial value x^4 (1-x)^4: the closed-form sine coefficients of the input
+    generator against a 400-point Gauss-Legendre projection (numpy's rule), the zero even
+    modes (symmetry about x = 1/2), and the reconstruction of u0 from 40 modes."""
+    import math
+
+    from paper_2510_11023_amd import workloads as W
+
+    M = 40
+    c = W.u0_paper_1d(M)
+    x, w = np.polynomial.legendre.leggauss(400)
+    x, w = (x + 1) / 2, w / 2
+    k = np.arange(1, M + 1)
+    cq = (w * x ** 4 * (1 - x) ** 4) @ (math.sqrt(2) * np.sin(np.outer(x, k) * math.pi))
+    assert np.max(np.abs(c - cq)) < 1e-15
+    assert not np.any(c[1::2])
+    xs = np.linspace(0, 1, 101)
+    rec = math.sqrt(2) * np.sin(np.outer(xs, k) * math.pi) @ c
+    assert np.max(np.abs(rec - xs ** 4 * (1 - xs) ** 4)) < 1e-7
