@@ -57,7 +57,8 @@ typedef enum {
   L1PR_ENOMEM = -2,     /* workspace smaller than l1pr_workspace_bytes() */
   L1PR_EHIP = -3,       /* HIP runtime error */
   L1PR_ENOTCONV = -4,   /* parareal stopped at max_iter < P without meeting tol; U holds the last iterate */
-  L1PR_ENONFINITE = -5  /* a parareal increment was NaN or infinite (tol > 0 only) */
+  L1PR_ENONFINITE = -5, /* a parareal increment was NaN or infinite (tol > 0 only) */
+  L1PR_ESOLVE = -6      /* an iterative step solve (solver = 1) missed its tolerance */
 } l1pr_status;
 
 /* Diffusion selectors D(x,t,u). */
@@ -110,6 +111,21 @@ typedef struct {
                            the default, l1pr_autotune measures the best.  The variants sum in
                            different orders, so runs compared bit for bit must use the same
                            value. */
+  int32_t solver;       /* the step's linear system (I + tau K) c = rhs:
+                           0: Cholesky factorisation (register-resident for <= 256 coefficients,
+                              blocked through device memory beyond);
+                           1: preconditioned conjugate gradients, 2D only, Q >= 3M/2 (with
+                              fewer points the quadrature stiffness has near-null directions
+                              that the preconditioner does not see): K applied as the
+                              separable quadrature products (Phi' (x) Phi and Phi (x) Phi' at the
+                              Q x Q Gauss points, w w D between them), preconditioned by the
+                              constant-coefficient operator I + tau Dbar pi^2 (k1^2 + k2^2)
+                              (Dbar = the quadrature mean of D), which is diagonal in the sine
+                              basis; started from the lagged state and stopped when
+                              ||r|| <= 1e-14 ||rhs|| (at most 200 iterations, else
+                              L1PR_ESOLVE).  No M^2 x M^2 matrix is formed.  Each unit
+                              iterates on its own data, so parareal stays exact; the host checks
+                              convergence every 4 iterations (one stream synchronisation). */
 } l1pr_problem;
 
 /* Operation codes for l1pr_workspace_bytes. */

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libl1pr.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE, ESOLVE = 0, -1, -2, -3, -4, -5, -6
 OP_SERIAL, OP_PARAREAL = 0, 1
 
 
@@ -34,6 +34,7 @@ class Problem(ctypes.Structure):
         ("source_time", ctypes.c_int32),
         ("assembly", ctypes.c_int32),
         ("tune", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
     ]
 
 

@@ -30,12 +30,18 @@ namespace {
 constexpr int kMaxModes1D = 1024;  // the 1D evaluation kernel stages Mp + Qp doubles in LDS
 constexpr int kMaxModes2D = 64;
 constexpr int kSerialBlock = 64;  // steps per prefix launch of the full-history serial solve
+constexpr int kCgCap = 200;       // conjugate-gradient iterations per step solve, at most
+constexpr int kCgCheck = 4;       // iterations between the host's convergence checks
 
 struct Layout {
   size_t total = 0;
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
   size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
+  size_t b12 = 0, s2 = 0;    // 2D: stacked basis tables of the separable stiffness products
+  // conjugate-gradient solves (solver = 1): x, r, p, K p [units][Mp]; G [units][2][Qp][Qp];
+  // H [units][2 Qp][M1p]; per-unit scalars [units][8]; two counters
+  size_t cgx = 0, cgr = 0, cgp = 0, cgkp = 0, cgG = 0, cgH = 0, cgs = 0, cgcnt = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -64,6 +70,11 @@ bool valid(const l1pr_problem* p) {
   if (p->assembly != 0 && p->assembly != 1) return false;
   if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY | TUNE_NB128 | TUNE_TRAIL64))
     return false;
+  if (p->solver != 0 && p->solver != 1) return false;
+  if (p->solver == 1 && p->dim != 2) return false;  // the iterative solve is the 2D one
+  // with fewer Gauss points the quadrature stiffness aliases into near-null directions that
+  // the constant-coefficient preconditioner does not see
+  if (p->solver == 1 && 2 * p->quad < 3 * p->modes) return false;
   return true;
 }
 
@@ -124,7 +135,8 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   const size_t nq = two ? Qp * Qp : Qp;  // quadrature points per unit
   L.d = take(cur, D * units * nq);
   L.rhs = take(cur, D * units * Mp);
-  L.A = take(cur, D * units * Mp * Mp);
+  const bool pcg = p->solver == 1;
+  L.A = pcg ? 0 : take(cur, D * units * Mp * Mp);
   L.g = take(cur, D * units * nq);
   L.mom = take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
   L.F = take(cur, D * units * Mp);
@@ -132,7 +144,21 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
   // back-substitution partial sums of the device-memory factorisation
   const size_t nblk = (Mp + tb.nb - 1) / tb.nb;
-  L.q = reg_path_ok(tb.Mp, tb.Qp) ? 0 : take(cur, D * units * nblk * tb.nb);
+  L.q = (pcg || reg_path_ok(tb.Mp, tb.Qp)) ? 0 : take(cur, D * units * nblk * tb.nb);
+  if (two) {
+    L.b12 = take(cur, D * M1p * 2 * Qp);
+    L.s2 = take(cur, D * 2 * Qp * M1p);
+  }
+  if (pcg) {
+    L.cgx = take(cur, D * units * Mp);
+    L.cgr = take(cur, D * units * Mp);
+    L.cgp = take(cur, D * units * Mp);
+    L.cgkp = take(cur, D * units * Mp);
+    L.cgG = take(cur, D * units * 2 * Qp * Qp);
+    L.cgH = take(cur, D * units * 2 * Qp * M1p);
+    L.cgs = take(cur, D * units * 8);
+    L.cgcnt = take(cur, 2 * sizeof(int32_t));
+  }
   L.incrk = take(cur, D * B);
   L.total = cur;
 }
@@ -143,6 +169,7 @@ struct Ctx {
   bool reg;      // register-resident step kernel (Mp <= 256)
   bool moments;  // stiffness from cosine moments, inside that kernel
   bool full;     // parareal with full-history fine propagators
+  bool pcg;      // 2D step systems by preconditioned conjugate gradients
   char* ws;
   hipStream_t s;
   double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -184,6 +211,9 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.bw = c.ptr(c.L.bw);
   tb.bhyb = c.ptr(c.L.bhyb);
   tb.cosq = c.ptr(c.L.cosq);
+  tb.b12 = c.L.b12 ? c.ptr(c.L.b12) : nullptr;
+  tb.s2 = c.L.s2 ? c.ptr(c.L.s2) : nullptr;
+  c.pcg = p->solver == 1;
   c.reg = reg_path_ok(tb.Mp, tb.Qp);
   c.moments = c.reg && p->assembly == 0 && p->dim == 1;
   c.full = op == L1PR_OP_PARAREAL && p->history == 1;
@@ -196,7 +226,8 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
     L1PR_TRY(launch_fill(c.ptr(c.L.alpha), B, p->alpha, c.s));
   L1PR_TRY(launch_tables(tb, c.ptr(c.L.xq), c.ptr(c.L.wq), c.ptr(c.L.phi), c.ptr(c.L.phiT),
                          c.ptr(c.L.dphi), c.ptr(c.L.inst), c.ptr(c.L.bw), c.ptr(c.L.bhyb),
-                         c.ptr(c.L.cosq), alpha_dev, un.modes, un.spp, c.s));
+                         c.ptr(c.L.cosq), alpha_dev, un.modes, un.spp, c.s,
+                         c.L.b12 ? c.ptr(c.L.b12) : nullptr, c.L.s2 ? c.ptr(c.L.s2) : nullptr));
   return L1PR_OK;
 }
 
@@ -253,6 +284,51 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 // Mp > 256: evaluation (1D) or the separable products (2D), the assembly, and the blocked
 //   factorisation through device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
+  if (c.tb.dim == 2 && c.pcg) {
+    // separable products (lagged state, D, f, load vector), the history sums and the
+    // right-hand side, then conjugate gradients from the lagged state with K applied
+    // separably; the host looks at the units' status every 4 iterations
+    L1PR_TRY(timed("products2d", a, units, c.s, [&] {
+      return launch_step2d_products(c.tb, a, units, a.C2, a.T2, a.mom, c.s, false);
+    }));
+    L1PR_TRY(timed("history", a, units, c.s, [&] { return launch_history(c.tb, a, units, a.rhs, c.s); }));
+    L1PR_TRY(timed("rhs", a, units, c.s, [&] { return launch_form_rhs(c.tb, a, units, c.s); }));
+    double* x = c.ptr(c.L.cgx);
+    double* r = c.ptr(c.L.cgr);
+    double* p = c.ptr(c.L.cgp);
+    double* kp = c.ptr(c.L.cgkp);
+    double* G = c.ptr(c.L.cgG);
+    double* H = c.ptr(c.L.cgH);
+    double* cgs = c.ptr(c.L.cgs);
+    int32_t* cnt = reinterpret_cast<int32_t*>(c.ws + c.L.cgcnt);
+    auto apply = [&](const double* v) {
+      return timed("cg_apply", a, units, c.s, [&] {
+        return launch_stiff2d_apply(c.tb, a, units, v, kp, a.T2, G, H, c.s);
+      });
+    };
+    L1PR_TRY(apply(a.C2));
+    L1PR_TRY(timed("cg_update", a, units, c.s, [&] {
+      return launch_cg_init(c.tb, a, units, a.C2, kp, x, r, p, cgs, c.s);
+    }));
+    bool done = false;
+    for (int it = 0; it < kCgCap && !done; it += kCgCheck) {
+      for (int j = 0; j < kCgCheck; ++j) {
+        L1PR_TRY(apply(p));
+        L1PR_TRY(timed("cg_update", a, units, c.s, [&] {
+          return launch_cg_update(c.tb, a, units, x, r, p, kp, cgs, kCgCap, c.s);
+        }));
+      }
+      int32_t h[2] = {0, 0};
+      L1PR_TRY(launch_cg_count(cgs, units, cnt, c.s));
+      L1PR_TRY(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, c.s));
+      L1PR_TRY(hipStreamSynchronize(c.s));
+      if (h[1] > 0) return L1PR_ESOLVE;
+      done = h[0] == 0;
+    }
+    if (!done) return L1PR_ESOLVE;
+    L1PR_TRY(timed("cg_finish", a, units, c.s, [&] { return launch_cg_finish(c.tb, a, e, units, x, c.s); }));
+    return L1PR_OK;
+  }
   if (c.tb.dim == 2) {
     // separable products (lagged state at the Gauss points, D, f, load vector, cosine
     // moments), the system from the moments, the history sums, then the factorisation
@@ -306,7 +382,7 @@ StepArgs base_args(const Ctx& c) {
   std::memset(&a, 0, sizeof(a));
   a.d = c.ptr(c.L.d);
   a.rhs = c.ptr(c.L.rhs);
-  a.A = c.ptr(c.L.A);
+  a.A = c.pcg ? nullptr : c.ptr(c.L.A);
   a.g = c.ptr(c.L.g);
   a.mom = c.ptr(c.L.mom);
   a.F = c.ptr(c.L.F);
@@ -708,6 +784,10 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
     l1pr_status st = setup(&q, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
     const Tables& tb = c.tb;
+    if (c.pcg) {  // no factorisation: nothing to choose
+      *tune_out = 0;
+      return L1PR_OK;
+    }
     if (!c.reg) {
       // blocked factorisation: block width (256 / 128) and trailing tiles (128 / 64), timed on
       // a fine step's systems (B P units, set to the identity before each factorisation; the
@@ -927,6 +1007,7 @@ const char* l1pr_status_string(l1pr_status s) {
     case L1PR_EHIP: return "HIP runtime error";
     case L1PR_ENOTCONV: return "parareal did not meet the tolerance within max_iter sweeps";
     case L1PR_ENONFINITE: return "non-finite parareal increment";
+    case L1PR_ESOLVE: return "iterative step solve missed its tolerance";
   }
   return "unknown status";
 }
@@ -962,7 +1043,7 @@ std::vector<BatchGroup> batch_groups(const l1pr_problem* probs, int count) {
       bool same = q.dim == r.dim && q.quad == r.quad && q.slices == r.slices && q.T == r.T &&
                   q.d_sel == r.d_sel && q.d_param == r.d_param && q.f_sel == r.f_sel &&
                   q.history == r.history && q.source_time == r.source_time &&
-                  q.assembly == r.assembly && q.tune == r.tune;
+                  q.assembly == r.assembly && q.tune == r.tune && q.solver == r.solver;
       if (un) same = same && roundup(q.modes, 16) == roundup(r.modes, 16);
       else same = same && q.modes == r.modes && q.steps == r.steps;
       if (same) found = (int)k;

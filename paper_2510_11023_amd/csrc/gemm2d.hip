@@ -21,7 +21,7 @@ struct BOp {
   int trans;
 };
 
-enum { BG_STORE = 0, BG_EVAL2D = 1 };
+enum { BG_STORE = 0, BG_EVAL2D = 1, BG_MULD = 2 };
 
 constexpr int BT = 64, BK = 16;
 
@@ -29,6 +29,7 @@ constexpr int BT = 64, BK = 16;
 // with 2 x 2 FP64 MFMA 16x16x4 tiles each, operands staged through LDS in chunks of 16.
 // Each output is a fixed-order sum over its own row and column.  BG_EVAL2D: the product is
 // the lagged state u at (x_i, x_j); the epilogue writes d = w_i w_j D and g = w_i w_j f.
+// BG_MULD: the product times the unit's w_i w_j D_ij.
 __global__ __launch_bounds__(256) void k_bgemm(BOp A, BOp B, double* C, long ldc, long sc, int m,
                                                int n, int kd, int epi, Tables tb, StepArgs a,
                                                double* gout) {
@@ -96,6 +97,9 @@ __global__ __launch_bounds__(256) void k_bgemm(BOp A, BOp B, double* C, long ldc
         const long o = (long)u * sc + (long)i * ldc + j;
         if (epi == BG_STORE) {
           C[o] = val;
+        } else if (epi == BG_MULD) {  // times w_i w_j D_ij of the unit (a.d, [Qp][Qp], set
+                                      // for i, j < Q only; padding nodes carry no weight)
+          C[o] = (i < tb.Q && j < tb.Q) ? val * a.d[((long)u * tb.Qp + i) * tb.Qp + j] : 0.0;
         } else {
           const double w = tb.wq[i] * tb.wq[j], X = tb.xq[i], Y = tb.xq[j];
           C[o] = w * coef_D(tb.d_sel, tb.d_param, val);
@@ -168,7 +172,7 @@ __global__ void k_form_rhs(Tables tb, StepArgs a, int units, const double* F, do
 // load vector F and the cosine moments.  Scratch: C [units][Mp] (lagged states), T
 // [units][Qp * Jp] (intermediate products).
 hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units, double* Cbuf,
-                                  double* T, double* mom, hipStream_t s) {
+                                  double* T, double* mom, hipStream_t s, bool moments) {
   const int M1 = tb.M1, M1p = tb.M1p, Q = tb.Q, Qp = tb.Qp, Mp = tb.Mp;
   const int J = 2 * M1 + 1, Jp = 2 * M1p + 1;
   const long sT = (long)Qp * Jp, sQ = (long)Qp * Qp;
@@ -190,12 +194,41 @@ hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units
   if (r != hipSuccess) return r;
   r = bgemm(BOp{tb.phiT, Qp, 0, 0}, BOp{T, M1p, sT, 0}, a.F, M1, Mp, M1, M1, Q, units, BG_STORE, tb,
             a, nullptr, s);
-  if (r != hipSuccess) return r;
+  if (r != hipSuccess || !moments) return r;
   // T = Dw Cy : [Q][J];  m = Cx^T T : [J][J]
   r = bgemm(BOp{a.d, Qp, sQ, 0}, BOp{tb.cosq, Jp, 0, 0}, T, Jp, sT, Q, J, Q, units, BG_STORE, tb, a,
             nullptr, s);
   if (r != hipSuccess) return r;
   return bgemm(BOp{tb.cosq, Jp, 0, 1}, BOp{T, Jp, sT, 0}, mom, Jp, (long)Jp * Jp, J, J, Q, units,
+               BG_STORE, tb, a, nullptr, s);
+}
+
+// Kv = K V for every unit (the stiffness without tau, as the quadrature sum of the bilinear
+// form, separably):  T12 = V [phi^T | dphi^T]  (M1 x 2Qp);  Gx = dphi T12[:, :Qp] o Dw,
+// Gy = phi T12[:, Qp:] o Dw  (Qp x Qp, the x and y derivatives at the Gauss points times
+// w w D);  H = [Gx phi; Gy dphi]  (2Qp x M1);  Kv = [dphi; phi]^T H.  V and Kv hold the M1 x M1
+// coefficient matrix of each unit at stride Mp (entries past M1^2 are not touched).
+// Scratch per unit: T12 [M1p][2Qp], G [2][Qp][Qp], H [2Qp][M1p].
+hipError_t launch_stiff2d_apply(const Tables& tb, const StepArgs& a, int units, const double* V,
+                                double* Kv, double* T12, double* G, double* H, hipStream_t s) {
+  const int M1 = tb.M1, M1p = tb.M1p, Qp = tb.Qp, Mp = tb.Mp;
+  const long sT = (long)M1p * 2 * Qp, sG = 2L * Qp * Qp, sH = 2L * Qp * M1p;
+  hipError_t r = bgemm(BOp{V, M1, Mp, 0}, BOp{tb.b12, 2 * Qp, 0, 0}, T12, 2 * Qp, sT, M1, 2 * Qp,
+                       M1, units, BG_STORE, tb, a, nullptr, s);
+  if (r != hipSuccess) return r;
+  r = bgemm(BOp{tb.dphi, M1p, 0, 0}, BOp{T12, 2 * Qp, sT, 0}, G, Qp, sG, Qp, Qp, M1, units, BG_MULD,
+            tb, a, nullptr, s);
+  if (r != hipSuccess) return r;
+  r = bgemm(BOp{tb.phi, M1p, 0, 0}, BOp{T12 + Qp, 2 * Qp, sT, 0}, G + (long)Qp * Qp, Qp, sG, Qp, Qp,
+            M1, units, BG_MULD, tb, a, nullptr, s);
+  if (r != hipSuccess) return r;
+  r = bgemm(BOp{G, Qp, sG, 0}, BOp{tb.phi, M1p, 0, 0}, H, M1p, sH, Qp, M1, Qp, units, BG_STORE, tb,
+            a, nullptr, s);
+  if (r != hipSuccess) return r;
+  r = bgemm(BOp{G + (long)Qp * Qp, Qp, sG, 0}, BOp{tb.dphi, M1p, 0, 0}, H + (long)Qp * M1p, M1p, sH,
+            Qp, M1, Qp, units, BG_STORE, tb, a, nullptr, s);
+  if (r != hipSuccess) return r;
+  return bgemm(BOp{tb.s2, M1p, 0, 1}, BOp{H, M1p, sH, 0}, Kv, M1, Mp, M1, M1, 2 * Qp, units,
                BG_STORE, tb, a, nullptr, s);
 }
 

@@ -52,6 +52,8 @@ struct Tables {
   const double* bw;
   const double* bhyb;
   const double* cosq;  // [Qp][2 Mp + 1] = cos(j pi x_q) (zero for padding nodes)
+  const double* b12;   // 2D: [M1p][2 Qp] = [phi^T | dphi^T]
+  const double* s2;    // 2D: [2 Qp][M1p] = [dphi; phi]
 };
 
 // What one step-launch computes for each of its units.
@@ -298,10 +300,21 @@ __device__ inline void epi_store(const StepArgs& a, const Epilogue& ep, int u, l
 hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
                          double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
                          const double* alpha_dev, const int32_t* Mb, const int32_t* Sb,
-                         hipStream_t s);
+                         hipStream_t s, double* b12 = nullptr, double* s2 = nullptr);
 // 2D steps (gemm2d.hip)
 hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units, double* Cbuf,
-                                  double* T, double* mom, hipStream_t s);
+                                  double* T, double* mom, hipStream_t s, bool moments = true);
+hipError_t launch_stiff2d_apply(const Tables& tb, const StepArgs& a, int units, const double* V,
+                                double* Kv, double* T12, double* G, double* H, hipStream_t s);
+// preconditioned conjugate gradients for the 2D step systems (cg2d.hip); cgs [units][8]
+hipError_t launch_cg_init(const Tables& tb, const StepArgs& a, int units, const double* x0,
+                          const double* kx, double* x, double* r, double* p, double* cgs,
+                          hipStream_t s);
+hipError_t launch_cg_update(const Tables& tb, const StepArgs& a, int units, double* x, double* r,
+                            double* p, const double* kp, double* cgs, int cap, hipStream_t s);
+hipError_t launch_cg_count(const double* cgs, int units, int32_t* out, hipStream_t s);
+hipError_t launch_cg_finish(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                            const double* x, hipStream_t s);
 hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, const double* mom,
                              hipStream_t s);
 hipError_t launch_form_rhs(const Tables& tb, const StepArgs& a, int units, hipStream_t s);

@@ -44,9 +44,10 @@ __global__ void k_gauss_legendre(int Q, int Qp, double* xq, double* wq) {
 }
 
 // phi[q][k] = sqrt2 sin((k+1) pi x_q), dphi[q][k] = sqrt2 (k+1) pi cos((k+1) pi x_q),
-// zero outside k < M, q < Q.
+// zero outside k < M, q < Q.  When b12 is set (2D), also the stacked tables of the
+// separable stiffness products: b12 [Mp][2 Qp] = [phi^T | dphi^T], s2 [2 Qp][Mp] = [dphi; phi].
 __global__ void k_basis(int M, int Q, int Mp, int Qp, const double* xq, double* phi,
-                        double* phiT, double* dphi) {
+                        double* phiT, double* dphi, double* b12, double* s2) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)Qp * Mp) return;
   const int q = (int)(idx / Mp), k = (int)(idx % Mp);
@@ -60,6 +61,12 @@ __global__ void k_basis(int M, int Q, int Mp, int Qp, const double* xq, double* 
   phi[(long)q * Mp + k] = v;
   phiT[(long)k * Qp + q] = v;
   dphi[(long)q * Mp + k] = dv;
+  if (b12) {
+    b12[(long)k * 2 * Qp + q] = v;
+    b12[(long)k * 2 * Qp + Qp + q] = dv;
+    s2[(long)q * Mp + k] = dv;
+    s2[(long)(Qp + q) * Mp + k] = v;
+  }
 }
 
 // cosq[q][j] = cos(j pi x_q), j = 0..Jp-1 (cosine moments of the stiffness)
@@ -146,12 +153,13 @@ hipError_t launch_fill(double* x, long n, double v, hipStream_t s) {
 hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, double* phiT,
                          double* dphi, double* inst, double* bw, double* bhyb, double* cosq,
                          const double* alpha_dev, const int32_t* Mb, const int32_t* Sb,
-                         hipStream_t s) {
+                         hipStream_t s, double* b12, double* s2) {
   const int T = 256;
   k_gauss_legendre<<<(tb.Qp + T - 1) / T, T, 0, s>>>(tb.Q, tb.Qp, xq, wq);
   // basis tables per direction: M1 modes padded to M1p (M1 = M in 1D)
   const long nb = (long)tb.Qp * tb.M1p;
-  k_basis<<<(unsigned)((nb + T - 1) / T), T, 0, s>>>(tb.M1, tb.Q, tb.M1p, tb.Qp, xq, phi, phiT, dphi);
+  k_basis<<<(unsigned)((nb + T - 1) / T), T, 0, s>>>(tb.M1, tb.Q, tb.M1p, tb.Qp, xq, phi, phiT, dphi,
+                                                    b12, s2);
   if (cosq) {
     const long nc = (long)tb.Qp * (2 * tb.M1p + 1);
     k_cosq<<<(unsigned)((nc + T - 1) / T), T, 0, s>>>(tb.Q, tb.Qp, 2 * tb.M1p + 1, xq, cosq);

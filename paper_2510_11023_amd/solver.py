@@ -20,9 +20,9 @@ ASSEMBLY_GEMM = 1      # stiffness as the quadrature GEMM dphi^T diag(w D) dphi 
 
 def make_problem(dim=1, modes=32, quad=64, steps=256, slices=8, alpha=0.5, T=1.0, d_sel=0,
                  d_param=1.0, f_sel=0, history=0, source_time=0,
-                 assembly=ASSEMBLY_MOMENTS, tune=0) -> Problem:
+                 assembly=ASSEMBLY_MOMENTS, tune=0, solver=0) -> Problem:
     return Problem(dim, modes, quad, steps, slices, alpha, T, d_sel, d_param, f_sel, history,
-                   source_time, assembly, tune)
+                   source_time, assembly, tune, solver)
 
 
 def nmodes(p: Problem) -> int:

@@ -41,11 +41,16 @@ def test_host_entry_points(L):
     par = L.l1pr_workspace_bytes(ctypes.byref(p), 32, 1)
     # the parareal workspace holds B*P systems of M^2 doubles
     assert par > 32 * 64 * 256 * 256 * 8 > ser > 0
+    # the iterative solve is 2D only; solver codes past 1 are invalid
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.C2))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.C3))) == 0
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.C3))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.with_(W.C3, quad=95)))) == -1
     bad = make_problem(**W.with_(W.C2, steps=4095))
     assert L.l1pr_validate(ctypes.byref(bad)) == -1
     assert L.l1pr_workspace_bytes(ctypes.byref(bad), 32, 1) == 0
     assert L.l1pr_workspace_bytes(ctypes.byref(p), 0, 1) == 0
-    for s in (0, -1, -2, -3, -4, -5):
+    for s in (0, -1, -2, -3, -4, -5, -6):
         assert L.l1pr_status_string(s)
     # invalid problems are rejected before any device work
     u = ctypes.c_void_p(1)
