@@ -351,6 +351,73 @@ def config3_2d(l1, torch, W, dev, with_parareal=True):
                         "achieved_rel_err": rel_err_max(U, Us)})
         out["parareal_plain"] = rec
         log(f"config 3: parareal k*={ks} " + (f"{rec.get('ms')} ms" if ks is not None else ""))
+    out["conjugate_gradients"] = config3_cg(l1, torch, W, dev, Us)
+    return out
+
+
+def config3_cg(l1, torch, W, dev, Us_direct=None):
+    """Config 3 with the step systems solved by preconditioned conjugate gradients
+    (solver = 1): fine sweep, serial solve and plain parareal to 1e-8 of that serial
+    solution; the stiffness products' MFMA rate; agreement with the Cholesky path."""
+    from paper_2510_11023_amd import _lib
+
+    kw = dict(W.C3)
+    M1, N, P = kw["modes"], kw["steps"], kw["slices"]
+    Md, S, Q = M1 * M1, N // P, kw["quad"]
+    p = l1.make_problem(solver=1, **kw)
+    u0 = torch.tensor(W.u0_random_2d(M1, 0)[None], device=dev)
+    ws = l1.parareal_workspace(p, 1, dev)
+    Z = l1.solve_parareal(p, u0, 0, tol=0.0, want_iterates=True, workspace=ws).iterates[0]
+    Z = Z.contiguous()
+    l1.fine_apply(p, Z, workspace=ws)
+    torch.cuda.synchronize()
+    _lib.profile_start()
+    t0 = time.perf_counter()
+    l1.fine_apply(p, Z, workspace=ws)
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t0
+    st = _lib.profile_stop()
+    out = {"workload": "config 3 with solver = 1 (conjugate gradients)",
+           "workspace_gib": round(ws.numel() / 2 ** 30, 3),
+           "fine_sweep_ms": round(t_sweep * 1e3, 1),
+           "fine_sweep_mode_steps_per_s": P * S * Md / t_sweep}
+    n_a, tot_a = st.get(f"cg_grid/fine/{P}", (0, 0.0))
+    n_u, tot_u = st.get(f"cg_step/fine/{P}", (0, 0.0))
+    if n_a and n_u:
+        avg = (tot_a / n_a + tot_u / n_u) / 1e3
+        fl = P * 2 * (4 * Q * M1 * M1 + 4 * Q * Q * M1)
+        out["apply_roofline"] = {"bound": "mfma", "kernel": f"separable stiffness product and CG "
+                                 f"update (3 batched k_bgemm launches + k_cg_step, {P} units)",
+                                 "achieved": round(fl / avg / 1e12, 2), "peak": PEAK_FP64_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(fl / avg / 1e12 / PEAK_FP64_TFLOPS, 4),
+                                 "avg_apply_us": round(avg * 1e6, 1), "flops_per_apply": fl}
+        out["cg_iterations_per_step"] = round((n_u - S) / S, 2)
+    tot = sum(v[1] for v in st.values())
+    out["fine_sweep_share"] = {k: round(v[1] / tot, 4) for k, v in st.items()}
+    ws_s = torch.empty(l1.workspace_bytes(p, 1, 0), dtype=torch.uint8, device=dev)
+    l1.solve_serial(p, u0, workspace=ws_s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Us, _ = l1.solve_serial(p, u0, workspace=ws_s)
+    torch.cuda.synchronize()
+    t_ser = time.perf_counter() - t0
+    out["serial_ms"] = round(t_ser * 1e3, 1)
+    out["serial_mode_steps_per_s"] = N * Md / t_ser
+    if Us_direct is not None:
+        out["rel_diff_vs_cholesky_serial"] = rel_err_max(Us, Us_direct)
+    ks, e = find_kstar(l1, p, u0, Us, ws, 14)
+    rec = {"kstar": ks, "rel_err_by_sweep": [float(f"{v:.3e}") for v in e]}
+    if ks is not None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U = l1.solve_parareal(p, u0, ks, tol=0.0, want_incr=False, workspace=ws).U
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        rec.update({"ms": round(tp * 1e3, 1), "mode_steps_per_s": N * Md / tp,
+                    "achieved_rel_err": rel_err_max(U, Us), "speedup_over_serial": round(t_ser / tp, 2)})
+    out["parareal_plain"] = rec
+    log(f"config 3 (CG): fine sweep {t_sweep * 1e3:.0f} ms, serial {t_ser * 1e3:.0f} ms, "
+        f"parareal k*={ks} {rec.get('ms')} ms")
     return out
 
 

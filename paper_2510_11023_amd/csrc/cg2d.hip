@@ -1,26 +1,26 @@
 // Preconditioned conjugate gradients for the 2D step systems (I + tau K) c = rhs.
 //
-// K is applied separably at the Gauss points (launch_stiff2d_apply), never formed.  The
-// preconditioner is the constant-coefficient operator I + tau Dbar pi^2 (k1^2 + k2^2), Dbar
-// the quadrature mean of D: with D constant the sine basis diagonalises K (its eigenvalues
-// are D pi^2 (k1^2 + k2^2)), so the preconditioned system has its spectrum in
-// [min D / Dbar, max D / Dbar] up to quadrature effects, and CG contracts by about
-// (sqrt(kappa) - 1) / (sqrt(kappa) + 1) per iteration.  The start is the lagged state (the new
-// state differs from it by one time step).
+// K is applied at the Gauss points, never formed: launch_stiff2d_grid forms
+// G = [Gx; Gy] = [dphi V phi^T; phi V dphi^T] o (w w D) for the current vector V, and the fused
+// step kernel below finishes K V = dphi^T Gx phi + phi^T Gy dphi and updates the iterates.
+// The preconditioner is the diagonal of I + tau K (Jacobi), from the cosine moments.  With D
+// constant the sine basis diagonalises K, so for the workloads' D (within a factor 1.5 or 2 of
+// its mean) the preconditioned spectrum stays within a small interval when the quadrature
+// resolves the modes (Q >= 3M/2; below that the quadrature stiffness has near-null directions).
+// The start is the lagged state.
 //
-// One 256-thread work-group per unit; the unit's vectors live in device memory between the
-// stiffness products; dot products are fixed-order sums (per-thread strided sums, then a
-// fixed tree), so a unit's iterates depend only on its own data.  Per-unit state in
-// cgs[u][8]: rz = r.z, ||rhs||^2, status, Dbar, iteration count.  A unit stops (and is left
-// untouched by later launches) once ||r|| <= 1e-14 ||rhs||.
+// One 256-thread work-group per unit; the unit's vectors live in device memory between
+// iterations; dot products are fixed-order sums (per-lane sums, then a fixed tree), so a unit's
+// iterates depend only on its own data.  Per-unit state in cgs[u][8]: rz = r.z, ||rhs||^2,
+// status, iteration count.  A unit stops (and is left untouched by later launches) once
+// ||r|| <= 1e-14 ||rhs||.
 #include "l1pr_internal.h"
 
 namespace l1pr {
 
 constexpr int CG_T = 256;
-constexpr int CG_E = 16;  // entries per thread: Mp <= CG_T * CG_E = 4096
 constexpr double CG_TOL2 = 1e-28;
-enum { CG_RZ = 0, CG_BN = 1, CG_ST = 2, CG_DBAR = 3, CG_IT = 4, CG_NS = 8 };
+enum { CG_RZ = 0, CG_BN = 1, CG_ST = 2, CG_IT = 3, CG_NS = 8 };
 constexpr double CG_ACTIVE = 0.0, CG_DONE = 1.0, CG_FAIL = 2.0;
 
 __device__ inline double block_sum(double v, double* red) {
@@ -37,113 +37,194 @@ __device__ inline double block_sum(double v, double* red) {
   return r;
 }
 
-// diagonal of the preconditioner at entry k < M1^2
-__device__ inline double cg_pdiag(int k, int M1, double tau, double dbar) {
-  const double K1 = (double)(k / M1 + 1), K2 = (double)(k % M1 + 1);
-  return 1.0 + tau * dbar * (kPi * kPi) * (K1 * K1 + K2 * K2);
-}
+// One conjugate-gradient step (INIT = 0) or the start (INIT = 1) for the unit of each
+// work-group, fused with the second half of the stiffness product: from G = [Gx; Gy]
+// (launch_stiff2d_grid; 2Qp x Qp per unit), Kp = [dphi; phi]^T [Gx phi; Gy dphi] is summed over
+// 16-row chunks of G on FP64 MFMA 16x16x4 (chunk rows staged in LDS, H = chunk x table per
+// wave, then Kp += [dphi; phi]_chunk^T H), and stays in the accumulators: entry (i, j) of the
+// M1 x M1 coefficient matrix, k = i M1 + j, belongs to one lane.  Then, for INIT, the Jacobi
+// diagonal d_k = 1 + tau K_kk (from the cosine moments), x = x0, r = rhs - (x0 + tau K x0),
+// z = r / d, p = z; otherwise the CG update with Ap = p + tau K p.  Dot products are
+// per-lane sums followed by the fixed tree.
+constexpr int KV_T = 256;
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(CG_T) void k_cg_init(Tables tb, StepArgs a, const double* x0,
-                                                  const double* kx, double* x, double* r,
-                                                  double* p, double* cgs) {
-  __shared__ double red[CG_T];
-  const int u = blockIdx.x, tid = threadIdx.x, Mp = tb.Mp, Qp = tb.Qp, M1 = tb.M1;
-  const UnitView v = decode_unit(tb, a, u);
-  const double* ins = tb.inst + (long)v.b * NSCAL;
-  const double tau = ins[v.tau_slot];
-  const int Mb = M1 * M1;
-  // Dbar = sum_ij w_i w_j D_ij over the Q x Q Gauss points (the weights of each direction sum
-  // to 1; the padded rows and columns of a.d are not written)
-  const double* dw = a.d + (long)u * Qp * Qp;
-  const int Q = tb.Q;
-  double sd = 0.0;
-  for (int e = tid; e < Q * Q; e += CG_T) sd += dw[(long)(e / Q) * Qp + e % Q];
-  const double dbar = block_sum(sd, red);
-  const long o = (long)u * Mp;
-  double bn = 0.0;
-  for (int k = tid; k < Mp; k += CG_T) {
-    const double b = a.rhs[o + k];
-    bn += b * b;
-  }
-  bn = block_sum(bn, red);
-  double rz = 0.0, rn = 0.0;
-  for (int k = tid; k < Mp; k += CG_T) {
-    double xk = 0.0, rk = 0.0, zk = 0.0;
-    if (k < Mb && bn > 0.0) {
-      xk = x0[o + k];
-      rk = a.rhs[o + k] - (xk + tau * kx[o + k]);
-      zk = rk / cg_pdiag(k, M1, tau, dbar);
-    }
-    x[o + k] = xk;
-    r[o + k] = rk;
-    p[o + k] = zk;
-    rz += rk * zk;
-    rn += rk * rk;
-  }
-  rz = block_sum(rz, red);
-  rn = block_sum(rn, red);
-  if (tid == 0) {
-    double* cs = cgs + (long)u * CG_NS;
-    cs[CG_RZ] = rz;
-    cs[CG_BN] = bn;
-    cs[CG_ST] = (bn == 0.0 || rn <= CG_TOL2 * bn) ? CG_DONE : CG_ACTIVE;
-    cs[CG_DBAR] = dbar;
-    cs[CG_IT] = 0.0;
-  }
-}
-
-__global__ __launch_bounds__(CG_T) void k_cg_update(Tables tb, StepArgs a, double* x, double* r,
-                                                    double* p, const double* kp, double* cgs,
-                                                    int cap) {
-  __shared__ double red[CG_T];
-  const int u = blockIdx.x, tid = threadIdx.x, Mp = tb.Mp, M1 = tb.M1;
+template <int INIT>
+__global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const double* G,
+                                                  const double* x0, double* x, double* r,
+                                                  double* p, double* pd, double* cgs, int cap) {
+  extern __shared__ double sm[];
+  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M1 = tb.M1, M1p = tb.M1p, Qp = tb.Qp, Mp = tb.Mp;
   double* cs = cgs + (long)u * CG_NS;
-  if (cs[CG_ST] != CG_ACTIVE) return;  // the same for the whole work-group
+  if (!INIT && cs[CG_ST] != CG_ACTIVE) return;  // the same for the whole work-group
+  const int ldg = Qp + 1, ldh = 65;
+  double* sG = sm;
+  double* sH = sG + 16 * ldg;
+  double* red = sH + 16 * ldh;
+  const double* Gu = G + (long)u * 2 * Qp * Qp;
+  const int wi = wave >> 1, wj = wave & 1;
+  d4 acc[2][2];
+#pragma unroll
+  for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy) acc[xx][yy] = d4{0.0, 0.0, 0.0, 0.0};
+  const int hcol = wave * 16 + (lane & 15);
+  for (int q0 = 0; q0 < 2 * Qp; q0 += 16) {
+    for (int e = tid; e < 16 * Qp; e += KV_T) {
+      const int rr = e / Qp, q = e % Qp;
+      sG[rr * ldg + q] = Gu[(long)(q0 + rr) * Qp + q];
+    }
+    __syncthreads();
+    // H = G[q0 .. q0+15] T with T = phi (rows of Gx) or dphi (rows of Gy); wave w: columns
+    // 16w .. 16w+15
+    const double* T = q0 < Qp ? tb.phi : tb.dphi;
+    d4 h = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k4 = 0; k4 < Qp; k4 += 4) {
+      const int kk = k4 + (lane >> 4);
+      const double av = sG[(lane & 15) * ldg + kk];
+      const double bv = hcol < M1 ? T[(long)kk * M1p + hcol] : 0.0;
+      h = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, h, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sH[((lane >> 4) + 4 * v) * ldh + hcol] = h[v];
+    __syncthreads();
+    // Kp += [dphi; phi][q0 .. q0+15]^T H
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const int kk = k4 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int xx = 0; xx < 2; ++xx) {
+        const int i = wi * 32 + xx * 16 + (lane & 15);
+        af[xx] = i < M1 ? tb.s2[(long)(q0 + kk) * M1p + i] : 0.0;
+      }
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy) bf[yy] = sH[kk * ldh + wj * 32 + yy * 16 + (lane & 15)];
+#pragma unroll
+      for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy)
+          acc[xx][yy] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[xx], bf[yy], acc[xx][yy], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
   const UnitView v = decode_unit(tb, a, u);
   const double tau = tb.inst[(long)v.b * NSCAL + v.tau_slot];
-  const double rz = cs[CG_RZ], bn = cs[CG_BN], dbar = cs[CG_DBAR];
-  const double it = cs[CG_IT] + 1.0;
-  const int Mb = M1 * M1;
   const long o = (long)u * Mp;
-  double ap[CG_E];
+  // the lane's entries: (xx, yy, e) -> i = wi 32 + xx 16 + (lane >> 4) + 4e, j = wj 32 + yy 16 + (lane & 15)
+  if (INIT) {
+    const int Jp = 2 * M1p + 1;
+    const double* m = a.mom + (long)u * Jp * Jp;
+    const double pi2 = kPi * kPi;
+    double bn = 0.0, rz = 0.0, rn = 0.0;
+#pragma unroll
+    for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = wi * 32 + xx * 16 + (lane >> 4) + 4 * e, j = wj * 32 + yy * 16 + (lane & 15);
+          if (i >= M1 || j >= M1) continue;
+          const int k = i * M1 + j;
+          const int s1 = 2 * (i + 1), s2 = 2 * (j + 1);
+          const double m00 = m[0], m0s = m[s2], ms0 = m[(long)s1 * Jp], mss = m[(long)s1 * Jp + s2];
+          const double K1 = (double)(i + 1), K2 = (double)(j + 1);
+          const double kdiag = K1 * K1 * pi2 * (((m00 - m0s) + ms0) - mss) +
+                               K2 * K2 * pi2 * (((m00 + m0s) - ms0) - mss);
+          const double dk = 1.0 + tau * kdiag;
+          const double b = a.rhs[o + k], xk = x0[o + k];
+          const double rk = b - (xk + tau * acc[xx][yy][e]);
+          const double zk = rk / dk;
+          pd[o + k] = dk;
+          x[o + k] = xk;
+          r[o + k] = rk;
+          p[o + k] = zk;
+          bn += b * b;
+          rz += rk * zk;
+          rn += rk * rk;
+        }
+    for (int k = M1 * M1 + tid; k < Mp; k += KV_T) {  // padding of the coefficient vector
+      x[o + k] = 0.0;
+      r[o + k] = 0.0;
+      p[o + k] = 0.0;
+    }
+    bn = block_sum(bn, red);
+    rz = block_sum(rz, red);
+    rn = block_sum(rn, red);
+    if (bn == 0.0) {  // zero right-hand side: the solution is 0
+#pragma unroll
+      for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = wi * 32 + xx * 16 + (lane >> 4) + 4 * e, j = wj * 32 + yy * 16 + (lane & 15);
+            if (i < M1 && j < M1) x[o + i * M1 + j] = 0.0;
+          }
+    }
+    if (tid == 0) {
+      cs[CG_RZ] = rz;
+      cs[CG_BN] = bn;
+      cs[CG_ST] = (bn == 0.0 || rn <= CG_TOL2 * bn) ? CG_DONE : CG_ACTIVE;
+      cs[CG_IT] = 0.0;
+    }
+    return;
+  }
+  const double rz = cs[CG_RZ], bn = cs[CG_BN];
+  const double it = cs[CG_IT] + 1.0;
+  double ap[2][2][4];
   double pap = 0.0;
 #pragma unroll
-  for (int e = 0; e < CG_E; ++e) {
-    const int k = tid + e * CG_T;
-    ap[e] = 0.0;
-    if (k < Mb) {
-      const double pk = p[o + k];
-      ap[e] = pk + tau * kp[o + k];
-      pap += pk * ap[e];
-    }
-  }
+  for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = wi * 32 + xx * 16 + (lane >> 4) + 4 * e, j = wj * 32 + yy * 16 + (lane & 15);
+        ap[xx][yy][e] = 0.0;
+        if (i >= M1 || j >= M1) continue;
+        const double pk = p[o + i * M1 + j];
+        ap[xx][yy][e] = pk + tau * acc[xx][yy][e];
+        pap += pk * ap[xx][yy][e];
+      }
   pap = block_sum(pap, red);
   const double al = rz / pap;
   double rn = 0.0, rz1 = 0.0;
-  double zz[CG_E];
 #pragma unroll
-  for (int e = 0; e < CG_E; ++e) {
-    const int k = tid + e * CG_T;
-    zz[e] = 0.0;
-    if (k < Mb) {
-      x[o + k] += al * p[o + k];
-      const double rk = r[o + k] - al * ap[e];
-      r[o + k] = rk;
-      zz[e] = rk / cg_pdiag(k, M1, tau, dbar);
-      rn += rk * rk;
-      rz1 += rk * zz[e];
-    }
-  }
+  for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = wi * 32 + xx * 16 + (lane >> 4) + 4 * e, j = wj * 32 + yy * 16 + (lane & 15);
+        if (i >= M1 || j >= M1) continue;
+        const long k = o + i * M1 + j;
+        x[k] += al * p[k];
+        const double rk = r[k] - al * ap[xx][yy][e];
+        r[k] = rk;
+        const double zk = rk / pd[k];
+        ap[xx][yy][e] = zk;  // z from here on
+        rn += rk * rk;
+        rz1 += rk * zk;
+      }
   rn = block_sum(rn, red);
   rz1 = block_sum(rz1, red);
   const bool done = rn <= CG_TOL2 * bn;
   if (!done) {
     const double be = rz1 / rz;
 #pragma unroll
-    for (int e = 0; e < CG_E; ++e) {
-      const int k = tid + e * CG_T;
-      if (k < Mb) p[o + k] = zz[e] + be * p[o + k];
-    }
+    for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = wi * 32 + xx * 16 + (lane >> 4) + 4 * e, j = wj * 32 + yy * 16 + (lane & 15);
+          if (i >= M1 || j >= M1) continue;
+          const long k = o + i * M1 + j;
+          p[k] = ap[xx][yy][e] + be * p[k];
+        }
   }
   if (tid == 0) {
     cs[CG_RZ] = rz1;
@@ -178,18 +259,16 @@ __global__ void k_cg_finish(Tables tb, StepArgs a, Epilogue ep, int units, const
   epi_store(a, ep, u, v.slot, last, k, x[idx]);
 }
 
-hipError_t launch_cg_init(const Tables& tb, const StepArgs& a, int units, const double* x0,
-                          const double* kx, double* x, double* r, double* p, double* cgs,
-                          hipStream_t s) {
-  if (tb.Mp > CG_T * CG_E) return hipErrorInvalidValue;
-  k_cg_init<<<units, CG_T, 0, s>>>(tb, a, x0, kx, x, r, p, cgs);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_update(const Tables& tb, const StepArgs& a, int units, double* x, double* r,
-                            double* p, const double* kp, double* cgs, int cap, hipStream_t s) {
-  if (tb.Mp > CG_T * CG_E) return hipErrorInvalidValue;
-  k_cg_update<<<units, CG_T, 0, s>>>(tb, a, x, r, p, kp, cgs, cap);
+hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const double* G,
+                          const double* x0, double* x, double* r, double* p, double* pd,
+                          double* cgs, int cap, bool init, hipStream_t s) {
+  if (tb.M1 > 64) return hipErrorInvalidValue;  // the unit's M1 x M1 product is one 64 x 64 tile
+  const size_t lds = sizeof(double) * (16 * (tb.Qp + 1) + 16 * 65 + KV_T);
+  if (lds > 65536) return hipErrorInvalidValue;  // Qp up to 432
+  if (init)
+    k_cg_step<1><<<units, KV_T, lds, s>>>(tb, a, G, x0, x, r, p, pd, cgs, cap);
+  else
+    k_cg_step<0><<<units, KV_T, lds, s>>>(tb, a, G, x0, x, r, p, pd, cgs, cap);
   return hipGetLastError();
 }
 

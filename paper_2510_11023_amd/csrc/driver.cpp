@@ -39,9 +39,9 @@ struct Layout {
   size_t g, mom, F, C2, T2, q;
   size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
   size_t b12 = 0, s2 = 0;    // 2D: stacked basis tables of the separable stiffness products
-  // conjugate-gradient solves (solver = 1): x, r, p, K p [units][Mp]; G [units][2][Qp][Qp];
-  // H [units][2 Qp][M1p]; per-unit scalars [units][8]; two counters
-  size_t cgx = 0, cgr = 0, cgp = 0, cgkp = 0, cgG = 0, cgH = 0, cgs = 0, cgcnt = 0;
+  // conjugate-gradient solves (solver = 1): x, r, p, Jacobi diagonal [units][Mp];
+  // G [units][2][Qp][Qp]; per-unit scalars [units][8]; two counters
+  size_t cgx = 0, cgr = 0, cgp = 0, cgpd = 0, cgG = 0, cgs = 0, cgcnt = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -153,9 +153,8 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
     L.cgx = take(cur, D * units * Mp);
     L.cgr = take(cur, D * units * Mp);
     L.cgp = take(cur, D * units * Mp);
-    L.cgkp = take(cur, D * units * Mp);
+    L.cgpd = take(cur, D * units * Mp);
     L.cgG = take(cur, D * units * 2 * Qp * Qp);
-    L.cgH = take(cur, D * units * 2 * Qp * M1p);
     L.cgs = take(cur, D * units * 8);
     L.cgcnt = take(cur, 2 * sizeof(int32_t));
   }
@@ -285,37 +284,37 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 //   factorisation through device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
   if (c.tb.dim == 2 && c.pcg) {
-    // separable products (lagged state, D, f, load vector), the history sums and the
-    // right-hand side, then conjugate gradients from the lagged state with K applied
-    // separably; the host looks at the units' status every 4 iterations
+    // separable products (lagged state, D, f, load vector, cosine moments for the Jacobi
+    // diagonal), the history sums and the right-hand side, then conjugate gradients from the
+    // lagged state with K applied separably; the host looks at the units' status every 4
+    // iterations
     L1PR_TRY(timed("products2d", a, units, c.s, [&] {
-      return launch_step2d_products(c.tb, a, units, a.C2, a.T2, a.mom, c.s, false);
+      return launch_step2d_products(c.tb, a, units, a.C2, a.T2, a.mom, c.s);
     }));
     L1PR_TRY(timed("history", a, units, c.s, [&] { return launch_history(c.tb, a, units, a.rhs, c.s); }));
     L1PR_TRY(timed("rhs", a, units, c.s, [&] { return launch_form_rhs(c.tb, a, units, c.s); }));
     double* x = c.ptr(c.L.cgx);
     double* r = c.ptr(c.L.cgr);
     double* p = c.ptr(c.L.cgp);
-    double* kp = c.ptr(c.L.cgkp);
+    double* pd = c.ptr(c.L.cgpd);
     double* G = c.ptr(c.L.cgG);
-    double* H = c.ptr(c.L.cgH);
     double* cgs = c.ptr(c.L.cgs);
     int32_t* cnt = reinterpret_cast<int32_t*>(c.ws + c.L.cgcnt);
-    auto apply = [&](const double* v) {
-      return timed("cg_apply", a, units, c.s, [&] {
-        return launch_stiff2d_apply(c.tb, a, units, v, kp, a.T2, G, H, c.s);
+    auto grid = [&](const double* v) {
+      return timed("cg_grid", a, units, c.s, [&] {
+        return launch_stiff2d_grid(c.tb, a, units, v, a.T2, G, c.s);
       });
     };
-    L1PR_TRY(apply(a.C2));
-    L1PR_TRY(timed("cg_update", a, units, c.s, [&] {
-      return launch_cg_init(c.tb, a, units, a.C2, kp, x, r, p, cgs, c.s);
+    L1PR_TRY(grid(a.C2));
+    L1PR_TRY(timed("cg_step", a, units, c.s, [&] {
+      return launch_cg_step(c.tb, a, units, G, a.C2, x, r, p, pd, cgs, kCgCap, true, c.s);
     }));
     bool done = false;
     for (int it = 0; it < kCgCap && !done; it += kCgCheck) {
       for (int j = 0; j < kCgCheck; ++j) {
-        L1PR_TRY(apply(p));
-        L1PR_TRY(timed("cg_update", a, units, c.s, [&] {
-          return launch_cg_update(c.tb, a, units, x, r, p, kp, cgs, kCgCap, c.s);
+        L1PR_TRY(grid(p));
+        L1PR_TRY(timed("cg_step", a, units, c.s, [&] {
+          return launch_cg_step(c.tb, a, units, G, nullptr, x, r, p, pd, cgs, kCgCap, false, c.s);
         }));
       }
       int32_t h[2] = {0, 0};

@@ -203,33 +203,24 @@ hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units
                BG_STORE, tb, a, nullptr, s);
 }
 
-// Kv = K V for every unit (the stiffness without tau, as the quadrature sum of the bilinear
-// form, separably):  T12 = V [phi^T | dphi^T]  (M1 x 2Qp);  Gx = dphi T12[:, :Qp] o Dw,
-// Gy = phi T12[:, Qp:] o Dw  (Qp x Qp, the x and y derivatives at the Gauss points times
-// w w D);  H = [Gx phi; Gy dphi]  (2Qp x M1);  Kv = [dphi; phi]^T H.  V and Kv hold the M1 x M1
-// coefficient matrix of each unit at stride Mp (entries past M1^2 are not touched).
-// Scratch per unit: T12 [M1p][2Qp], G [2][Qp][Qp], H [2Qp][M1p].
-hipError_t launch_stiff2d_apply(const Tables& tb, const StepArgs& a, int units, const double* V,
-                                double* Kv, double* T12, double* G, double* H, hipStream_t s) {
+// First half of K V for every unit (the stiffness without tau, as the quadrature sum of the
+// bilinear form, separably): T12 = V [phi^T | dphi^T]  (M1 x 2Qp), then
+// G = [Gx; Gy] = [dphi T12[:, :Qp]; phi T12[:, Qp:]] o (w w D)  (2Qp x Qp: the x and y
+// derivatives at the Gauss points times w_i w_j D_ij, zero at padding nodes).  The second half,
+// K V = dphi^T Gx phi + phi^T Gy dphi, is fused into the conjugate-gradient step.  V holds the
+// M1 x M1 coefficient matrix of each unit at stride Mp.  Scratch: T12 [units][M1p][2Qp].
+hipError_t launch_stiff2d_grid(const Tables& tb, const StepArgs& a, int units, const double* V,
+                               double* T12, double* G, hipStream_t s) {
   const int M1 = tb.M1, M1p = tb.M1p, Qp = tb.Qp, Mp = tb.Mp;
-  const long sT = (long)M1p * 2 * Qp, sG = 2L * Qp * Qp, sH = 2L * Qp * M1p;
+  const long sT = (long)M1p * 2 * Qp, sG = 2L * Qp * Qp;
   hipError_t r = bgemm(BOp{V, M1, Mp, 0}, BOp{tb.b12, 2 * Qp, 0, 0}, T12, 2 * Qp, sT, M1, 2 * Qp,
                        M1, units, BG_STORE, tb, a, nullptr, s);
   if (r != hipSuccess) return r;
   r = bgemm(BOp{tb.dphi, M1p, 0, 0}, BOp{T12, 2 * Qp, sT, 0}, G, Qp, sG, Qp, Qp, M1, units, BG_MULD,
             tb, a, nullptr, s);
   if (r != hipSuccess) return r;
-  r = bgemm(BOp{tb.phi, M1p, 0, 0}, BOp{T12 + Qp, 2 * Qp, sT, 0}, G + (long)Qp * Qp, Qp, sG, Qp, Qp,
-            M1, units, BG_MULD, tb, a, nullptr, s);
-  if (r != hipSuccess) return r;
-  r = bgemm(BOp{G, Qp, sG, 0}, BOp{tb.phi, M1p, 0, 0}, H, M1p, sH, Qp, M1, Qp, units, BG_STORE, tb,
-            a, nullptr, s);
-  if (r != hipSuccess) return r;
-  r = bgemm(BOp{G + (long)Qp * Qp, Qp, sG, 0}, BOp{tb.dphi, M1p, 0, 0}, H + (long)Qp * M1p, M1p, sH,
-            Qp, M1, Qp, units, BG_STORE, tb, a, nullptr, s);
-  if (r != hipSuccess) return r;
-  return bgemm(BOp{tb.s2, M1p, 0, 1}, BOp{H, M1p, sH, 0}, Kv, M1, Mp, M1, M1, 2 * Qp, units,
-               BG_STORE, tb, a, nullptr, s);
+  return bgemm(BOp{tb.phi, M1p, 0, 0}, BOp{T12 + Qp, 2 * Qp, sT, 0}, G + (long)Qp * Qp, Qp, sG, Qp,
+               Qp, M1, units, BG_MULD, tb, a, nullptr, s);
 }
 
 hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, const double* mom,
