@@ -78,16 +78,29 @@ __global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const d
     __syncthreads();
     // H = G[q0 .. q0+15] T with T = phi (rows of Gx) or dphi (rows of Gy); wave w: columns
     // 16w .. 16w+15
-    const double* T = q0 < Qp ? tb.phi : tb.dphi;
-    d4 h = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k4 = 0; k4 < Qp; k4 += 4) {
-      const int kk = k4 + (lane >> 4);
-      const double av = sG[(lane & 15) * ldg + kk];
-      const double bv = hcol < M1 ? T[(long)kk * M1p + hcol] : 0.0;
-      h = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, h, 0, 0, 0);
+    // 16 rows of T per group (Qp is a multiple of 16): the next group's table entries are
+    // loaded while the current group's four MFMAs run, and two accumulators alternate
+    const double* Tc = (q0 < Qp ? tb.phi : tb.dphi) + (lane >> 4) * M1p + (hcol < M1 ? hcol : 0);
+    const double tmask = hcol < M1 ? 1.0 : 0.0;
+    const double* sGr = sG + (lane & 15) * ldg + (lane >> 4);
+    d4 h0 = d4{0.0, 0.0, 0.0, 0.0}, h1 = d4{0.0, 0.0, 0.0, 0.0};
+    double bv[4], bn[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) bv[g] = Tc[(long)(4 * g) * M1p];
+    for (int k0 = 0; k0 < Qp; k0 += 16) {
+      const int kn = k0 + 16 < Qp ? k0 + 16 : k0;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) bn[g] = Tc[(long)(kn + 4 * g) * M1p];
+#pragma unroll
+      for (int g = 0; g < 4; g += 2) {
+        h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(sGr[k0 + 4 * g], bv[g] * tmask, h0, 0, 0, 0);
+        h1 = __builtin_amdgcn_mfma_f64_16x16x4f64(sGr[k0 + 4 * g + 4], bv[g + 1] * tmask, h1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) bv[g] = bn[g];
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sH[((lane >> 4) + 4 * v) * ldh + hcol] = h[v];
+    for (int v = 0; v < 4; ++v) sH[((lane >> 4) + 4 * v) * ldh + hcol] = h0[v] + h1[v];
     __syncthreads();
     // Kp += [dphi; phi][q0 .. q0+15]^T H
 #pragma unroll
