@@ -537,14 +537,16 @@ def main():
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-full-history", action="store_true")
     ap.add_argument("--no-paper-model", action="store_true")
-    ap.add_argument("--mode", choices=["full", "kernels", "kernels2d", "kernelsfh", "fullhistory"],
+    ap.add_argument("--mode", choices=["full", "kernels", "kernels2d", "kernelsfh", "fullhistory",
+                                       "cg2d"],
                     default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
                          "device copy (for hardware-counter runs); kernels2d: one fine sweep of "
                          "the 2D workload (128 slices) and the same copy; kernelsfh: one "
                          "full-history parareal sweep of the alpha=0.3 batch and the same copy; "
                          "none of these prints a JSON line; fullhistory: only the full-history "
-                         "parareal section (its JSON)")
+                         "parareal section (its JSON); cg2d: only the config-3 conjugate-gradient "
+                         "section (its JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; a run on several GPUs is not supported "
@@ -596,6 +598,10 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         log("kernelsfh mode done")
+        return
+
+    if args.mode == "cg2d":
+        print(json.dumps(config3_cg(l1, torch, W, dev)), flush=True)
         return
 
     if args.mode == "fullhistory":

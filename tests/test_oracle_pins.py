@@ -573,3 +573,31 @@ def test_paper_u0_coefficients_closed_form():
     xs = np.linspace(0, 1, 101)
     rec = math.sqrt(2) * np.sin(np.outer(xs, k) * math.pi) @ c
     assert np.max(np.abs(rec - xs ** 4 * (1 - xs) ** 4)) < 1e-7
+
+
+def test_2d_stiffness_equals_separable_quadrature_products():
+    """The oracle's assembled 2D stiffness K against the separable form of the same quadrature
+    sum, dphi^T (wwD o dphi V phi^T) phi + phi^T (wwD o phi V dphi^T) dphi, evaluated with
+    numpy's Gauss-Legendre rule on a random V (the form the iterative solve applies)."""
+    import math
+
+    from paper_2510_11023_amd import workloads as W
+
+    oracle = pytest.importorskip("oracle")
+    oracle.lib()
+    for M, Q in ((6, 10), (9, 14)):
+        kw = dict(W.C3, modes=M, quad=Q, steps=12, slices=3)
+        p = oracle.problem(**kw)
+        c = W.u0_random_2d(M, 3)
+        K, _ = oracle.galerkin(p, c, 0.3, 0.3)
+        x, w = np.polynomial.legendre.leggauss(Q)
+        x, w = (x + 1) / 2, w / 2
+        k = np.arange(1, M + 1)
+        phi = math.sqrt(2) * np.sin(np.outer(x, k) * math.pi)
+        dphi = math.sqrt(2) * (k * math.pi) * np.cos(np.outer(x, k) * math.pi)
+        U = phi @ c.reshape(M, M) @ phi.T
+        Dw = np.outer(w, w) * (1 + 0.5 * np.exp(-U ** 2))
+        V = np.random.default_rng(1).standard_normal((M, M))
+        Kv = dphi.T @ (Dw * (dphi @ V @ phi.T)) @ phi + phi.T @ (Dw * (phi @ V @ dphi.T)) @ dphi
+        ref = (K @ V.reshape(-1)).reshape(M, M)
+        assert np.linalg.norm(Kv - ref) <= 1e-13 * np.linalg.norm(ref)
