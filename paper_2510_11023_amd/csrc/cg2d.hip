@@ -37,90 +37,122 @@ __device__ inline double block_sum(double v, double* red) {
   return r;
 }
 
-// One conjugate-gradient step (INIT = 0) or the start (INIT = 1) for the unit of each
-// work-group, fused with the second half of the stiffness product: from G = [Gx; Gy]
-// (launch_stiff2d_grid; 2Qp x Qp per unit), Kp = [dphi; phi]^T [Gx phi; Gy dphi] is summed over
-// 16-row chunks of G on FP64 MFMA 16x16x4 (chunk rows staged in LDS, H = chunk x table per
-// wave, then Kp += [dphi; phi]_chunk^T H), and stays in the accumulators: entry (i, j) of the
-// M1 x M1 coefficient matrix, k = i M1 + j, belongs to one lane.  Then, for INIT, the Jacobi
-// diagonal d_k = 1 + tau K_kk (from the cosine moments), x = x0, r = rhs - (x0 + tau K x0),
-// z = r / d, p = z; otherwise the CG update with Ap = p + tau K p.  Dot products are
-// per-lane sums followed by the fixed tree.
+// The second half of the stiffness product, K p = [dphi; phi]^T [Gx phi; Gy dphi], from
+// G = [Gx; Gy] (launch_stiff2d_grid; 2Qp x Qp per unit), one work-group per (16-row chunk of G,
+// unit): the chunk's rows staged in LDS, H = chunk x table on FP64 MFMA 16x16x4 (the table
+// operands loaded one 16-row group ahead, two accumulators), then the chunk's share
+// [dphi; phi]_chunk^T H of the M1 x M1 result, written as a partial in the accumulator layout:
+// kvp[u][c][tid][16], entry (i, j) (k = i M1 + j) held by one lane.  Spreading a unit over its
+// 2Qp/16 chunks keeps single-unit steps off a single CU; the step kernel sums the partials in
+// chunk order, so the arithmetic never depends on the number of units in a launch.
 constexpr int KV_T = 256;
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// lane entries: (xx, yy, e) -> i = wi 32 + xx 16 + (lane >> 4) + 4 e, j = wj 32 + yy 16 + (lane & 15)
 template <int INIT>
-__global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const double* G,
-                                                  const double* x0, double* x, double* r,
-                                                  double* p, double* pd, double* cgs, int cap) {
+__global__ __launch_bounds__(KV_T) void k_cg_part(Tables tb, const double* G, double* kvp,
+                                                  const double* cgs) {
   extern __shared__ double sm[];
-  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int M1 = tb.M1, M1p = tb.M1p, Qp = tb.Qp, Mp = tb.Mp;
-  double* cs = cgs + (long)u * CG_NS;
-  if (!INIT && cs[CG_ST] != CG_ACTIVE) return;  // the same for the whole work-group
+  const int c = blockIdx.x, u = blockIdx.y, nch = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M1 = tb.M1, M1p = tb.M1p, Qp = tb.Qp;
+  if (!INIT && cgs[(long)u * CG_NS + CG_ST] != CG_ACTIVE) return;
   const int ldg = Qp + 1, ldh = 65;
   double* sG = sm;
   double* sH = sG + 16 * ldg;
-  double* red = sH + 16 * ldh;
   const double* Gu = G + (long)u * 2 * Qp * Qp;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int hcol = wave * 16 + (lane & 15);
+  const int q0 = 16 * c;
+  for (int e = tid; e < 16 * Qp; e += KV_T) {
+    const int rr = e / Qp, q = e % Qp;
+    sG[rr * ldg + q] = Gu[(long)(q0 + rr) * Qp + q];
+  }
+  __syncthreads();
+  // H = G[q0 .. q0+15] T with T = phi (rows of Gx) or dphi (rows of Gy); wave w: columns
+  // 16w .. 16w+15.  16 rows of T per group (Qp is a multiple of 16).
+  const double* Tc = (q0 < Qp ? tb.phi : tb.dphi) + (lane >> 4) * M1p + (hcol < M1 ? hcol : 0);
+  const double tmask = hcol < M1 ? 1.0 : 0.0;
+  const double* sGr = sG + (lane & 15) * ldg + (lane >> 4);
+  d4 h0 = d4{0.0, 0.0, 0.0, 0.0}, h1 = d4{0.0, 0.0, 0.0, 0.0};
+  double bv[4], bn[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) bv[g] = Tc[(long)(4 * g) * M1p];
+  for (int k0 = 0; k0 < Qp; k0 += 16) {
+    const int kn = k0 + 16 < Qp ? k0 + 16 : k0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) bn[g] = Tc[(long)(kn + 4 * g) * M1p];
+#pragma unroll
+    for (int g = 0; g < 4; g += 2) {
+      h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(sGr[k0 + 4 * g], bv[g] * tmask, h0, 0, 0, 0);
+      h1 = __builtin_amdgcn_mfma_f64_16x16x4f64(sGr[k0 + 4 * g + 4], bv[g + 1] * tmask, h1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) bv[g] = bn[g];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) sH[((lane >> 4) + 4 * v) * ldh + hcol] = h0[v] + h1[v];
+  __syncthreads();
+  // partial = [dphi; phi][q0 .. q0+15]^T H
+  d4 acc[2][2];
+#pragma unroll
+  for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy) acc[xx][yy] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k4 = 0; k4 < 16; k4 += 4) {
+    const int kk = k4 + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int xx = 0; xx < 2; ++xx) {
+      const int i = wi * 32 + xx * 16 + (lane & 15);
+      af[xx] = i < M1 ? tb.s2[(long)(q0 + kk) * M1p + i] : 0.0;
+    }
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy) bf[yy] = sH[kk * ldh + wj * 32 + yy * 16 + (lane & 15)];
+#pragma unroll
+    for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+      for (int yy = 0; yy < 2; ++yy)
+        acc[xx][yy] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[xx], bf[yy], acc[xx][yy], 0, 0, 0);
+  }
+  double* out = kvp + (((long)u * nch + c) * KV_T + tid) * 16;
+#pragma unroll
+  for (int xx = 0; xx < 2; ++xx)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[(xx * 2 + yy) * 4 + e] = acc[xx][yy][e];
+}
+
+// One conjugate-gradient step (INIT = 0) or the start (INIT = 1) for the unit of each
+// work-group, with K p (K x0) = the sum of the unit's nch partials in chunk order.  INIT: the
+// Jacobi diagonal d_k = 1 + tau K_kk (from the cosine moments), x = x0, r = rhs - (x0 + tau K x0),
+// z = r / d, p = z.  Otherwise the CG update with Ap = p + tau K p.  Dot products are per-lane
+// sums followed by the fixed tree.
+template <int INIT>
+__global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const double* kvp,
+                                                  int nch, const double* x0, double* x, double* r,
+                                                  double* p, double* pd, double* cgs, int cap) {
+  __shared__ double red[KV_T];
+  const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M1 = tb.M1, M1p = tb.M1p, Mp = tb.Mp;
+  double* cs = cgs + (long)u * CG_NS;
+  if (!INIT && cs[CG_ST] != CG_ACTIVE) return;  // the same for the whole work-group
   const int wi = wave >> 1, wj = wave & 1;
   d4 acc[2][2];
 #pragma unroll
   for (int xx = 0; xx < 2; ++xx)
 #pragma unroll
     for (int yy = 0; yy < 2; ++yy) acc[xx][yy] = d4{0.0, 0.0, 0.0, 0.0};
-  const int hcol = wave * 16 + (lane & 15);
-  for (int q0 = 0; q0 < 2 * Qp; q0 += 16) {
-    for (int e = tid; e < 16 * Qp; e += KV_T) {
-      const int rr = e / Qp, q = e % Qp;
-      sG[rr * ldg + q] = Gu[(long)(q0 + rr) * Qp + q];
-    }
-    __syncthreads();
-    // H = G[q0 .. q0+15] T with T = phi (rows of Gx) or dphi (rows of Gy); wave w: columns
-    // 16w .. 16w+15
-    // 16 rows of T per group (Qp is a multiple of 16): the next group's table entries are
-    // loaded while the current group's four MFMAs run, and two accumulators alternate
-    const double* Tc = (q0 < Qp ? tb.phi : tb.dphi) + (lane >> 4) * M1p + (hcol < M1 ? hcol : 0);
-    const double tmask = hcol < M1 ? 1.0 : 0.0;
-    const double* sGr = sG + (lane & 15) * ldg + (lane >> 4);
-    d4 h0 = d4{0.0, 0.0, 0.0, 0.0}, h1 = d4{0.0, 0.0, 0.0, 0.0};
-    double bv[4], bn[4];
+  for (int c = 0; c < nch; ++c) {
+    const double* in = kvp + (((long)u * nch + c) * KV_T + tid) * 16;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) bv[g] = Tc[(long)(4 * g) * M1p];
-    for (int k0 = 0; k0 < Qp; k0 += 16) {
-      const int kn = k0 + 16 < Qp ? k0 + 16 : k0;
+    for (int xx = 0; xx < 2; ++xx)
 #pragma unroll
-      for (int g = 0; g < 4; ++g) bn[g] = Tc[(long)(kn + 4 * g) * M1p];
+      for (int yy = 0; yy < 2; ++yy)
 #pragma unroll
-      for (int g = 0; g < 4; g += 2) {
-        h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(sGr[k0 + 4 * g], bv[g] * tmask, h0, 0, 0, 0);
-        h1 = __builtin_amdgcn_mfma_f64_16x16x4f64(sGr[k0 + 4 * g + 4], bv[g + 1] * tmask, h1, 0, 0, 0);
-      }
-#pragma unroll
-      for (int g = 0; g < 4; ++g) bv[g] = bn[g];
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sH[((lane >> 4) + 4 * v) * ldh + hcol] = h0[v] + h1[v];
-    __syncthreads();
-    // Kp += [dphi; phi][q0 .. q0+15]^T H
-#pragma unroll
-    for (int k4 = 0; k4 < 16; k4 += 4) {
-      const int kk = k4 + (lane >> 4);
-      double af[2], bf[2];
-#pragma unroll
-      for (int xx = 0; xx < 2; ++xx) {
-        const int i = wi * 32 + xx * 16 + (lane & 15);
-        af[xx] = i < M1 ? tb.s2[(long)(q0 + kk) * M1p + i] : 0.0;
-      }
-#pragma unroll
-      for (int yy = 0; yy < 2; ++yy) bf[yy] = sH[kk * ldh + wj * 32 + yy * 16 + (lane & 15)];
-#pragma unroll
-      for (int xx = 0; xx < 2; ++xx)
-#pragma unroll
-        for (int yy = 0; yy < 2; ++yy)
-          acc[xx][yy] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[xx], bf[yy], acc[xx][yy], 0, 0, 0);
-    }
-    __syncthreads();
+        for (int e = 0; e < 4; ++e) acc[xx][yy][e] += in[(xx * 2 + yy) * 4 + e];
   }
 
   const UnitView v = decode_unit(tb, a, u);
@@ -273,15 +305,20 @@ __global__ void k_cg_finish(Tables tb, StepArgs a, Epilogue ep, int units, const
 }
 
 hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const double* G,
-                          const double* x0, double* x, double* r, double* p, double* pd,
-                          double* cgs, int cap, bool init, hipStream_t s) {
+                          double* kvp, const double* x0, double* x, double* r, double* p,
+                          double* pd, double* cgs, int cap, bool init, hipStream_t s) {
   if (tb.M1 > 64) return hipErrorInvalidValue;  // the unit's M1 x M1 product is one 64 x 64 tile
-  const size_t lds = sizeof(double) * (16 * (tb.Qp + 1) + 16 * 65 + KV_T);
-  if (lds > 65536) return hipErrorInvalidValue;  // Qp up to 432
-  if (init)
-    k_cg_step<1><<<units, KV_T, lds, s>>>(tb, a, G, x0, x, r, p, pd, cgs, cap);
-  else
-    k_cg_step<0><<<units, KV_T, lds, s>>>(tb, a, G, x0, x, r, p, pd, cgs, cap);
+  const size_t lds = sizeof(double) * (16 * (tb.Qp + 1) + 16 * 65);
+  if (lds > 65536) return hipErrorInvalidValue;  // Qp up to 444
+  const int nch = 2 * tb.Qp / 16;
+  const dim3 gp(nch, units);
+  if (init) {
+    k_cg_part<1><<<gp, KV_T, lds, s>>>(tb, G, kvp, cgs);
+    k_cg_step<1><<<units, KV_T, 0, s>>>(tb, a, kvp, nch, x0, x, r, p, pd, cgs, cap);
+  } else {
+    k_cg_part<0><<<gp, KV_T, lds, s>>>(tb, G, kvp, cgs);
+    k_cg_step<0><<<units, KV_T, 0, s>>>(tb, a, kvp, nch, x0, x, r, p, pd, cgs, cap);
+  }
   return hipGetLastError();
 }
 

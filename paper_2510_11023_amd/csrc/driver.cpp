@@ -40,8 +40,9 @@ struct Layout {
   size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
   size_t b12 = 0, s2 = 0;    // 2D: stacked basis tables of the separable stiffness products
   // conjugate-gradient solves (solver = 1): x, r, p, Jacobi diagonal [units][Mp];
-  // G [units][2][Qp][Qp]; per-unit scalars [units][8]; two counters
-  size_t cgx = 0, cgr = 0, cgp = 0, cgpd = 0, cgG = 0, cgs = 0, cgcnt = 0;
+  // G [units][2][Qp][Qp]; partial products [units][2Qp/16][4096]; per-unit scalars [units][8];
+  // two counters
+  size_t cgx = 0, cgr = 0, cgp = 0, cgpd = 0, cgG = 0, cgkv = 0, cgs = 0, cgcnt = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -155,6 +156,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
     L.cgp = take(cur, D * units * Mp);
     L.cgpd = take(cur, D * units * Mp);
     L.cgG = take(cur, D * units * 2 * Qp * Qp);
+    L.cgkv = take(cur, D * units * (2 * Qp / 16) * 4096);
     L.cgs = take(cur, D * units * 8);
     L.cgcnt = take(cur, 2 * sizeof(int32_t));
   }
@@ -298,23 +300,24 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
     double* p = c.ptr(c.L.cgp);
     double* pd = c.ptr(c.L.cgpd);
     double* G = c.ptr(c.L.cgG);
+    double* kv = c.ptr(c.L.cgkv);
     double* cgs = c.ptr(c.L.cgs);
     int32_t* cnt = reinterpret_cast<int32_t*>(c.ws + c.L.cgcnt);
     auto grid = [&](const double* v) {
       return timed("cg_grid", a, units, c.s, [&] {
-        return launch_stiff2d_grid(c.tb, a, units, v, a.T2, G, c.s);
+        return launch_stiff2d_grid(c.tb, a, units, v, G, c.s);
       });
     };
     L1PR_TRY(grid(a.C2));
     L1PR_TRY(timed("cg_step", a, units, c.s, [&] {
-      return launch_cg_step(c.tb, a, units, G, a.C2, x, r, p, pd, cgs, kCgCap, true, c.s);
+      return launch_cg_step(c.tb, a, units, G, kv, a.C2, x, r, p, pd, cgs, kCgCap, true, c.s);
     }));
     bool done = false;
     for (int it = 0; it < kCgCap && !done; it += kCgCheck) {
       for (int j = 0; j < kCgCheck; ++j) {
         L1PR_TRY(grid(p));
         L1PR_TRY(timed("cg_step", a, units, c.s, [&] {
-          return launch_cg_step(c.tb, a, units, G, nullptr, x, r, p, pd, cgs, kCgCap, false, c.s);
+          return launch_cg_step(c.tb, a, units, G, kv, nullptr, x, r, p, pd, cgs, kCgCap, false, c.s);
         }));
       }
       int32_t h[2] = {0, 0};

@@ -21,7 +21,7 @@ struct BOp {
   int trans;
 };
 
-enum { BG_STORE = 0, BG_EVAL2D = 1, BG_MULD = 2 };
+enum { BG_STORE = 0, BG_EVAL2D = 1 };
 
 constexpr int BT = 64, BK = 16;
 
@@ -29,7 +29,6 @@ constexpr int BT = 64, BK = 16;
 // with 2 x 2 FP64 MFMA 16x16x4 tiles each, operands staged through LDS in chunks of 16.
 // Each output is a fixed-order sum over its own row and column.  BG_EVAL2D: the product is
 // the lagged state u at (x_i, x_j); the epilogue writes d = w_i w_j D and g = w_i w_j f.
-// BG_MULD: the product times the unit's w_i w_j D_ij.
 __global__ __launch_bounds__(256) void k_bgemm(BOp A, BOp B, double* C, long ldc, long sc, int m,
                                                int n, int kd, int epi, Tables tb, StepArgs a,
                                                double* gout) {
@@ -97,9 +96,6 @@ __global__ __launch_bounds__(256) void k_bgemm(BOp A, BOp B, double* C, long ldc
         const long o = (long)u * sc + (long)i * ldc + j;
         if (epi == BG_STORE) {
           C[o] = val;
-        } else if (epi == BG_MULD) {  // times w_i w_j D_ij of the unit (a.d, [Qp][Qp], set
-                                      // for i, j < Q only; padding nodes carry no weight)
-          C[o] = (i < tb.Q && j < tb.Q) ? val * a.d[((long)u * tb.Qp + i) * tb.Qp + j] : 0.0;
         } else {
           const double w = tb.wq[i] * tb.wq[j], X = tb.xq[i], Y = tb.xq[j];
           C[o] = w * coef_D(tb.d_sel, tb.d_param, val);
@@ -204,23 +200,114 @@ hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units
 }
 
 // First half of K V for every unit (the stiffness without tau, as the quadrature sum of the
-// bilinear form, separably): T12 = V [phi^T | dphi^T]  (M1 x 2Qp), then
-// G = [Gx; Gy] = [dphi T12[:, :Qp]; phi T12[:, Qp:]] o (w w D)  (2Qp x Qp: the x and y
-// derivatives at the Gauss points times w_i w_j D_ij, zero at padding nodes).  The second half,
-// K V = dphi^T Gx phi + phi^T Gy dphi, is fused into the conjugate-gradient step.  V holds the
-// M1 x M1 coefficient matrix of each unit at stride Mp.  Scratch: T12 [units][M1p][2Qp].
+// bilinear form, separably): G = [Gx; Gy] = [dphi (V phi^T); phi (V dphi^T)] o (w w D)
+// (2Qp x Qp: the x and y derivatives at the Gauss points times w_i w_j D_ij, zero at padding
+// nodes).  One work-group per (direction, 64 x 64 tile of G, unit), both products in it:
+// T = V B[:, tile columns] (B = phi^T or dphi^T, from the stacked table b12) into LDS, then
+// G tile = A[tile rows] T (A = dphi or phi), FP64 MFMA 16x16x4 with 16-wide LDS chunks as in
+// k_bgemm.  V holds the M1 x M1 coefficient matrix of each unit at stride Mp (M1 <= 64).  The
+// second half, K V = dphi^T Gx phi + phi^T Gy dphi, is in the conjugate-gradient kernels.
+__global__ __launch_bounds__(256) void k_stiff2d_grid(Tables tb, StepArgs a, const double* V,
+                                                      double* G) {
+  __shared__ double sA[BT][BK + 1];
+  __shared__ double sB[BK][BT + 1];
+  __shared__ double sT[BT][BT + 1];
+  const int u = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int M1 = tb.M1, M1p = tb.M1p, Q = tb.Q, Qp = tb.Qp, nt = (Qp + BT - 1) / BT;
+  const int dir = blockIdx.x / (nt * nt), ib = (blockIdx.x / nt) % nt, jb = blockIdx.x % nt;
+  const int i0 = ib * BT, j0 = jb * BT;
+  const double* Vu = V + (long)u * tb.Mp;
+  const double* Am = dir == 0 ? tb.dphi : tb.phi;
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  // T[k][c] = sum_l V[k][l] B[l][j0 + c]
+  for (int l0 = 0; l0 < M1; l0 += BK) {
+    for (int e = tid; e < BT * BK; e += 256) {
+      const int rr = e / BK, kk = e % BK;
+      sA[rr][kk] = (rr < M1 && l0 + kk < M1) ? Vu[rr * M1 + l0 + kk] : 0.0;
+    }
+    for (int e = tid; e < BK * BT; e += 256) {
+      const int kk = e / BT, cc = e % BT;
+      sB[kk][cc] = (l0 + kk < M1 && j0 + cc < Qp) ? tb.b12[(long)(l0 + kk) * 2 * Qp + dir * Qp + j0 + cc]
+                                                  : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kq = ks * 4 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) af[x] = sA[wi * 32 + x * 16 + (lane & 15)][kq];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bf[y] = sB[kq][wj * 32 + y * 16 + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        sT[wi * 32 + x * 16 + (lane >> 4) + 4 * v][wj * 32 + y * 16 + (lane & 15)] = acc[x][y][v];
+        acc[x][y][v] = 0.0;
+      }
+  __syncthreads();
+  // G tile = A[i0 .., :M1] T
+  for (int k0 = 0; k0 < M1; k0 += BK) {
+    for (int e = tid; e < BT * BK; e += 256) {
+      const int rr = e / BK, kk = e % BK;
+      sA[rr][kk] = (i0 + rr < Qp && k0 + kk < M1) ? Am[(long)(i0 + rr) * M1p + k0 + kk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kq = ks * 4 + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) af[x] = sA[wi * 32 + x * 16 + (lane & 15)][kq];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bf[y] = sT[k0 + kq][wj * 32 + y * 16 + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* Gu = G + ((long)u * 2 + dir) * Qp * Qp;
+  const double* dw = a.d + (long)u * Qp * Qp;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + wi * 32 + x * 16 + (lane >> 4) + 4 * v;
+      if (i >= Qp) continue;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int j = j0 + wj * 32 + y * 16 + (lane & 15);
+        if (j >= Qp) continue;
+        Gu[(long)i * Qp + j] = (i < Q && j < Q) ? acc[x][y][v] * dw[(long)i * Qp + j] : 0.0;
+      }
+    }
+}
+
 hipError_t launch_stiff2d_grid(const Tables& tb, const StepArgs& a, int units, const double* V,
-                               double* T12, double* G, hipStream_t s) {
-  const int M1 = tb.M1, M1p = tb.M1p, Qp = tb.Qp, Mp = tb.Mp;
-  const long sT = (long)M1p * 2 * Qp, sG = 2L * Qp * Qp;
-  hipError_t r = bgemm(BOp{V, M1, Mp, 0}, BOp{tb.b12, 2 * Qp, 0, 0}, T12, 2 * Qp, sT, M1, 2 * Qp,
-                       M1, units, BG_STORE, tb, a, nullptr, s);
-  if (r != hipSuccess) return r;
-  r = bgemm(BOp{tb.dphi, M1p, 0, 0}, BOp{T12, 2 * Qp, sT, 0}, G, Qp, sG, Qp, Qp, M1, units, BG_MULD,
-            tb, a, nullptr, s);
-  if (r != hipSuccess) return r;
-  return bgemm(BOp{tb.phi, M1p, 0, 0}, BOp{T12 + Qp, 2 * Qp, sT, 0}, G + (long)Qp * Qp, Qp, sG, Qp,
-               Qp, M1, units, BG_MULD, tb, a, nullptr, s);
+                               double* G, hipStream_t s) {
+  if (tb.M1 > BT) return hipErrorInvalidValue;
+  const int nt = (tb.Qp + BT - 1) / BT;
+  k_stiff2d_grid<<<dim3(2 * nt * nt, units), 256, 0, s>>>(tb, a, V, G);
+  return hipGetLastError();
 }
 
 hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, const double* mom,

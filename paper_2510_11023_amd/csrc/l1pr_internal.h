@@ -305,13 +305,13 @@ hipError_t launch_tables(const Tables& tb, double* xq, double* wq, double* phi, 
 hipError_t launch_step2d_products(const Tables& tb, const StepArgs& a, int units, double* Cbuf,
                                   double* T, double* mom, hipStream_t s, bool moments = true);
 hipError_t launch_stiff2d_grid(const Tables& tb, const StepArgs& a, int units, const double* V,
-                               double* T12, double* G, hipStream_t s);
+                               double* G, hipStream_t s);
 // preconditioned conjugate gradients for the 2D step systems (cg2d.hip): the start (init) or
-// one iteration, fused with the second half of the stiffness product from G; cgs [units][8],
-// pd [units][Mp] the Jacobi diagonal
+// one iteration, after the second half of the stiffness product from G (per-chunk partials in
+// kvp [units][2Qp/16][256][16]); cgs [units][8], pd [units][Mp] the Jacobi diagonal
 hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const double* G,
-                          const double* x0, double* x, double* r, double* p, double* pd,
-                          double* cgs, int cap, bool init, hipStream_t s);
+                          double* kvp, const double* x0, double* x, double* r, double* p,
+                          double* pd, double* cgs, int cap, bool init, hipStream_t s);
 hipError_t launch_cg_count(const double* cgs, int units, int32_t* out, hipStream_t s);
 hipError_t launch_cg_finish(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
                             const double* x, hipStream_t s);
