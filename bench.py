@@ -387,7 +387,7 @@ def config3_cg(l1, torch, W, dev, Us_direct=None):
         avg = (tot_a / n_a + tot_u / n_u) / 1e3
         fl = P * 2 * (4 * Q * M1 * M1 + 4 * Q * Q * M1)
         out["apply_roofline"] = {"bound": "mfma", "kernel": f"separable stiffness product and CG "
-                                 f"update (3 batched k_bgemm launches + k_cg_step, {P} units)",
+                                 f"update (k_stiff2d_grid, k_cg_part, k_cg_step; {P} units)",
                                  "achieved": round(fl / avg / 1e12, 2), "peak": PEAK_FP64_TFLOPS,
                                  "unit": "TFLOP/s", "frac": round(fl / avg / 1e12 / PEAK_FP64_TFLOPS, 4),
                                  "avg_apply_us": round(avg * 1e6, 1), "flops_per_apply": fl}

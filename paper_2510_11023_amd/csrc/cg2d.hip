@@ -23,16 +23,16 @@ constexpr double CG_TOL2 = 1e-28;
 enum { CG_RZ = 0, CG_BN = 1, CG_ST = 2, CG_IT = 3, CG_NS = 8 };
 constexpr double CG_ACTIVE = 0.0, CG_DONE = 1.0, CG_FAIL = 2.0;
 
+// Sum over the work-group: a butterfly within each wave (both lanes of a pair add the same
+// two values, so every lane ends with the same sum), then the four wave sums in order.
 __device__ inline double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
 #pragma unroll
-  for (int s = CG_T / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double r = red[0];
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < CG_T / 64; ++w) r += red[w];
   __syncthreads();
   return r;
 }
@@ -145,6 +145,7 @@ __global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const d
   for (int xx = 0; xx < 2; ++xx)
 #pragma unroll
     for (int yy = 0; yy < 2; ++yy) acc[xx][yy] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
   for (int c = 0; c < nch; ++c) {
     const double* in = kvp + (((long)u * nch + c) * KV_T + tid) * 16;
 #pragma unroll
