@@ -664,42 +664,58 @@ def main():
 
     useful = len(alphas) * B * M * N
     value = useful / (ms_per_step / 1e3)
-    executed = sum(kstar[a] for a in alphas) * B * M * N
+    # sweep k launches only the slices n >= k (the earlier ones are converged)
+    fine_units = [B * (P - min(k, P - 1)) for a in alphas for k in range(kstar[a])]
+    executed = sum(u * S * M for u in fine_units)
     serial_total = sum(t_serial.values())
-    units = B * P
     total_ms = sum(x[1] for x in stats.values())
     share = {k: round(v[1] / total_ms, 4) for k, v in stats.items()}
 
-    # dominant kernel: the fine-sweep factor-and-solve kernel
+    def fine_launches(kernel):
+        # (units, launches, total ms) of every fine-sweep launch of `kernel`
+        out = []
+        for key, (n, tot) in stats.items():
+            parts = key.split("/")
+            if len(parts) == 3 and parts[0] == kernel and parts[1] == "fine":
+                out.append((int(parts[2]), n, tot))
+        return out
+
+    # dominant kernel: the fine-sweep factor-and-solve kernel, over all its launches
     roofline = None
-    n_c, tot_c = stats.get(f"chol/fine/{units}", (0, 0.0))
-    if n_c:
-        avg_s = tot_c / n_c / 1e3
+    chol = fine_launches("chol")
+    if chol:
         per_unit = M ** 3 / 3 + M ** 2 / 2 + M / 6 + 2 * M ** 2
-        flops = units * per_unit
-        achieved = flops / avg_s / 1e12
+        flops = sum(u * per_unit * n for u, n, _ in chol)
+        tot_s = sum(t for _, _, t in chol) / 1e3
+        n_c = sum(n for _, n, _ in chol)
+        achieved = flops / tot_s / 1e12
         traffic = None
         if TRAFFIC_RECORD and TRAFFIC_RECORD.get("sha256") == sources_hash():
             traffic = TRAFFIC_RECORD["bytes_per_launch"]
-        roofline = {"bound": "mfma", "kernel": f"k_chol_reg<moments> (fine sweep, {units} units)",
+        units = B * P
+        full = [x for x in chol if x[0] == units]
+        roofline = {"bound": "mfma", "kernel": f"k_chol_reg<moments> (fine sweeps, {B * P} units "
+                    f"per full launch; sweep k launches B (P - k))",
                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                    "traffic": traffic, "avg_launch_ms": round(avg_s * 1e3, 4),
-                    "flops_per_launch": int(flops), "launches": n_c}
+                    "traffic": traffic,
+                    "avg_launch_ms": round(tot_s * 1e3 / n_c, 4),
+                    "avg_full_launch_ms": round(full[0][2] / full[0][1], 4) if full else None,
+                    "flops_per_full_launch": int(units * per_unit), "launches": n_c}
 
-    # history sum: algorithmic bytes of one fine sweep (S launches, local step r = 1..S)
+    # history sum: algorithmic bytes of the timed fine sweeps (launch with U units at step r:
+    # rows 0..r-1 of every slot, the instance's slice ends once, the output rows)
     history = None
-    n_h, tot_h = stats.get(f"history/fine/{units}", (0, 0.0))
-    if n_h:
+    hist = fine_launches("history")
+    if hist:
         row = Mp * 8
-        traj_rows = units * sum(range(1, S + 1))          # rows 0..r-1 of every unit
-        ends_rows = S * B * (P + 1)                        # each instance's slice ends, once
-        out_rows = S * units
-        sweep_bytes = (traj_rows + ends_rows + out_rows) * row
-        sweeps = n_h / S
-        gbs = sweep_bytes * sweeps / (tot_h / 1e3) / 1e9
+        sweep_bytes = [(u * sum(range(1, S + 1)) + S * B * (P + 1) + S * u) * row for u in fine_units]
+        tot_bytes = sum(sweep_bytes) * args.steps
+        tot_h = sum(t for _, _, t in hist)
+        n_h = sum(n for _, n, _ in hist)
+        gbs = tot_bytes / (tot_h / 1e3) / 1e9
         history = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_sweep": sweep_bytes,
+                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_full_sweep": sweep_bytes[0],
                    "avg_launch_us": round(tot_h / n_h * 1e3, 2)}
 
     # the same step with the quadrature-GEMM stiffness (assembly = 1)
@@ -711,6 +727,7 @@ def main():
     torch.cuda.synchronize()
     t_gemm = time.perf_counter() - t0
     stats_g = _lib.profile_stop()
+    units = B * P
     n_a, tot_a = stats_g.get(f"assemble/fine/{units}", (0, 0.0))
     gemm = {"ms_per_step": round(t_gemm * 1e3, 1),
             "achieved_rel_err": {str(a): rel_err_max(out_g[a], Us[a]) for a in alphas}}

@@ -513,7 +513,9 @@ l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e, const
 // prev set (full history), the history of slice n also runs over the earlier slices' states
 // in prev (the previous iterate's trajectories); their part of each sum is formed first, for
 // every (slice, step), into hp.
-l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double* prev) {
+// Slices below n_lo are not launched: their trajectory slots keep the previous sweep's values.
+l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double* prev,
+                       int n_lo = 0) {
   const Tables& tb = c.tb;
   const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp;
   const long slotS = (long)(S + 1) * Mp;
@@ -535,12 +537,13 @@ l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double
     L1PR_TRY(timed("prefix", a, B * P, c.s, [&] { return launch_hist_prefix(tb, pa, c.s); }));
   }
   L1PR_TRY(launch_fill_slot0(tb, Z, traj, B, P, c.s));
+  const int nP = P - n_lo;
   for (int r = 1; r <= S; ++r) {
     StepArgs a = base_args(c);
     a.mode = MODE_FINE;
     a.r = r;
-    a.nP = P;
-    a.n_lo = 0;
+    a.nP = nP;
+    a.n_lo = n_lo;
     a.traj = traj;
     a.trajP = P;
     a.trajN0 = 0;
@@ -553,7 +556,7 @@ l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double
     e.out_stride = slotS;
     e.gold = traj + (long)S * Mp;
     e.gold_stride = slotS;
-    l1pr_status st = run_step(c, a, e, B * P);
+    l1pr_status st = run_step(c, a, e, B * nP);
     if (st != L1PR_OK) return st;
   }
   return L1PR_OK;
@@ -605,8 +608,13 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   bool met = false;
   std::vector<double> h_incr(B);
   for (int k = 0; k < max_iter; ++k) {
-    // parallel stage: F_old(n) = F_n(U^k_0..U^k_n) for all (b, n)
-    l1pr_status stf = fine_sweep(c, Zk, traj, prev);
+    // parallel stage: F_old(n) = F_n(U^k_0..U^k_n) for all (b, n).  After k sweeps the slice
+    // ends U^k_0..U^k_k equal those of the previous iterate bit for bit (they are the serial
+    // solution), so for n < k the inputs of F_n are unchanged and its slot still holds F_n
+    // from an earlier sweep: those units are not launched.  (Full history: the fine
+    // propagators also read the previous trajectories, which swap every sweep; no skip.)
+    const int n_lo = prev ? 0 : std::min(k, P - 1);
+    l1pr_status stf = fine_sweep(c, Zk, traj, prev, n_lo);
     if (stf != L1PR_OK) return stf;
     // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n))
     L1PR_TRY(launch_pack(u0, M, B, M, Zk1, Mp, vecP, c.s));

@@ -281,7 +281,8 @@ __device__ inline double full_serial_history(const Tables& tb, const StepArgs& a
 
 // Where the new value x of entry k of unit u goes.  Fine steps: the trajectory row `out` at
 // every step of the unit and, at the instance's last step of the slice (r == Sb), the slice
-// end `gold` as well when it is set.  Other steps: by kind (STORE, STORE2 = also gold,
+// end `gold` as well when it is set (both indexed by the unit's trajectory slot, so a launch
+// may cover a subset of the slices).  Other steps: by kind (STORE, STORE2 = also gold,
 // CORRECT = the parareal update F_old + (x - G_old), then G_old = x).
 __device__ inline void epi_store(const StepArgs& a, const Epilogue& ep, int u, long slot,
                                  bool last_fine, int k, double x) {
@@ -293,7 +294,8 @@ __device__ inline void epi_store(const StepArgs& a, const Epilogue& ep, int u, l
   }
   ep.out[slot * ep.out_stride + k] = x;
   const bool g = (a.mode == MODE_FINE) ? last_fine : (ep.kind == EPI_STORE2);
-  if (g && ep.gold) ep.gold[(long)u * ep.gold_stride + k] = x;
+  const long gi = (a.mode == MODE_FINE) ? slot : (long)u;  // fine steps: by trajectory slot
+  if (g && ep.gold) ep.gold[gi * ep.gold_stride + k] = x;
 }
 
 // ---- launchers (implemented in the .hip files) ----
