@@ -63,14 +63,14 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 TARGET = 1e-8
 
-# HBM traffic of the fine-sweep factor-and-solve kernel, 2048 units per launch, from
+# HBM traffic of the fine-sweep factor-and-solve kernel, per full launch (2048 units), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on `python bench.py --mode kernels`, divided by
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "d2f68d2cfefe0671dd6d1341c6620d7954efefe380e4f2b3cf32b03467a5b814",
-                  "fetch_kib": 8765, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
-                  "bytes_per_launch": (2 * 8765 + 4096) * 1024}
+TRAFFIC_RECORD = {"sha256": "d64451dc99d6f1118d5f3caca84aefab22e4ef5ef6043a4c8c61ed1db7503ff2",
+                  "fetch_kib": 8766, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+                  "bytes_per_launch": (2 * 8766 + 4096) * 1024}
 
 
 def log(msg):
