@@ -638,17 +638,27 @@ def main():
         kstar[a] = max(ks if ks is not None else P, 1)   # exact after P sweeps
         log(f"parareal alpha={a}: k*={kstar[a]} errors " + " ".join(f"{v:.1e}" for v in e[: kstar[a] + 1]))
 
+    # the three alpha groups are independent: each runs on a stream and a workspace of its own,
+    # so that one group's fine launches take the CUs another group's coarse sweeps leave idle
+    streams = [torch.cuda.Stream() for _ in alphas]
+    ws_groups = [ws_par] + [torch.empty_like(ws_par) for _ in alphas[1:]]
+
     def step(pr=probs):
         out = {}
-        for a in alphas:
-            out[a] = l1.solve_parareal(pr[a], u0, kstar[a], tol=0.0, want_incr=False,
-                                       workspace=ws_par).U
+        cur = torch.cuda.current_stream()
+        for a, s_, w in zip(alphas, streams, ws_groups):
+            s_.wait_stream(cur)
+            with torch.cuda.stream(s_):
+                out[a] = l1.solve_parareal(pr[a], u0, kstar[a], tol=0.0, want_incr=False,
+                                           workspace=w).U
+        for s_ in streams:
+            cur.wait_stream(s_)
         return out
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    _lib.profile_start()
+    _lib.profile_start(only=("chol", "history"))  # the roofline kernels only
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = step()
@@ -668,8 +678,8 @@ def main():
     fine_units = [B * (P - min(k, P - 1)) for a in alphas for k in range(kstar[a])]
     executed = sum(u * S * M for u in fine_units)
     serial_total = sum(t_serial.values())
-    total_ms = sum(x[1] for x in stats.values())
-    share = {k: round(v[1] / total_ms, 4) for k, v in stats.items()}
+    # share of the step's wall time in the profiled kernels (summed over the three streams)
+    share = {k: round(v[1] / (ms_per_step * args.steps), 4) for k, v in stats.items()}
 
     def fine_launches(kernel):
         # (units, launches, total ms) of every fine-sweep launch of `kernel`
@@ -702,6 +712,26 @@ def main():
                     "avg_launch_ms": round(tot_s * 1e3 / n_c, 4),
                     "avg_full_launch_ms": round(full[0][2] / full[0][1], 4) if full else None,
                     "flops_per_full_launch": int(units * per_unit), "launches": n_c}
+
+    # the same kernel with the GPU to itself: one alpha group alone, on one stream
+    if roofline is not None:
+        a_iso = alphas[0]
+        l1.solve_parareal(probs[a_iso], u0, kstar[a_iso], tol=0.0, want_incr=False, workspace=ws_par)
+        torch.cuda.synchronize()
+        _lib.profile_start(only=("chol",))
+        l1.solve_parareal(probs[a_iso], u0, kstar[a_iso], tol=0.0, want_incr=False, workspace=ws_par)
+        torch.cuda.synchronize()
+        st_iso = _lib.profile_stop()
+        iso = [(int(k.split("/")[2]), n, t) for k, (n, t) in st_iso.items() if k.startswith("chol/fine/")]
+        fl_iso = sum(u * per_unit * n for u, n, _ in iso)
+        t_iso = sum(t for _, _, t in iso) / 1e3
+        full_iso = [x for x in iso if x[0] == B * P]
+        roofline["isolated"] = {
+            "note": f"one alpha group ({a_iso}) alone on one stream after the timed region; in the "
+                    "timed region the three groups share the CUs, which lengthens each launch",
+            "achieved": round(fl_iso / t_iso / 1e12, 3),
+            "frac": round(fl_iso / t_iso / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "avg_full_launch_ms": round(full_iso[0][2] / full_iso[0][1], 4) if full_iso else None}
 
     # history sum: algorithmic bytes of the timed fine sweeps (launch with U units at step r:
     # rows 0..r-1 of every slot, the instance's slice ends once, the output rows)
@@ -792,7 +822,8 @@ def main():
         "serial_ms": serial_total * 1e3,
         "serial_mode_steps_per_s": useful / serial_total,
         "executed_mode_steps_per_s": executed / (ms_per_step / 1e3),
-        "kernel_time_share": share,
+        "profiled_kernel_time_per_wall_time": share,
+        "schedule": "the three alpha groups on three streams, one workspace each",
         "roofline": roofline,
         "history_hbm": history,
         "gemm_assembly": gemm,

@@ -341,13 +341,18 @@ l1pr_status l1pr_mlp_train_step(int32_t modes, void* params, void* state, const 
                                 size_t ws_bytes, void* stream);
 
 /* Kernel-launch profiling (for benchmarks).  After l1pr_profile_start(), every step kernel
- * that the solvers enqueue is bracketed by two HIP events recorded on its stream.
+ * that the solvers enqueue is bracketed by two HIP events recorded on its stream;
+ * l1pr_profile_start_only(names) brackets only the kernels named in the comma-separated
+ * list (NULL or "" = all), so that a timed run pays for the events of those launches alone.
  * l1pr_profile_stop() turns recording off, waits for the recorded events, and aggregates
- * the elapsed times by "kernel/mode/units" (kernel = eval | assemble | solve, mode =
- * fine | coarse | full, units = systems per launch).  It writes up to max_out entries to
- * `out` (host memory owned by the caller) and returns the number of distinct entries, or
- * -1 on a HIP error.  The events are created on first use and kept by the library for
- * reuse; nothing else is allocated. */
+ * the elapsed times by "kernel/mode/units" (kernel = lag | proj | assemble | history | chol |
+ * eval | blk_solve | products2d | assemble2d | rhs | prefix | cg_grid | cg_step | cg_finish |
+ * mlp, mode = fine | coarse | full, units = systems per launch).  It writes up to max_out
+ * entries to `out` (host memory owned by the caller) and returns the number of distinct
+ * entries, or -1 on a HIP error.  With launches on several streams at once, a launch's time
+ * runs from its stream reaching it to its end, so it includes any wait for CUs held by the
+ * other streams.  The events are created on first use and kept by the library for reuse;
+ * nothing else is allocated. */
 typedef struct {
   char    name[64];
   int64_t launches;
@@ -355,6 +360,7 @@ typedef struct {
 } l1pr_kernel_stat;
 
 void    l1pr_profile_start(void);
+void    l1pr_profile_start_only(const char* names);
 int32_t l1pr_profile_stop(l1pr_kernel_stat* out, int32_t max_out);
 
 /* Static description of a status code. */

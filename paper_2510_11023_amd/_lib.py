@@ -152,6 +152,8 @@ def lib():
         L.l1pr_mlp_train_step.restype = ctypes.c_int
         L.l1pr_profile_start.argtypes = []
         L.l1pr_profile_start.restype = None
+        L.l1pr_profile_start_only.argtypes = [ctypes.c_char_p]
+        L.l1pr_profile_start_only.restype = None
         L.l1pr_profile_stop.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32]
         L.l1pr_profile_stop.restype = ctypes.c_int32
         L.l1pr_status_string.argtypes = [ctypes.c_int]
@@ -164,8 +166,13 @@ def status_string(status: int) -> str:
     return lib().l1pr_status_string(int(status)).decode()
 
 
-def profile_start():
-    lib().l1pr_profile_start()
+def profile_start(only=None):
+    """Bracket every step kernel with HIP events, or only the kernels named in `only` (an
+    iterable of names such as "chol", "history")."""
+    if only:
+        lib().l1pr_profile_start_only(",".join(only).encode())
+    else:
+        lib().l1pr_profile_start()
 
 
 def profile_stop():

@@ -238,6 +238,7 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
 struct Profiler {
   std::mutex mu;
   bool on = false;
+  std::vector<std::string> only;  // kernels to bracket (empty: all)
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec { std::string name; size_t ev; };
@@ -265,6 +266,8 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
   Profiler& p = prof();
   if (!p.on) return launch();
   std::lock_guard<std::mutex> g(p.mu);
+  if (!p.only.empty() && std::find(p.only.begin(), p.only.end(), kernel) == p.only.end())
+    return launch();
   const size_t i0 = p.used;
   hipEvent_t e0 = p.next(), e1 = p.next();
   if (!e0 || !e1) return hipErrorOutOfMemory;
@@ -961,13 +964,22 @@ l1pr_status l1pr_fine_apply(const l1pr_problem* p, int32_t batch, const double* 
   }
 }
 
-void l1pr_profile_start(void) {
+void l1pr_profile_start_only(const char* names) {
   Profiler& p = prof();
   std::lock_guard<std::mutex> g(p.mu);
   p.on = true;
   p.used = 0;
   p.recs.clear();
+  p.only.clear();
+  for (const char* c = names; c && *c;) {
+    const char* e = std::strchr(c, ',');
+    const size_t n = e ? (size_t)(e - c) : std::strlen(c);
+    if (n) p.only.emplace_back(c, n);
+    c = e ? e + 1 : c + n;
+  }
 }
+
+void l1pr_profile_start(void) { l1pr_profile_start_only(nullptr); }
 
 int32_t l1pr_profile_stop(l1pr_kernel_stat* out, int32_t max_out) {
   Profiler& p = prof();
