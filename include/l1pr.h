@@ -118,14 +118,16 @@ typedef struct {
                               fewer points the quadrature stiffness has near-null directions
                               that the preconditioner does not see): K applied as the
                               separable quadrature products (Phi' (x) Phi and Phi (x) Phi' at the
-                              Q x Q Gauss points, w w D between them), preconditioned by the
-                              constant-coefficient operator I + tau Dbar pi^2 (k1^2 + k2^2)
-                              (Dbar = the quadrature mean of D), which is diagonal in the sine
-                              basis; started from the lagged state and stopped when
-                              ||r|| <= 1e-14 ||rhs|| (at most 200 iterations, else
-                              L1PR_ESOLVE).  No M^2 x M^2 matrix is formed.  Each unit
-                              iterates on its own data, so parareal stays exact; the host checks
-                              convergence every 4 iterations (one stream synchronisation). */
+                              Q x Q Gauss points, w w D between them), never formed;
+                              preconditioned by the diagonal of I + tau K (from the cosine
+                              moments; with constant D the sine basis diagonalises K); started
+                              from the lagged state and stopped when ||r|| <= 1e-14 ||rhs||
+                              (coarse steps of parareal: 1e-10; they steer the iteration, the
+                              fine steps fix its result); at most 200 iterations, else
+                              L1PR_ESOLVE.  Each unit iterates on its own data, so parareal
+                              stays exact; the host checks convergence every 4 iterations (one
+                              stream synchronisation), so such a solve cannot be captured in a
+                              graph. */
 } l1pr_problem;
 
 /* Operation codes for l1pr_workspace_bytes. */

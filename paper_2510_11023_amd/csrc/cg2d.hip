@@ -13,13 +13,12 @@
 // iterations; dot products are fixed-order sums (per-lane sums, then a fixed tree), so a unit's
 // iterates depend only on its own data.  Per-unit state in cgs[u][8]: rz = r.z, ||rhs||^2,
 // status, iteration count.  A unit stops (and is left untouched by later launches) once
-// ||r|| <= 1e-14 ||rhs||.
+// ||r|| <= tol ||rhs|| (1e-14 for fine and full-history steps, 1e-10 for coarse steps).
 #include "l1pr_internal.h"
 
 namespace l1pr {
 
 constexpr int CG_T = 256;
-constexpr double CG_TOL2 = 1e-28;
 enum { CG_RZ = 0, CG_BN = 1, CG_ST = 2, CG_IT = 3, CG_NS = 8 };
 constexpr double CG_ACTIVE = 0.0, CG_DONE = 1.0, CG_FAIL = 2.0;
 
@@ -133,7 +132,8 @@ __global__ __launch_bounds__(KV_T) void k_cg_part(Tables tb, const double* G, do
 template <int INIT>
 __global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const double* kvp,
                                                   int nch, const double* x0, double* x, double* r,
-                                                  double* p, double* pd, double* cgs, int cap) {
+                                                  double* p, double* pd, double* cgs, int cap,
+                                                  double tol2) {
   __shared__ double red[KV_T];
   const int u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int M1 = tb.M1, M1p = tb.M1p, Mp = tb.Mp;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const d
     if (tid == 0) {
       cs[CG_RZ] = rz;
       cs[CG_BN] = bn;
-      cs[CG_ST] = (bn == 0.0 || rn <= CG_TOL2 * bn) ? CG_DONE : CG_ACTIVE;
+      cs[CG_ST] = (bn == 0.0 || rn <= tol2 * bn) ? CG_DONE : CG_ACTIVE;
       cs[CG_IT] = 0.0;
     }
     return;
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(KV_T) void k_cg_step(Tables tb, StepArgs a, const d
       }
   rn = block_sum(rn, red);
   rz1 = block_sum(rz1, red);
-  const bool done = rn <= CG_TOL2 * bn;
+  const bool done = rn <= tol2 * bn;
   if (!done) {
     const double be = rz1 / rz;
 #pragma unroll
@@ -307,7 +307,8 @@ __global__ void k_cg_finish(Tables tb, StepArgs a, Epilogue ep, int units, const
 
 hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const double* G,
                           double* kvp, const double* x0, double* x, double* r, double* p,
-                          double* pd, double* cgs, int cap, bool init, hipStream_t s) {
+                          double* pd, double* cgs, int cap, double tol, bool init, hipStream_t s) {
+  const double tol2 = tol * tol;
   if (tb.M1 > 64) return hipErrorInvalidValue;  // the unit's M1 x M1 product is one 64 x 64 tile
   const size_t lds = sizeof(double) * (16 * (tb.Qp + 1) + 16 * 65);
   if (lds > 65536) return hipErrorInvalidValue;  // Qp up to 444
@@ -315,10 +316,10 @@ hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const 
   const dim3 gp(nch, units);
   if (init) {
     k_cg_part<1><<<gp, KV_T, lds, s>>>(tb, G, kvp, cgs);
-    k_cg_step<1><<<units, KV_T, 0, s>>>(tb, a, kvp, nch, x0, x, r, p, pd, cgs, cap);
+    k_cg_step<1><<<units, KV_T, 0, s>>>(tb, a, kvp, nch, x0, x, r, p, pd, cgs, cap, tol2);
   } else {
     k_cg_part<0><<<gp, KV_T, lds, s>>>(tb, G, kvp, cgs);
-    k_cg_step<0><<<units, KV_T, 0, s>>>(tb, a, kvp, nch, x0, x, r, p, pd, cgs, cap);
+    k_cg_step<0><<<units, KV_T, 0, s>>>(tb, a, kvp, nch, x0, x, r, p, pd, cgs, cap, tol2);
   }
   return hipGetLastError();
 }

@@ -32,6 +32,10 @@ constexpr int kMaxModes2D = 64;
 constexpr int kSerialBlock = 64;  // steps per prefix launch of the full-history serial solve
 constexpr int kCgCap = 200;       // conjugate-gradient iterations per step solve, at most
 constexpr int kCgCheck = 4;       // iterations between the host's convergence checks
+// relative residual at which a step solve stops: the fine (and full-history) steps define
+// the solution; a coarse step only steers parareal's convergence, its fixed point being that
+// of the fine propagator, and it is deterministic at any tolerance, so exactness holds
+constexpr double kCgTolFine = 1e-14, kCgTolCoarse = 1e-10;
 
 struct Layout {
   size_t total = 0;
@@ -306,6 +310,7 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
     double* kv = c.ptr(c.L.cgkv);
     double* cgs = c.ptr(c.L.cgs);
     int32_t* cnt = reinterpret_cast<int32_t*>(c.ws + c.L.cgcnt);
+    const double cg_tol = a.mode == MODE_COARSE ? kCgTolCoarse : kCgTolFine;
     auto grid = [&](const double* v) {
       return timed("cg_grid", a, units, c.s, [&] {
         return launch_stiff2d_grid(c.tb, a, units, v, G, c.s);
@@ -313,14 +318,15 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
     };
     L1PR_TRY(grid(a.C2));
     L1PR_TRY(timed("cg_step", a, units, c.s, [&] {
-      return launch_cg_step(c.tb, a, units, G, kv, a.C2, x, r, p, pd, cgs, kCgCap, true, c.s);
+      return launch_cg_step(c.tb, a, units, G, kv, a.C2, x, r, p, pd, cgs, kCgCap, cg_tol, true, c.s);
     }));
     bool done = false;
     for (int it = 0; it < kCgCap && !done; it += kCgCheck) {
       for (int j = 0; j < kCgCheck; ++j) {
         L1PR_TRY(grid(p));
         L1PR_TRY(timed("cg_step", a, units, c.s, [&] {
-          return launch_cg_step(c.tb, a, units, G, kv, nullptr, x, r, p, pd, cgs, kCgCap, false, c.s);
+          return launch_cg_step(c.tb, a, units, G, kv, nullptr, x, r, p, pd, cgs, kCgCap, cg_tol, false,
+                                c.s);
         }));
       }
       int32_t h[2] = {0, 0};

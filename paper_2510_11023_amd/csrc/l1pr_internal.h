@@ -313,7 +313,7 @@ hipError_t launch_stiff2d_grid(const Tables& tb, const StepArgs& a, int units, c
 // kvp [units][2Qp/16][256][16]); cgs [units][8], pd [units][Mp] the Jacobi diagonal
 hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const double* G,
                           double* kvp, const double* x0, double* x, double* r, double* p,
-                          double* pd, double* cgs, int cap, bool init, hipStream_t s);
+                          double* pd, double* cgs, int cap, double tol, bool init, hipStream_t s);
 hipError_t launch_cg_count(const double* cgs, int units, int32_t* out, hipStream_t s);
 hipError_t launch_cg_finish(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
                             const double* x, hipStream_t s);
