@@ -85,3 +85,16 @@ def test_product_path_has_no_cpu_fallback():
             assert "import oracle" not in txt and "from oracle" not in txt, fn
     txt = open(os.path.join(pkg, "_lib.py")).read()
     assert "raise ImportError" in txt
+
+
+def test_profiler_start_stop_without_launches(L):
+    """Profiling with and without a kernel filter records nothing until a solver runs (host
+    only: no event is created or read)."""
+    from paper_2510_11023_amd import _lib
+
+    for names in (None, "chol,history", ",,chol,", ""):
+        if names is None:
+            L.l1pr_profile_start()
+        else:
+            L.l1pr_profile_start_only(names.encode())
+        assert _lib.profile_stop() == {}
