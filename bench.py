@@ -718,7 +718,7 @@ def main():
         a_iso = alphas[0]
         l1.solve_parareal(probs[a_iso], u0, kstar[a_iso], tol=0.0, want_incr=False, workspace=ws_par)
         torch.cuda.synchronize()
-        _lib.profile_start(only=("chol",))
+        _lib.profile_start(only=("chol", "history"))
         l1.solve_parareal(probs[a_iso], u0, kstar[a_iso], tol=0.0, want_incr=False, workspace=ws_par)
         torch.cuda.synchronize()
         st_iso = _lib.profile_stop()
@@ -747,6 +747,16 @@ def main():
         history = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                    "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_full_sweep": sweep_bytes[0],
                    "avg_launch_us": round(tot_h / n_h * 1e3, 2)}
+        if roofline is not None:  # the isolated pass above (one alpha group alone)
+            hist_iso = [(n, t) for k, (n, t) in st_iso.items() if k.startswith("history/fine/")]
+            if hist_iso:
+                a_iso = alphas[0]
+                units_iso = [B * (P - min(k, P - 1)) for k in range(kstar[a_iso])]
+                b_iso = sum((u * sum(range(1, S + 1)) + S * B * (P + 1) + S * u) * row for u in units_iso)
+                t_h = sum(t for _, t in hist_iso) / 1e3
+                history["isolated"] = {"achieved": round(b_iso / t_h / 1e9, 1),
+                                       "frac": round(b_iso / t_h / 1e9 / PEAK_HBM_GBS, 4),
+                                       "avg_launch_us": round(t_h * 1e6 / sum(n for n, _ in hist_iso), 2)}
 
     # the same step with the quadrature-GEMM stiffness (assembly = 1)
     step(probs_gemm)
