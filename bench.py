@@ -68,7 +68,7 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "d64451dc99d6f1118d5f3caca84aefab22e4ef5ef6043a4c8c61ed1db7503ff2",
+TRAFFIC_RECORD = {"sha256": "812facc5907e3440ce71f504617c88673d8c1679461f5668a014f5a43ce2fc87",
                   "fetch_kib": 8766, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": (2 * 8766 + 4096) * 1024}
 
