@@ -262,3 +262,28 @@ def test_full_size_parareal_prefix_exact(gpu, c2_full):
     # the iterates approach the serial solution
     errs = [rel(its[k], U) for k in range(4)]
     assert errs[3] < errs[0]
+
+
+def test_full_size_concurrent_groups_equal_sequential(gpu):
+    """The benchmark's schedule: independent alpha groups at the full config-2 size, each on a
+    stream and a workspace of its own, give exactly the results they give one after another."""
+    B, alphas, k = 32, (0.3, 1.0), 3
+    u0 = dev(W.u0_batch_1d(256, range(B)))
+    probs = {a: gpu.make_problem(**W.with_(W.C2, alpha=a)) for a in alphas}
+    ws = [torch.empty(gpu.workspace_bytes(probs[a], B, 1), dtype=torch.uint8, device="cuda")
+          for a in alphas]
+    seq = {a: gpu.solve_parareal(probs[a], u0, k, tol=0.0, want_incr=False, workspace=ws[0]).U
+           for a in alphas}
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in alphas]
+    cur = torch.cuda.current_stream()
+    conc = {}
+    for a, s, w in zip(alphas, streams, ws):
+        s.wait_stream(cur)
+        with torch.cuda.stream(s):
+            conc[a] = gpu.solve_parareal(probs[a], u0, k, tol=0.0, want_incr=False, workspace=w).U
+    for s in streams:
+        cur.wait_stream(s)
+    torch.cuda.synchronize()
+    for a in alphas:
+        assert torch.equal(conc[a], seq[a]), a
