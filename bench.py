@@ -758,6 +758,23 @@ def main():
                                        "frac": round(b_iso / t_h / 1e9 / PEAK_HBM_GBS, 4),
                                        "avg_launch_us": round(t_h * 1e6 / sum(n for n, _ in hist_iso), 2)}
 
+    # whole-step roofline: each phase at its own bound, summed (step solves at the FP64 MFMA
+    # peak, history sums at the HBM bandwidth), over the measured step time.  Work per
+    # unit-step: lagged state 2QM, moments 2Q(2M+1), load 2QM, factor and solves.
+    unit_step = 2 * Q * M + 2 * Q * (2 * M + 1) + 2 * Q * M + (M ** 3 / 3 + M ** 2 / 2 + M / 6 + 2 * M ** 2)
+    fine_unit_steps = sum(u * S for u in fine_units)
+    coarse_unit_steps = sum((kstar[a] + 1) * P * B for a in alphas)
+    solve_ms = (fine_unit_steps + coarse_unit_steps) * unit_step / (PEAK_FP64_TFLOPS * 1e12) * 1e3
+    row = Mp * 8
+    hist_bytes = sum((u * sum(range(1, S + 1)) + S * B * (P + 1) + S * u) * row for u in fine_units)
+    hist_bytes += sum((kstar[a] + 1) * B * sum(range(1, P + 1)) * row for a in alphas)  # coarse
+    hist_ms = hist_bytes / (PEAK_HBM_GBS * 1e9) * 1e3
+    whole = {"solves_ms": round(solve_ms, 2), "history_ms": round(hist_ms, 2),
+             "roofline_ms": round(solve_ms + hist_ms, 2), "measured_ms": round(ms_per_step, 1),
+             "frac": round((solve_ms + hist_ms) / ms_per_step, 4),
+             "flops_per_unit_step": int(unit_step),
+             "unit_steps": {"fine": fine_unit_steps, "coarse": coarse_unit_steps}}
+
     # the same step with the quadrature-GEMM stiffness (assembly = 1)
     step(probs_gemm)
     torch.cuda.synchronize()
@@ -836,6 +853,7 @@ def main():
         "schedule": "the three alpha groups on three streams, one workspace each",
         "roofline": roofline,
         "history_hbm": history,
+        "whole_step_roofline": whole,
         "gemm_assembly": gemm,
         "learned_vs_plain": learned,
         "uneven_batch": uneven,
