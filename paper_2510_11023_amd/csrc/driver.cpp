@@ -625,9 +625,16 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
     const int n_lo = prev ? 0 : std::min(k, P - 1);
     l1pr_status stf = fine_sweep(c, Zk, traj, prev, n_lo);
     if (stf != L1PR_OK) return stf;
-    // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n))
+    // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n)).
+    // For n <= k the inputs of G_n are the converged slice ends, the same as when G_old(n) was
+    // formed, so the bracket is exactly zero: those rows are F_old(n), copied, and G_old(n)
+    // stays.
     L1PR_TRY(launch_pack(u0, M, B, M, Zk1, Mp, vecP, c.s));
-    for (int n = 0; n < P; ++n) {
+    const int n_conv = std::min(k + 1, P);
+    for (int n = 0; n < n_conv; ++n)
+      L1PR_TRY(launch_copy_rows(traj + ((long)n * (S + 1) + S) * Mp, (long)P * slotS,
+                                Zk1 + (long)(n + 1) * Mp, vecP, 1, Mp, B, c.s));
+    for (int n = n_conv; n < P; ++n) {
       Epilogue e{};
       e.kind = EPI_CORRECT;
       e.out = Zk1 + (long)(n + 1) * Mp;
