@@ -41,6 +41,7 @@ class Problem(ctypes.Structure):
         ("f_sel", ctypes.c_int32),
         ("history", ctypes.c_int32),
         ("source_time", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
     ]
 
 
@@ -77,9 +78,9 @@ def lib():
 
 
 def problem(dim=1, modes=8, quad=16, steps=16, slices=4, alpha=0.5, T=1.0, d_sel=0,
-            d_param=1.0, f_sel=0, history=0, source_time=0) -> Problem:
+            d_param=1.0, f_sel=0, history=0, source_time=0, solver=0) -> Problem:
     return Problem(dim, modes, quad, steps, slices, alpha, T, d_sel, d_param, f_sel, history,
-                   source_time)
+                   source_time, solver)
 
 
 def nmodes(p: Problem) -> int:

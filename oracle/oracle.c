@@ -49,6 +49,8 @@ int oracle_validate(const oracle_problem* p) {
   if (p->history != 0 && p->history != 1) return -1;
   if (p->source_time != 0 && p->source_time != 1) return -1;
   if (p->source_time == 1 && !f_is_u_independent(p->f_sel)) return -1;
+  if (p->solver < 0 || p->solver > 2) return -1;
+  if (p->solver == 2 && p->d_sel != 0) return -1;
   return 0;
 }
 
@@ -346,9 +348,22 @@ static int solve_dense(int n, double* A, double* b) {
   return 0;
 }
 
+/* Eigenvalue of -Laplace for basis function k (Dirichlet sine basis): (k pi)^2 in 1D,
+   (k1^2 + k2^2) pi^2 in 2D for k = (k1-1) M + (k2-1). */
+static double sine_eigenvalue(const oracle_problem* p, int k) {
+  const double pi = ORACLE_PI;
+  if (p->dim == 1) return (double)(k + 1) * (double)(k + 1) * pi * pi;
+  double k1 = (double)(k / p->modes + 1), k2 = (double)(k % p->modes + 1);
+  return (k1 * k1 + k2 * k2) * pi * pi;
+}
+
 /* One semi-implicit L1-Galerkin step (Section 2.1 and Section 2.2): the diffusion
    coefficient and the source are taken at the previous level (c_prev), the gradient
-   term at the new level:  (I + tau K) c = hist + tau F. */
+   term at the new level:  (I + tau K) c = hist + tau F.
+   solver = 2 (constant D, the spectral diagonalisation named among the paper's outlook
+   items in its conclusions): a(phi_k, phi_l) = D (grad phi_k, grad phi_l) = D lambda_k
+   delta_kl exactly for the orthonormal sine basis, so c_k = (hist_k + tau F_k) /
+   (1 + tau D lambda_k); the load F is still the quadrature sum. */
 int oracle_step(const oracle_problem* p, const double* c_prev, double tD, double tf,
                 const double* hist, double tau, double* c_out) {
   if (oracle_validate(p)) return -1;
@@ -356,6 +371,12 @@ int oracle_step(const oracle_problem* p, const double* c_prev, double tD, double
   double* K = (double*)malloc(sizeof(double) * (size_t)Md * Md);
   double* F = (double*)malloc(sizeof(double) * Md);
   oracle_galerkin(p, c_prev, tD, tf, K, F);
+  if (p->solver == 2) {
+    for (int k = 0; k < Md; k++)
+      c_out[k] = (hist[k] + tau * F[k]) / (1.0 + tau * p->d_param * sine_eigenvalue(p, k));
+    free(K); free(F);
+    return 0;
+  }
   for (int k = 0; k < Md; k++) {
     for (int l = 0; l < Md; l++) K[(size_t)k * Md + l] *= tau;
     K[(size_t)k * Md + k] += 1.0;

@@ -43,6 +43,9 @@ typedef struct {
   int32_t f_sel;        /* source selector */
   int32_t history;      /* 0 hybrid (coarse history in F), 1 full uniform fine L1 */
   int32_t source_time;  /* 0 lagged source (the paper), 1 source at the new time level */
+  int32_t solver;       /* 0 (or 1): stiffness by Gauss quadrature, dense solve;
+                           2: constant D only, stiffness integral taken exactly,
+                           D lambda_k on the diagonal (the sine basis diagonalises it) */
 } oracle_problem;
 
 /* 0 on success, -1 if the problem is invalid. */

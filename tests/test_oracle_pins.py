@@ -601,3 +601,54 @@ def test_2d_stiffness_equals_separable_quadrature_products():
         Kv = dphi.T @ (Dw * (dphi @ V @ phi.T)) @ phi + phi.T @ (Dw * (phi @ V @ dphi.T)) @ dphi
         ref = (K @ V.reshape(-1)).reshape(M, M)
         assert np.linalg.norm(Kv - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------- constant-D spectral diagonal solve
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_diagonal_solver_backward_euler_every_mode(orc, dim):
+    """solver = 2 (constant D, stiffness integral taken exactly): at alpha = 1 with f = 0 each
+    sine mode decays on its own as c_k(0) (1 + dt D lambda_k)^(-m), lambda_k the Dirichlet
+    eigenvalue (k pi)^2 in 1D, (k1^2 + k2^2) pi^2 in 2D.  Q = M: there the quadrature
+    stiffness is far from diagonal, so a result that went through it would fail."""
+    M = 5 if dim == 1 else 4
+    D = 0.3
+    p = orc.problem(dim=dim, modes=M, quad=M, steps=12, slices=3, alpha=1.0, d_sel=0,
+                    d_param=D, history=1, solver=2)
+    Md = orc.nmodes(p)
+    u0 = np.random.default_rng(11).standard_normal(Md)
+    U, traj = orc.solve_serial(p, u0, want_traj=True)
+    if dim == 1:
+        lam = (np.arange(1, M + 1) * math.pi) ** 2
+    else:
+        k1, k2 = np.meshgrid(np.arange(1, M + 1), np.arange(1, M + 1), indexing="ij")
+        lam = ((k1 ** 2 + k2 ** 2) * math.pi ** 2).ravel()
+    dt = 1.0 / 12
+    ref = u0[None, :] * (1.0 + dt * D * lam[None, :]) ** (-np.arange(13)[:, None])
+    assert np.max(np.abs(traj - ref) / np.abs(ref)) < 1e-13
+
+
+@pytest.mark.parametrize("dim,M,Q", [(1, 8, 48), (2, 5, 24)])
+@pytest.mark.parametrize("history", [0, 1])
+def test_diagonal_solver_equals_dense_quadrature_solve(orc, dim, M, Q, history):
+    """With Q well above M the Gauss rule integrates the products of basis gradients exactly
+    to rounding, so the dense quadrature-stiffness solve (Gaussian elimination) and the
+    diagonal solve of solver = 2 give the same trajectory; alpha < 1 and a state-dependent
+    source exercise the L1 history and the load."""
+    kw = dict(dim=dim, modes=M, quad=Q, steps=12, slices=3, alpha=0.6, d_sel=0, d_param=0.9,
+              f_sel=2, history=history)
+    Md = M if dim == 1 else M * M
+    u0 = np.random.default_rng(5).standard_normal(Md) / np.arange(1, Md + 1)
+    Ud = orc.solve_serial(orc.problem(solver=2, **kw), u0)
+    Uq = orc.solve_serial(orc.problem(**kw), u0)
+    assert np.linalg.norm(Ud - Uq) <= 1e-12 * np.linalg.norm(Uq)
+    # and the difference is not trivially zero at a coarse rule, where the two discretise
+    # the stiffness differently
+    Uc = orc.solve_serial(orc.problem(solver=2, **dict(kw, quad=M)), u0)
+    Uqc = orc.solve_serial(orc.problem(**dict(kw, quad=M)), u0)
+    assert np.linalg.norm(Uc - Uqc) > 1e-6 * np.linalg.norm(Uqc)
+
+
+def test_diagonal_solver_rejects_variable_d(orc):
+    assert orc.lib().oracle_validate(orc.problem(d_sel=1, solver=2)) == -1
+    assert orc.lib().oracle_validate(orc.problem(d_sel=0, solver=2)) == 0
