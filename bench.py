@@ -68,7 +68,7 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "812facc5907e3440ce71f504617c88673d8c1679461f5668a014f5a43ce2fc87",
+TRAFFIC_RECORD = {"sha256": "804cc2ec7373b11fd3515a4e39c2292171c0bbe4669f5b7ee861896fe5f45d0f",
                   "fetch_kib": 8766, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": (2 * 8766 + 4096) * 1024}
 
@@ -478,6 +478,86 @@ def full_history(l1, torch, W, dev, alpha=0.3):
     return out
 
 
+def constant_d(l1, torch, W, dev, alpha=0.3):
+    """Constant D on the config-2 batch (D = 1, the other settings as config 2): the diagonal
+    step solve (solver = 2) against the Cholesky path on the quadrature stiffness, serial and
+    parareal wall time, the diagonal kernel against the HBM peak; and one 2D fine sweep at the
+    config-3 shape with constant D by both solvers."""
+    from paper_2510_11023_amd import _lib
+
+    kw = W.with_(W.C2, alpha=alpha, d_sel=0, d_param=1.0)
+    M, N, P = kw["modes"], kw["steps"], kw["slices"]
+    S, B = N // P, W.C2_BATCH
+    u0 = torch.tensor(W.u0_batch_1d(M, range(B)), dtype=torch.float64, device=dev)
+    out = {"workload": f"1D, M={M}, Q={kw['quad']}, N={N}, P={P}, alpha={alpha}, {B} instances "
+                       f"(seeds 0..{B - 1}), D = 1, config-2 f"}
+    res = {}
+    for solver in (2, 0):
+        p = l1.make_problem(solver=solver, **kw)
+        ws = torch.empty(l1.workspace_bytes(p, B, 1), dtype=torch.uint8, device=dev)
+        ws_s = torch.empty(l1.workspace_bytes(p, B, 0), dtype=torch.uint8, device=dev)
+        l1.solve_serial(p, u0, workspace=ws_s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Us, _ = l1.solve_serial(p, u0, workspace=ws_s)
+        torch.cuda.synchronize()
+        t_ser = time.perf_counter() - t0
+        del ws_s
+        ks, e = find_kstar(l1, p, u0, Us, ws, 24)
+        k = ks if ks is not None else P
+        l1.solve_parareal(p, u0, k, tol=0.0, want_incr=False, workspace=ws)
+        torch.cuda.synchronize()
+        _lib.profile_start(only=("diag", "chol"))
+        t0 = time.perf_counter()
+        U = l1.solve_parareal(p, u0, k, tol=0.0, want_incr=False, workspace=ws).U
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        st = _lib.profile_stop()
+        r = {"serial_ms": round(t_ser * 1e3, 1), "serial_mode_steps_per_s": B * M * N / t_ser,
+             "kstar": ks, "parareal_ms": round(tp * 1e3, 1), "mode_steps_per_s": B * M * N / tp,
+             "achieved_rel_err": rel_err_max(U, Us), "speedup_over_serial": round(t_ser / tp, 2)}
+        n_d, tot_d = st.get(f"diag/fine/{B * P}", (0, 0.0))
+        if n_d:
+            avg = tot_d / n_d / 1e3
+            nbytes = B * P * M * 24  # rhs and F read, the new state written
+            ach = nbytes / avg / 1e9
+            r["diag_roofline"] = {
+                "bound": "hbm", "kernel": f"k_diag_solve ({B * P} units, fine steps)",
+                "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "avg_launch_us": round(avg * 1e6, 2),
+                "bytes_per_launch": nbytes, "launches": n_d}
+        res[solver] = (r, Us)
+        del ws
+    out["solver2_diagonal"] = res[2][0]
+    out["solver0_cholesky"] = res[0][0]
+    out["serial_speedup_diag_over_cholesky"] = round(res[0][0]["serial_ms"] / res[2][0]["serial_ms"], 2)
+    # the two discretise the stiffness differently (exact integral against Q = 1.5 M Gauss points)
+    out["rel_diff_vs_quadrature_stiffness"] = rel_err_max(res[2][1], res[0][1])
+    kw2 = W.with_(W.C3, d_sel=0, d_param=1.0)
+    u2 = torch.tensor(W.u0_random_2d(kw2["modes"], 0)[None], device=dev)
+    two = {}
+    for solver in (2, 0):
+        p2 = l1.make_problem(solver=solver, **kw2)
+        ws2 = l1.parareal_workspace(p2, 1, dev)
+        Z2 = l1.solve_parareal(p2, u2, 0, tol=0.0, want_iterates=True, workspace=ws2).iterates[0]
+        Z2 = Z2.contiguous()
+        l1.fine_apply(p2, Z2, workspace=ws2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        l1.fine_apply(p2, Z2, workspace=ws2)
+        torch.cuda.synchronize()
+        two[solver] = (time.perf_counter() - t0) * 1e3
+        del ws2
+    out["2d_fine_sweep_ms"] = {"workload": f"2D, M={kw2['modes']}x{kw2['modes']}, Q={kw2['quad']}, "
+                                           f"{kw2['slices']} slices of {kw2['steps'] // kw2['slices']} "
+                                           f"steps, D = 1, config-3 f",
+                               "solver2_diagonal": round(two[2], 2), "solver0_cholesky": round(two[0], 2)}
+    log(f"constant D: serial {res[2][0]['serial_ms']:.0f} ms (diag) vs {res[0][0]['serial_ms']:.0f} ms "
+        f"(Cholesky); parareal {res[2][0]['parareal_ms']:.0f} vs {res[0][0]['parareal_ms']:.0f} ms; "
+        f"2D fine sweep {two[2]:.1f} vs {two[0]:.1f} ms")
+    return out
+
+
 def paper_model(l1, torch, W, dev, sizes=((8, 8), (16, 16), (32, 32), (64, 64), (128, 128),
                                                (128, 256))):
     """The paper's model problem on the sine path (qualitative re-runs of its two figures):
@@ -537,8 +617,9 @@ def main():
     ap.add_argument("--no-2d", action="store_true")
     ap.add_argument("--no-full-history", action="store_true")
     ap.add_argument("--no-paper-model", action="store_true")
+    ap.add_argument("--no-constant-d", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernels", "kernels2d", "kernelsfh", "fullhistory",
-                                       "cg2d"],
+                                       "cg2d", "constd"],
                     default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
                          "device copy (for hardware-counter runs); kernels2d: one fine sweep of "
@@ -546,6 +627,7 @@ def main():
                          "full-history parareal sweep of the alpha=0.3 batch and the same copy; "
                          "none of these prints a JSON line; fullhistory: only the full-history "
                          "parareal section (its JSON); cg2d: only the config-3 conjugate-gradient "
+                         "section (its JSON); constd: only the constant-D diagonal-solve "
                          "section (its JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -602,6 +684,10 @@ def main():
 
     if args.mode == "cg2d":
         print(json.dumps(config3_cg(l1, torch, W, dev)), flush=True)
+        return
+
+    if args.mode == "constd":
+        print(json.dumps(constant_d(l1, torch, W, dev)), flush=True)
         return
 
     if args.mode == "fullhistory":
@@ -810,6 +896,10 @@ def main():
     if not args.no_paper_model:
         paper = paper_model(l1, torch, W, dev)
 
+    constd = None
+    if not args.no_constant_d:
+        constd = constant_d(l1, torch, W, dev)
+
     fullh = None
     if not args.no_full_history:
         fullh = full_history(l1, torch, W, dev)
@@ -859,6 +949,7 @@ def main():
         "uneven_batch": uneven,
         "config3_2d": two_d,
         "full_history": fullh,
+        "constant_d": constd,
         "paper_model": paper,
         "cpu_baseline": cpu,
     }

@@ -127,7 +127,17 @@ typedef struct {
                               L1PR_ESOLVE.  Each unit iterates on its own data, so parareal
                               stays exact; the host checks convergence every 4 iterations (one
                               stream synchronisation), so such a solve cannot be captured in a
-                              graph. */
+                              graph;
+                           2: constant D only (d_sel = L1PR_D_CONST, assembly = 0), 1D or 2D:
+                              the stiffness integral taken exactly, D (grad phi_k, grad phi_l) =
+                              D lambda_k delta_kl for the orthonormal sine basis (lambda_k =
+                              (k pi)^2, or (k1^2 + k2^2) pi^2 in 2D), so a step is the O(M)
+                              division c_k = (hist_k + tau F_k) / (1 + tau D lambda_k); the load
+                              F stays the quadrature sum.  Equal to solver 0 up to the
+                              quadrature error of the stiffness (rounding level once Q is
+                              about 2M in 1D, 3M in 2D); the spectral diagonalisation among the
+                              outlook items of the paper's conclusions.  Not for uneven
+                              batches. */
 } l1pr_problem;
 
 /* Operation codes for l1pr_workspace_bytes. */

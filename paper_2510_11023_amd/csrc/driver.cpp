@@ -75,8 +75,11 @@ bool valid(const l1pr_problem* p) {
   if (p->assembly != 0 && p->assembly != 1) return false;
   if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY | TUNE_NB128 | TUNE_TRAIL64))
     return false;
-  if (p->solver != 0 && p->solver != 1) return false;
+  if (p->solver < 0 || p->solver > 2) return false;
   if (p->solver == 1 && p->dim != 2) return false;  // the iterative solve is the 2D one
+  // the diagonal solve needs the sine basis to diagonalise the stiffness: constant D, whose
+  // stiffness it takes exactly (assembly does not apply)
+  if (p->solver == 2 && (p->d_sel != L1PR_D_CONST || p->assembly != 0)) return false;
   // with fewer Gauss points the quadrature stiffness aliases into near-null directions that
   // the constant-coefficient preconditioner does not see
   if (p->solver == 1 && 2 * p->quad < 3 * p->modes) return false;
@@ -140,8 +143,8 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   const size_t nq = two ? Qp * Qp : Qp;  // quadrature points per unit
   L.d = take(cur, D * units * nq);
   L.rhs = take(cur, D * units * Mp);
-  const bool pcg = p->solver == 1;
-  L.A = pcg ? 0 : take(cur, D * units * Mp * Mp);
+  const bool pcg = p->solver == 1, diag = p->solver == 2;
+  L.A = (pcg || diag) ? 0 : take(cur, D * units * Mp * Mp);
   L.g = take(cur, D * units * nq);
   L.mom = take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
   L.F = take(cur, D * units * Mp);
@@ -149,7 +152,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
   // back-substitution partial sums of the device-memory factorisation
   const size_t nblk = (Mp + tb.nb - 1) / tb.nb;
-  L.q = (pcg || reg_path_ok(tb.Mp, tb.Qp)) ? 0 : take(cur, D * units * nblk * tb.nb);
+  L.q = (pcg || diag || reg_path_ok(tb.Mp, tb.Qp)) ? 0 : take(cur, D * units * nblk * tb.nb);
   if (two) {
     L.b12 = take(cur, D * M1p * 2 * Qp);
     L.s2 = take(cur, D * 2 * Qp * M1p);
@@ -175,6 +178,7 @@ struct Ctx {
   bool moments;  // stiffness from cosine moments, inside that kernel
   bool full;     // parareal with full-history fine propagators
   bool pcg;      // 2D step systems by preconditioned conjugate gradients
+  bool diag;     // constant D: the diagonal solve in the sine basis
   char* ws;
   hipStream_t s;
   double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -219,8 +223,9 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.b12 = c.L.b12 ? c.ptr(c.L.b12) : nullptr;
   tb.s2 = c.L.s2 ? c.ptr(c.L.s2) : nullptr;
   c.pcg = p->solver == 1;
+  c.diag = p->solver == 2;
   c.reg = reg_path_ok(tb.Mp, tb.Qp);
-  c.moments = c.reg && p->assembly == 0 && p->dim == 1;
+  c.moments = c.reg && p->assembly == 0 && p->dim == 1 && !c.diag;
   c.full = op == L1PR_OP_PARAREAL && p->history == 1;
   const double* alpha_dev = c.ptr(c.L.alpha);
   if (un.alpha)  // device array of the caller (nothing is copied, so the call can be captured)
@@ -292,6 +297,31 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 // Mp > 256: evaluation (1D) or the separable products (2D), the assembly, and the blocked
 //   factorisation through device memory.
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
+  if (c.diag) {
+    // constant D: the load vector at the lagged state (separable products in 2D, the two
+    // GEMMs in 1D, or the evaluation kernel, which also forms hist + tau F, for more than 256
+    // coefficients), the history sums, then the diagonal solve
+    if (c.tb.dim == 2) {
+      L1PR_TRY(timed("products2d", a, units, c.s, [&] {
+        return launch_step2d_products(c.tb, a, units, a.C2, a.T2, a.mom, c.s, false);
+      }));
+    } else if (c.reg) {
+      const bool coarse = a.mode == MODE_COARSE;
+      const bool sk_lag = coarse || !(c.tb.tune & TUNE_LAG_TILED);
+      const bool sk_proj = coarse || (c.tb.tune & TUNE_PROJ_SKINNY);
+      L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, sk_lag, c.s); }));
+      L1PR_TRY(timed("proj", a, units, c.s, [&] {
+        return launch_proj_gemm(c.tb, units, a.d, a.g, nullptr, a.F, sk_proj, c.s);
+      }));
+    } else {
+      L1PR_TRY(timed("eval", a, units, c.s, [&] { return launch_eval(c.tb, a, units, c.s); }));
+      L1PR_TRY(timed("diag", a, units, c.s, [&] { return launch_diag_solve(c.tb, a, e, units, nullptr, c.s); }));
+      return L1PR_OK;
+    }
+    L1PR_TRY(timed("history", a, units, c.s, [&] { return launch_history(c.tb, a, units, a.rhs, c.s); }));
+    L1PR_TRY(timed("diag", a, units, c.s, [&] { return launch_diag_solve(c.tb, a, e, units, a.F, c.s); }));
+    return L1PR_OK;
+  }
   if (c.tb.dim == 2 && c.pcg) {
     // separable products (lagged state, D, f, load vector, cosine moments for the Jacobi
     // diagonal), the history sums and the right-hand side, then conjugate gradients from the
@@ -393,7 +423,7 @@ StepArgs base_args(const Ctx& c) {
   std::memset(&a, 0, sizeof(a));
   a.d = c.ptr(c.L.d);
   a.rhs = c.ptr(c.L.rhs);
-  a.A = c.pcg ? nullptr : c.ptr(c.L.A);
+  a.A = (c.pcg || c.diag) ? nullptr : c.ptr(c.L.A);
   a.g = c.ptr(c.L.g);
   a.mom = c.ptr(c.L.mom);
   a.F = c.ptr(c.L.F);
@@ -758,7 +788,8 @@ l1pr_status l1pr_solve_serial_uneven(const l1pr_problem* p, int32_t batch,
                                      const l1pr_uneven* desc, const double* u0, double* U,
                                      void* ws, size_t ws_bytes, void* stream) {
   try {
-    if (!p || !desc || !u0 || !U || p->history != 0 || p->dim != 1) return L1PR_EINVAL;
+    if (!p || !desc || !u0 || !U || p->history != 0 || p->dim != 1 || p->solver != 0)
+      return L1PR_EINVAL;
     Uneven un;
     un.alpha = desc->alpha;
     un.modes = desc->modes;
@@ -779,7 +810,8 @@ l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
                                        int64_t* stamps, double* incr, void* ws, size_t ws_bytes,
                                        void* stream) {
   try {
-    if (!p || !desc || !u0 || !U || p->history != 0 || p->dim != 1) return L1PR_EINVAL;
+    if (!p || !desc || !u0 || !U || p->history != 0 || p->dim != 1 || p->solver != 0)
+      return L1PR_EINVAL;
     if (sweeps < 0 || sweeps > p->slices || !(conv_tol >= 0.0)) return L1PR_EINVAL;
     Uneven un;
     un.alpha = desc->alpha;
@@ -810,7 +842,7 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
     l1pr_status st = setup(&q, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
     const Tables& tb = c.tb;
-    if (c.pcg) {  // no factorisation: nothing to choose
+    if (c.pcg || (c.diag && !c.reg)) {  // no factorisation: nothing to choose
       *tune_out = 0;
       return L1PR_OK;
     }

@@ -318,6 +318,42 @@ hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, con
   return hipGetLastError();
 }
 
+// Constant D (solver = 2): the sine basis diagonalises the stiffness, D (grad phi_k, grad phi_l)
+// = D lambda_k delta_kl with lambda_k = (k pi)^2 (1D) or (k1^2 + k2^2) pi^2 (2D), so the step is
+// c_k = (rhs_k + tau F_k) / (1 + tau D lambda_k), one thread per coefficient, stored through
+// the step's epilogue.  F = nullptr: rhs already holds hist + tau F.
+__global__ void k_diag_solve(Tables tb, StepArgs a, Epilogue ep, int units, const double* F,
+                             const double* rhs) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)units * tb.Mp) return;
+  const int u = (int)(idx / tb.Mp), k = (int)(idx % tb.Mp);
+  const UnitView v = decode_unit(tb, a, u);
+  const double* ins = tb.inst + (long)v.b * NSCAL;
+  double x = 0.0;
+  if (k < (int)ins[IS_MB]) {
+    const double tau = ins[v.tau_slot];
+    double lam;
+    if (tb.dim == 1) {
+      const double kp = (double)(k + 1) * kPi;
+      lam = kp * kp;
+    } else {
+      const double k1 = (double)(k / tb.M1 + 1), k2 = (double)(k % tb.M1 + 1);
+      lam = (k1 * k1 + k2 * k2) * (kPi * kPi);
+    }
+    const double r = F ? rhs[idx] + tau * F[idx] : rhs[idx];
+    x = r / (1.0 + tau * (tb.d_param * lam));
+  }
+  const bool last = (a.mode == MODE_FINE) && (a.r == v.Sb);
+  epi_store(a, ep, u, v.slot, last, k, x);
+}
+
+hipError_t launch_diag_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                             const double* F, hipStream_t s) {
+  const long n = (long)units * tb.Mp;
+  k_diag_solve<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(tb, a, e, units, F, a.rhs);
+  return hipGetLastError();
+}
+
 hipError_t launch_form_rhs(const Tables& tb, const StepArgs& a, int units, hipStream_t s) {
   const long n = (long)units * tb.Mp;
   k_form_rhs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(tb, a, units, a.F, a.rhs);

@@ -41,10 +41,18 @@ def test_host_entry_points(L):
     par = L.l1pr_workspace_bytes(ctypes.byref(p), 32, 1)
     # the parareal workspace holds B*P systems of M^2 doubles
     assert par > 32 * 64 * 256 * 256 * 8 > ser > 0
-    # the iterative solve is 2D only; solver codes past 1 are invalid
+    # the iterative solve is 2D only; the diagonal solve needs constant D and the moment
+    # assembly; solver codes past 2 are invalid
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.C2))) == -1
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.C3))) == 0
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.C3))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(W.C3, d_sel=0)))) == 0
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(W.C2, d_sel=0)))) == 0
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, assembly=1, **W.with_(W.C2, d_sel=0)))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=3, **W.with_(W.C2, d_sel=0)))) == -1
+    # no factorisation workspace for the diagonal solve
+    pd, pc = make_problem(solver=2, **W.with_(W.C2, d_sel=0)), make_problem(**W.with_(W.C2, d_sel=0))
+    assert L.l1pr_workspace_bytes(ctypes.byref(pd), 32, 1) < L.l1pr_workspace_bytes(ctypes.byref(pc), 32, 1)
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.with_(W.C3, quad=95)))) == -1
     bad = make_problem(**W.with_(W.C2, steps=4095))
     assert L.l1pr_validate(ctypes.byref(bad)) == -1
