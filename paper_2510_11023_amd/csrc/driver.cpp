@@ -1094,7 +1094,7 @@ struct BatchGroup {
 int batch_md(const l1pr_problem& p) { return p.dim == 1 ? p.modes : p.modes * p.modes; }
 
 bool uneven_capable(const l1pr_problem& p) {
-  return p.dim == 1 && p.history == 0 && roundup(p.modes, 16) <= 256;
+  return p.dim == 1 && p.history == 0 && p.solver == 0 && roundup(p.modes, 16) <= 256;
 }
 
 // Groups in order of first appearance; members in input order.

@@ -74,6 +74,25 @@ def test_batch_parareal_equals_single_runs(gpu):
         assert torch.equal(U, own[0]), kw
 
 
+def test_batch_constant_d_diagonal_groups(gpu, orc):
+    """Problems with the diagonal solve (solver = 2) never join an uneven group (which runs
+    the factorisation only): each size runs as its own plain group, equal to its single run
+    and to the oracle."""
+    probs = [(base1d(modes=24, steps=16, alpha=0.3, d_sel=0, d_param=0.7), 1),
+             (base1d(modes=30, steps=16, alpha=0.6, d_sel=0, d_param=0.7), 2),
+             (base1d(modes=30, steps=16, alpha=0.6, d_sel=0, d_param=0.7), 3),
+             (dict(W.C3, modes=4, quad=8, steps=8, slices=4, d_sel=0, d_param=0.7), 4)]
+    ps = [gpu.make_problem(solver=2, **kw) for kw, _ in probs] + [gpu.make_problem(**PROBLEMS[0][0])]
+    u0s = [torch.tensor(u0_of(kw, s), device="cuda") for kw, s in probs + [PROBLEMS[0]]]
+    outs = gpu.solve_batch(ps, u0s)
+    for i, (p, u, U) in enumerate(zip(ps, u0s, outs)):
+        own, _ = gpu.solve_serial(p, u[None])
+        assert torch.equal(U, own[0]), i
+    for (kw, s), U in zip(probs, outs):
+        ref = orc.solve_serial(orc.problem(solver=2, **kw), u0_of(kw, s))
+        assert rel(U.cpu().numpy(), ref) <= TOL, (kw, rel(U.cpu().numpy(), ref))
+
+
 def test_batch_rejects_before_launching(gpu):
     from paper_2510_11023_amd import _lib
 
