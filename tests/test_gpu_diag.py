@@ -122,6 +122,22 @@ def test_diag_parareal_exact_and_matches_oracle(gpu, orc, name):
     assert torch.equal(r.U, Us)
 
 
+@pytest.mark.parametrize("tune", [1, 2, 3])
+def test_diag_tile_variants_match_oracle_and_stay_exact(gpu, orc, tune):
+    """The GEMM tile variants (tune bits 0 and 1) change the load vector's summation order
+    only: serial against the oracle at 1e-10, parareal exact against the serial solve."""
+    kw = CASES["1d_M24_Q32"]
+    print(f"[diag] tune={tune}", flush=True)
+    pg, po = gpu.make_problem(solver=2, tune=tune, **kw), orc.problem(solver=2, **kw)
+    u0 = u0_of(kw, [5, 6])
+    Us, _ = gpu.solve_serial(pg, dev(u0))
+    for b in range(2):
+        assert rel(Us[b].cpu().numpy(), orc.solve_serial(po, u0[b])) <= TOL, b
+    r = gpu.solve_parareal(pg, dev(u0), 2, tol=0.0, want_iterates=True)
+    for k in range(3):
+        assert torch.equal(r.iterates[k][:, : k + 1], Us[:, : k + 1]), k
+
+
 def test_diag_full_shape_first_step_every_coefficient(gpu, orc):
     """One step at the config-2 shape with constant D (256 modes, 384 points): every GPU
     coefficient satisfies c1_k (1 + tau D lambda_k) = c0_k + tau F_k with the oracle's load."""
