@@ -298,3 +298,19 @@ def test_features_match_definition(gpu):
             assert np.array_equal(x[s, :M], G[b, n].astype(np.float32))
             assert x[s, M] == np.float32(al[b]) and x[s, M + 1] == np.float32(n / P)
             assert np.array_equal(t[s], (Z[b, n + 1] - G[b, n]).astype(np.float32))
+
+
+def test_learned_parareal_exact_with_diagonal_solve(gpu):
+    """Constant D with the diagonal step solve (solver = 2): the learned coarse step wraps the
+    plain one the same way, and parareal stays exact bit for bit against the serial solve."""
+    kw = W.with_(SMALL, d_sel=0, d_param=0.8)
+    model = _trained(gpu, kw, list(W.alphas_uniform(16, seed=6)), range(16), epochs=1)
+    pg = gpu.make_problem(solver=2, **kw)
+    u0 = dev(W.u0_batch_1d(kw["modes"], [31, 32]))
+    Us, _ = gpu.solve_serial(pg, u0)
+    res = gpu.solve_parareal(pg, u0, kw["slices"], want_iterates=True, coarse=gpu.COARSE_LEARNED,
+                             mlp_params=model.params)
+    for k in range(res.iters + 1):
+        assert torch.equal(res.iterates[k][:, : k + 1], Us[:, : k + 1]), k
+    plain = gpu.solve_parareal(pg, u0, 0, want_iterates=True).iterates[0]
+    assert not torch.equal(res.iterates[0], plain)   # the network's correction is applied
