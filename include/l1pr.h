@@ -134,8 +134,9 @@ typedef struct {
                               (k pi)^2, or (k1^2 + k2^2) pi^2 in 2D), so a step is the O(M)
                               division c_k = (hist_k + tau F_k) / (1 + tau D lambda_k); the load
                               F stays the quadrature sum.  Equal to solver 0 up to the
-                              quadrature error of the stiffness (rounding level once Q is
-                              about 2M in 1D, 3M in 2D); the spectral diagonalisation among the
+                              quadrature error of the stiffness (rounding level at Q = 2M in
+                              1D from M of about 64 on, at Q = 3M in 2D for M = 12; smaller M
+                              needs a larger ratio); the spectral diagonalisation among the
                               outlook items of the paper's conclusions.  Not for uneven
                               batches. */
 } l1pr_problem;
