@@ -556,9 +556,38 @@ def constant_d(l1, torch, W, dev, alpha=0.3):
                                            f"{kw2['slices']} slices of {kw2['steps'] // kw2['slices']} "
                                            f"steps, D = 1, config-3 f",
                                "solver2_diagonal": round(two[2], 2), "solver0_cholesky": round(two[0], 2)}
+    # 256 x 256 modes (65536 coefficients): beyond the factorisation paths
+    kw3 = W.with_(W.C3, modes=256, quad=384, d_sel=0, d_param=1.0)
+    M3 = kw3["modes"] ** 2
+    p3 = l1.make_problem(solver=2, **kw3)
+    u3 = torch.tensor(W.u0_random_2d(kw3["modes"], 0)[None], device=dev)
+    ws3 = l1.parareal_workspace(p3, 1, dev)
+    Z3 = l1.solve_parareal(p3, u3, 0, tol=0.0, want_iterates=True, workspace=ws3).iterates[0].contiguous()
+    l1.fine_apply(p3, Z3, workspace=ws3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l1.fine_apply(p3, Z3, workspace=ws3)
+    torch.cuda.synchronize()
+    t_fs = time.perf_counter() - t0
+    del ws3
+    ws3s = torch.empty(l1.workspace_bytes(p3, 1, 0), dtype=torch.uint8, device=dev)
+    l1.solve_serial(p3, u3, workspace=ws3s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l1.solve_serial(p3, u3, workspace=ws3s)
+    torch.cuda.synchronize()
+    t_s3 = time.perf_counter() - t0
+    del ws3s
+    N3 = kw3["steps"]
+    out["2d_256_modes"] = {
+        "workload": f"2D, M=256x256 ({M3} coefficients), Q=384, N={N3}, P={kw3['slices']}, D = 1, "
+                    f"config-3 f and alpha, one instance, diagonal solve",
+        "fine_sweep_ms": round(t_fs * 1e3, 2), "fine_sweep_mode_steps_per_s": M3 * N3 / t_fs,
+        "serial_ms": round(t_s3 * 1e3, 1), "serial_mode_steps_per_s": M3 * N3 / t_s3}
     log(f"constant D: serial {res[2][0]['serial_ms']:.0f} ms (diag) vs {res[0][0]['serial_ms']:.0f} ms "
         f"(Cholesky); parareal {res[2][0]['parareal_ms']:.0f} vs {res[0][0]['parareal_ms']:.0f} ms; "
-        f"2D fine sweep {two[2]:.1f} vs {two[0]:.1f} ms")
+        f"2D fine sweep {two[2]:.1f} vs {two[0]:.1f} ms; 256x256 modes: fine sweep {t_fs * 1e3:.1f} ms, "
+        f"serial {t_s3 * 1e3:.0f} ms")
     return out
 
 

@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kMaxModes1D = 1024;  // the 1D evaluation kernel stages Mp + Qp doubles in LDS
 constexpr int kMaxModes2D = 64;
+constexpr int kMaxModes2DDiag = 256;  // the diagonal solve forms no system matrix
 constexpr int kSerialBlock = 64;  // steps per prefix launch of the full-history serial solve
 constexpr int kCgCap = 200;       // conjugate-gradient iterations per step solve, at most
 constexpr int kCgCheck = 4;       // iterations between the host's convergence checks
@@ -61,7 +62,7 @@ bool valid(const l1pr_problem* p) {
   if (p->modes < 1 || p->quad < p->modes) return false;
   if (p->dim == 1 && (p->modes > kMaxModes1D || roundup(p->modes, 16) + roundup(p->quad, 16) > 8192))
     return false;
-  if (p->dim == 2 && p->modes > kMaxModes2D) return false;
+  if (p->dim == 2 && p->modes > (p->solver == 2 ? kMaxModes2DDiag : kMaxModes2D)) return false;
   if (p->dim == 2 && p->assembly != 0) return false;  // 2D forms the stiffness from moments
   if (p->steps < 1 || p->slices < 1 || p->steps % p->slices != 0) return false;
   if (!(p->alpha > 0.0 && p->alpha <= 1.0)) return false;
@@ -146,7 +147,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   const bool pcg = p->solver == 1, diag = p->solver == 2;
   L.A = (pcg || diag) ? 0 : take(cur, D * units * Mp * Mp);
   L.g = take(cur, D * units * nq);
-  L.mom = take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
+  L.mom = (two && diag) ? 0 : take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
   L.F = take(cur, D * units * Mp);
   L.C2 = two ? take(cur, D * units * Mp) : 0;
   L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
@@ -425,7 +426,7 @@ StepArgs base_args(const Ctx& c) {
   a.rhs = c.ptr(c.L.rhs);
   a.A = (c.pcg || c.diag) ? nullptr : c.ptr(c.L.A);
   a.g = c.ptr(c.L.g);
-  a.mom = c.ptr(c.L.mom);
+  a.mom = c.L.mom ? c.ptr(c.L.mom) : nullptr;
   a.F = c.ptr(c.L.F);
   a.C2 = c.L.C2 ? c.ptr(c.L.C2) : nullptr;
   a.T2 = c.L.T2 ? c.ptr(c.L.T2) : nullptr;

@@ -50,6 +50,11 @@ def test_host_entry_points(L):
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(W.C2, d_sel=0)))) == 0
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, assembly=1, **W.with_(W.C2, d_sel=0)))) == -1
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=3, **W.with_(W.C2, d_sel=0)))) == -1
+    # without a system matrix the diagonal solve takes up to 256 modes per direction in 2D
+    big = W.with_(W.C3, d_sel=0, modes=256, quad=384)
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **big))) == 0
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=0, **big))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(big, modes=257, quad=400)))) == -1
     # no factorisation workspace for the diagonal solve
     pd, pc = make_problem(solver=2, **W.with_(W.C2, d_sel=0)), make_problem(**W.with_(W.C2, d_sel=0))
     assert L.l1pr_workspace_bytes(ctypes.byref(pd), 32, 1) < L.l1pr_workspace_bytes(ctypes.byref(pc), 32, 1)

@@ -67,6 +67,7 @@ CASES = {
     "2d_ragged_M7_Q10_logistic": const_d(W.C3, modes=7, quad=10, steps=9, slices=3, alpha=0.85,
                                          f_sel=2),
     "2d_full_history_M4": const_d(W.C3, modes=4, quad=8, steps=12, slices=3, history=1),
+    "2d_M12_Q18": const_d(W.C3, modes=12, quad=18, steps=8, slices=2, alpha=0.6),
 }
 
 
@@ -154,6 +155,32 @@ def test_diag_full_shape_first_step_every_coefficient(gpu, orc):
     rhs = c0[0] + tau * F
     scale = np.abs(lhs) + np.abs(c0[0]) + tau * np.abs(F)
     assert np.max(np.abs(lhs - rhs) / scale) <= TOL
+
+
+def test_diag_2d_128_modes_first_step_every_coefficient(gpu, orc):
+    """2D with 128 x 128 modes (16384 coefficients, beyond the factorisation paths), 144 x 144
+    points: every coefficient of one step against the oracle's load, and parareal exact."""
+    T = 1.0 / 2048
+    kw = const_d(W.C3, modes=128, quad=144, steps=1, slices=1, T=T)
+    pg, po = gpu.make_problem(solver=2, **kw), orc.problem(solver=2, **kw)
+    c0 = W.u0_random_2d(128, 2)
+    _, tr = gpu.solve_serial(pg, dev(c0[None]), want_traj=True)
+    c1 = tr[0, 1].cpu().numpy()
+    tau = T ** kw["alpha"] * math.gamma(2.0 - kw["alpha"])
+    _, F = orc.galerkin_rows(po, c0, 0.0, 0.0, [0])
+    k1, k2 = np.meshgrid(np.arange(1, 129), np.arange(1, 129), indexing="ij")
+    lam = ((k1 ** 2 + k2 ** 2) * math.pi ** 2).ravel()
+    lhs = c1 * (1.0 + tau * 0.8 * lam)
+    rhs = c0 + tau * F
+    scale = np.abs(lhs) + np.abs(c0) + tau * np.abs(F)
+    assert np.max(np.abs(lhs - rhs) / scale) <= TOL
+    kp = const_d(W.C3, modes=128, quad=144, steps=8, slices=4, T=8.0 / 2048)
+    pp = gpu.make_problem(solver=2, **kp)
+    u0 = dev(np.stack([W.u0_random_2d(128, s) for s in (3, 4)]))
+    Us, _ = gpu.solve_serial(pp, u0)
+    r = gpu.solve_parareal(pp, u0, 4, tol=0.0, want_iterates=True)
+    for k in range(5):
+        assert torch.equal(r.iterates[k][:, : k + 1], Us[:, : k + 1]), k
 
 
 def test_diag_full_shape_parareal_exact(gpu):
