@@ -583,6 +583,11 @@ def constant_d(l1, torch, W, dev, alpha=0.3):
         "workload": f"2D, M=256x256 ({M3} coefficients), Q=384, N={N3}, P={kw3['slices']}, D = 1, "
                     f"config-3 f and alpha, one instance, diagonal solve",
         "fine_sweep_ms": round(t_fs * 1e3, 2), "fine_sweep_mode_steps_per_s": M3 * N3 / t_fs,
+        # the four separable products per unit step (lagged state on the grid and back to the
+        # load vector): 2 (2 M^2 Q + 2 Q^2 M) flops, over the sweep's wall time
+        "products_tflops_over_sweep": round(
+            2 * (2 * kw3["modes"] ** 2 * kw3["quad"] + 2 * kw3["quad"] ** 2 * kw3["modes"])
+            * kw3["slices"] * (N3 // kw3["slices"]) / t_fs / 1e12, 2),
         "serial_ms": round(t_s3 * 1e3, 1), "serial_mode_steps_per_s": M3 * N3 / t_s3}
     log(f"constant D: serial {res[2][0]['serial_ms']:.0f} ms (diag) vs {res[0][0]['serial_ms']:.0f} ms "
         f"(Cholesky); parareal {res[2][0]['parareal_ms']:.0f} vs {res[0][0]['parareal_ms']:.0f} ms; "
