@@ -80,7 +80,8 @@ typedef struct {
   int32_t dim;          /* 1 or 2 */
   int32_t modes;        /* M per direction, >= 1; at most 1024 in 1D and 64 in 2D (M^2
                            coefficients; more than 256 go through the device-memory
-                           factorisation); 256 in 2D with the diagonal solve (solver = 2) */
+                           factorisation); with the diagonal solve (solver = 2) 4096 in 1D
+                           (Q <= 8192) and 256 in 2D */
   int32_t quad;         /* Q per direction, >= M */
   int32_t steps;        /* N fine steps, N % P == 0 */
   int32_t slices;       /* P parareal slices (coarse steps) */

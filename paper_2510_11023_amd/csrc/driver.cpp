@@ -30,6 +30,7 @@ namespace {
 constexpr int kMaxModes1D = 1024;  // the 1D evaluation kernel stages Mp + Qp doubles in LDS
 constexpr int kMaxModes2D = 64;
 constexpr int kMaxModes2DDiag = 256;  // the diagonal solve forms no system matrix
+constexpr int kMaxModes1DDiag = 4096;  // ... and in 1D runs the GEMM products at any size
 constexpr int kSerialBlock = 64;  // steps per prefix launch of the full-history serial solve
 constexpr int kCgCap = 200;       // conjugate-gradient iterations per step solve, at most
 constexpr int kCgCheck = 4;       // iterations between the host's convergence checks
@@ -60,7 +61,10 @@ bool valid(const l1pr_problem* p) {
   if (!p) return false;
   if (p->dim != 1 && p->dim != 2) return false;
   if (p->modes < 1 || p->quad < p->modes) return false;
-  if (p->dim == 1 && (p->modes > kMaxModes1D || roundup(p->modes, 16) + roundup(p->quad, 16) > 8192))
+  if (p->dim == 1 && p->solver == 2 && (p->modes > kMaxModes1DDiag || p->quad > 2 * kMaxModes1DDiag))
+    return false;
+  if (p->dim == 1 && p->solver != 2 &&
+      (p->modes > kMaxModes1D || roundup(p->modes, 16) + roundup(p->quad, 16) > 8192))
     return false;
   if (p->dim == 2 && p->modes > (p->solver == 2 ? kMaxModes2DDiag : kMaxModes2D)) return false;
   if (p->dim == 2 && p->assembly != 0) return false;  // 2D forms the stiffness from moments
@@ -300,13 +304,12 @@ hipError_t timed(const char* kernel, const StepArgs& a, int units, hipStream_t s
 l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int units) {
   if (c.diag) {
     // constant D: the load vector at the lagged state (separable products in 2D, the two
-    // GEMMs in 1D, or the evaluation kernel, which also forms hist + tau F, for more than 256
-    // coefficients), the history sums, then the diagonal solve
+    // GEMMs in 1D at any size), the history sums, then the diagonal solve
     if (c.tb.dim == 2) {
       L1PR_TRY(timed("products2d", a, units, c.s, [&] {
         return launch_step2d_products(c.tb, a, units, a.C2, a.T2, a.mom, c.s, false);
       }));
-    } else if (c.reg) {
+    } else {
       const bool coarse = a.mode == MODE_COARSE;
       const bool sk_lag = coarse || !(c.tb.tune & TUNE_LAG_TILED);
       const bool sk_proj = coarse || (c.tb.tune & TUNE_PROJ_SKINNY);
@@ -314,10 +317,6 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
       L1PR_TRY(timed("proj", a, units, c.s, [&] {
         return launch_proj_gemm(c.tb, units, a.d, a.g, nullptr, a.F, sk_proj, c.s);
       }));
-    } else {
-      L1PR_TRY(timed("eval", a, units, c.s, [&] { return launch_eval(c.tb, a, units, c.s); }));
-      L1PR_TRY(timed("diag", a, units, c.s, [&] { return launch_diag_solve(c.tb, a, e, units, nullptr, c.s); }));
-      return L1PR_OK;
     }
     L1PR_TRY(timed("history", a, units, c.s, [&] { return launch_history(c.tb, a, units, a.rhs, c.s); }));
     L1PR_TRY(timed("diag", a, units, c.s, [&] { return launch_diag_solve(c.tb, a, e, units, a.F, c.s); }));
@@ -843,11 +842,11 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
     l1pr_status st = setup(&q, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
     const Tables& tb = c.tb;
-    if (c.pcg || (c.diag && !c.reg)) {  // no factorisation: nothing to choose
+    if (c.pcg) {  // no factorisation: nothing to choose
       *tune_out = 0;
       return L1PR_OK;
     }
-    if (!c.reg) {
+    if (!c.reg && !c.diag) {
       // blocked factorisation: block width (256 / 128) and trailing tiles (128 / 64), timed on
       // a fine step's systems (B P units, set to the identity before each factorisation; the
       // kernels' work does not depend on the values)

@@ -55,6 +55,11 @@ def test_host_entry_points(L):
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **big))) == 0
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=0, **big))) == -1
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(big, modes=257, quad=400)))) == -1
+    long1d = W.with_(W.C2, d_sel=0, modes=4096, quad=8192)
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **long1d))) == 0
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=0, **long1d))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(long1d, modes=4097)))) == -1
+    assert L.l1pr_validate(ctypes.byref(make_problem(solver=2, **W.with_(long1d, quad=8193)))) == -1
     # no factorisation workspace for the diagonal solve
     pd, pc = make_problem(solver=2, **W.with_(W.C2, d_sel=0)), make_problem(**W.with_(W.C2, d_sel=0))
     assert L.l1pr_workspace_bytes(ctypes.byref(pd), 32, 1) < L.l1pr_workspace_bytes(ctypes.byref(pc), 32, 1)

@@ -3,8 +3,7 @@ stiffness, D (grad phi_k, grad phi_l) = D lambda_k delta_kl, so a step is
 c_k = (hist_k + tau F_k) / (1 + tau D lambda_k) with the load F by Gauss quadrature.
 
 Bars: serial trajectories and parareal iterates against the oracle's solver = 2 at 1e-10
-relative L2 (1D with the GEMM products and with the evaluation kernel beyond 256 modes, 2D,
-hybrid and full history); backward Euler in closed form at alpha = 1; at the full config-2
+relative L2 (1D below and above 256 modes, 2D, hybrid and full history); backward Euler in closed form at alpha = 1; at the full config-2
 shape every coefficient of one step against the oracle's load; parareal exact bit for bit
 against the GPU serial solve; an instance's result independent of its batch; agreement with
 the Cholesky path where the quadrature makes the stiffness diagonal to rounding."""
@@ -61,7 +60,7 @@ CASES = {
     "1d_ragged_M13_Q17_sin": const_d(W.C2, modes=13, quad=17, steps=12, slices=3, alpha=0.3,
                                      f_sel=3),
     "1d_full_history_M16": const_d(W.C2, modes=16, quad=24, steps=12, slices=3, history=1),
-    "1d_eval_M300_Q310": const_d(W.C2, modes=300, quad=310, steps=4, slices=2, alpha=0.7),
+    "1d_M300_Q310": const_d(W.C2, modes=300, quad=310, steps=4, slices=2, alpha=0.7),
     "1d_alpha1": const_d(W.C2, modes=20, quad=30, steps=8, slices=2, alpha=1.0),
     "2d_M6_Q9": const_d(W.C3, modes=6, quad=9, steps=12, slices=3),
     "2d_ragged_M7_Q10_logistic": const_d(W.C3, modes=7, quad=10, steps=9, slices=3, alpha=0.85,
@@ -106,7 +105,7 @@ def test_diag_backward_euler_closed_form(gpu, dim):
 
 
 @pytest.mark.parametrize("name", ["1d_M24_Q32", "1d_full_history_M16", "2d_M6_Q9",
-                                  "1d_eval_M300_Q310"])
+                                  "1d_M300_Q310"])
 def test_diag_parareal_exact_and_matches_oracle(gpu, orc, name):
     kw = CASES[name]
     P = kw["slices"]
@@ -177,6 +176,31 @@ def test_diag_2d_128_modes_first_step_every_coefficient(gpu, orc):
     kp = const_d(W.C3, modes=128, quad=144, steps=8, slices=4, T=8.0 / 2048)
     pp = gpu.make_problem(solver=2, **kp)
     u0 = dev(np.stack([W.u0_random_2d(128, s) for s in (3, 4)]))
+    Us, _ = gpu.solve_serial(pp, u0)
+    r = gpu.solve_parareal(pp, u0, 4, tol=0.0, want_iterates=True)
+    for k in range(5):
+        assert torch.equal(r.iterates[k][:, : k + 1], Us[:, : k + 1]), k
+
+
+def test_diag_1d_4096_modes_first_step_every_coefficient(gpu, orc):
+    """1D with 4096 modes and 4608 points (beyond the factorisation paths): every coefficient
+    of one step against the oracle's load; parareal exact at 2048 modes."""
+    T = 1.0 / 4096
+    kw = const_d(W.C2, modes=4096, quad=4608, steps=1, slices=1, T=T)
+    pg, po = gpu.make_problem(solver=2, **kw), orc.problem(solver=2, **kw)
+    c0 = W.u0_batch_1d(4096, [1])
+    _, tr = gpu.solve_serial(pg, dev(c0), want_traj=True)
+    c1 = tr[0, 1].cpu().numpy()
+    tau = T ** kw["alpha"] * math.gamma(2.0 - kw["alpha"])
+    _, F = orc.galerkin_rows(po, c0[0], 0.0, 0.0, [0])
+    lam = (np.arange(1, 4097) * math.pi) ** 2
+    lhs = c1 * (1.0 + tau * 0.8 * lam)
+    rhs = c0[0] + tau * F
+    scale = np.abs(lhs) + np.abs(c0[0]) + tau * np.abs(F)
+    assert np.max(np.abs(lhs - rhs) / scale) <= TOL
+    kp = const_d(W.C2, modes=2048, quad=2304, steps=8, slices=4, T=8.0 / 4096)
+    pp = gpu.make_problem(solver=2, **kp)
+    u0 = dev(W.u0_batch_1d(2048, [2, 3]))
     Us, _ = gpu.solve_serial(pp, u0)
     r = gpu.solve_parareal(pp, u0, 4, tol=0.0, want_iterates=True)
     for k in range(5):
