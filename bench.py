@@ -570,22 +570,33 @@ def constant_d(l1, torch, W, dev, alpha=0.3):
     l1.fine_apply(p1, Z1, workspace=ws1)
     torch.cuda.synchronize()
     t_f1 = time.perf_counter() - t0
-    del ws1, Z1
+    del Z1
     ws1s = torch.empty(l1.workspace_bytes(p1, B, 0), dtype=torch.uint8, device=dev)
     l1.solve_serial(p1, u1, workspace=ws1s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    l1.solve_serial(p1, u1, workspace=ws1s)
+    Us1, _ = l1.solve_serial(p1, u1, workspace=ws1s)
     torch.cuda.synchronize()
     t_s1 = time.perf_counter() - t0
     del ws1s
+    ks1, _ = find_kstar(l1, p1, u1, Us1, ws1, 16)
+    k1 = ks1 if ks1 is not None else 16
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U1 = l1.solve_parareal(p1, u1, k1, tol=0.0, want_incr=False, workspace=ws1).U
+    torch.cuda.synchronize()
+    t_p1 = time.perf_counter() - t0
+    del ws1
     out["1d_2048_modes"] = {
         "workload": f"1D, M={M1}, Q={kw1['quad']}, N={N}, P={P}, alpha={alpha}, {B} instances, D = 1, "
                     f"config-2 f, diagonal solve (tune = {int(p1.tune)})",
         "fine_sweep_ms": round(t_f1 * 1e3, 2), "fine_sweep_mode_steps_per_s": B * M1 * N / t_f1,
         # lagged-state product and projection, 2 M Q flops each per unit step
         "gemm_tflops_over_sweep": round(4 * M1 * kw1["quad"] * B * N / t_f1 / 1e12, 2),
-        "serial_ms": round(t_s1 * 1e3, 1), "serial_mode_steps_per_s": B * M1 * N / t_s1}
+        "serial_ms": round(t_s1 * 1e3, 1), "serial_mode_steps_per_s": B * M1 * N / t_s1,
+        "parareal_kstar": ks1, "parareal_ms": round(t_p1 * 1e3, 1),
+        "parareal_mode_steps_per_s": B * M1 * N / t_p1, "parareal_rel_err": rel_err_max(U1, Us1),
+        "parareal_speedup_over_serial": round(t_s1 / t_p1, 2)}
     # 256 x 256 modes (65536 coefficients): beyond the factorisation paths
     kw3 = W.with_(W.C3, modes=256, quad=384, d_sel=0, d_param=1.0)
     M3 = kw3["modes"] ** 2
@@ -622,7 +633,7 @@ def constant_d(l1, torch, W, dev, alpha=0.3):
     log(f"constant D: serial {res[2][0]['serial_ms']:.0f} ms (diag) vs {res[0][0]['serial_ms']:.0f} ms "
         f"(Cholesky); parareal {res[2][0]['parareal_ms']:.0f} vs {res[0][0]['parareal_ms']:.0f} ms; "
         f"2D fine sweep {two[2]:.1f} vs {two[0]:.1f} ms; 1D 2048 modes: fine sweep {t_f1 * 1e3:.1f} ms, "
-        f"serial {t_s1 * 1e3:.0f} ms; 256x256 modes: fine sweep {t_fs * 1e3:.1f} ms, "
+        f"serial {t_s1 * 1e3:.0f} ms, parareal k*={ks1} {t_p1 * 1e3:.0f} ms; 256x256 modes: fine sweep {t_fs * 1e3:.1f} ms, "
         f"serial {t_s3 * 1e3:.0f} ms")
     return out
 
