@@ -116,3 +116,21 @@ def test_profiler_start_stop_without_launches(L):
         else:
             L.l1pr_profile_start_only(names.encode())
         assert _lib.profile_stop() == {}
+
+
+def test_uneven_entry_points_reject_the_diagonal_solve(L):
+    """Uneven batches run the factorisation only: with solver = 2 both entry points return
+    L1PR_EINVAL from their argument check, before any device call (host buffers stand in for
+    the device pointers, which are never touched)."""
+    from paper_2510_11023_amd import _lib
+    from paper_2510_11023_amd import workloads as W
+    from paper_2510_11023_amd.solver import make_problem
+
+    p = make_problem(solver=2, **W.with_(W.C2, d_sel=0, modes=32, quad=48, steps=16, slices=4))
+    desc = _lib.Uneven(None, None, None)
+    buf = (ctypes.c_double * 64)()
+    ptr = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.l1pr_solve_serial_uneven(ctypes.byref(p), 1, ctypes.byref(desc), ptr, ptr, ptr, 64,
+                                      None) == _lib.EINVAL
+    assert L.l1pr_solve_parareal_uneven(ctypes.byref(p), 1, ctypes.byref(desc), ptr, ptr, 1, 0.0,
+                                        None, None, None, ptr, 64, None) == _lib.EINVAL
