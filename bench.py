@@ -68,7 +68,7 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "804cc2ec7373b11fd3515a4e39c2292171c0bbe4669f5b7ee861896fe5f45d0f",
+TRAFFIC_RECORD = {"sha256": "2c0c7b8d1426eb26d0ec288afd825fac6994c5e8bde47bb0e5eaa96f2cbff36b",
                   "fetch_kib": 8766, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": (2 * 8766 + 4096) * 1024}
 

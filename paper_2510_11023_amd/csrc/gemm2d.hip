@@ -320,8 +320,8 @@ hipError_t launch_assemble2d(const Tables& tb, const StepArgs& a, int units, con
 
 // Constant D (solver = 2): the sine basis diagonalises the stiffness, D (grad phi_k, grad phi_l)
 // = D lambda_k delta_kl with lambda_k = (k pi)^2 (1D) or (k1^2 + k2^2) pi^2 (2D), so the step is
-// c_k = (rhs_k + tau F_k) / (1 + tau D lambda_k), one thread per coefficient, stored through
-// the step's epilogue.  F = nullptr: rhs already holds hist + tau F.
+// c_k = (rhs_k + tau F_k) / (1 + tau D lambda_k), rhs holding the history sums; one thread per
+// coefficient, stored through the step's epilogue.
 __global__ void k_diag_solve(Tables tb, StepArgs a, Epilogue ep, int units, const double* F,
                              const double* rhs) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,8 +340,7 @@ __global__ void k_diag_solve(Tables tb, StepArgs a, Epilogue ep, int units, cons
       const double k1 = (double)(k / tb.M1 + 1), k2 = (double)(k % tb.M1 + 1);
       lam = (k1 * k1 + k2 * k2) * (kPi * kPi);
     }
-    const double r = F ? rhs[idx] + tau * F[idx] : rhs[idx];
-    x = r / (1.0 + tau * (tb.d_param * lam));
+    x = (rhs[idx] + tau * F[idx]) / (1.0 + tau * (tb.d_param * lam));
   }
   const bool last = (a.mode == MODE_FINE) && (a.r == v.Sb);
   epi_store(a, ep, u, v.slot, last, k, x);

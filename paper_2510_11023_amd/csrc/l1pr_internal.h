@@ -314,7 +314,7 @@ hipError_t launch_stiff2d_grid(const Tables& tb, const StepArgs& a, int units, c
 hipError_t launch_cg_step(const Tables& tb, const StepArgs& a, int units, const double* G,
                           double* kvp, const double* x0, double* x, double* r, double* p,
                           double* pd, double* cgs, int cap, double tol, bool init, hipStream_t s);
-// constant-D diagonal step solve (gemm2d.hip); F = nullptr when rhs already holds hist + tau F
+// constant-D diagonal step solve (gemm2d.hip): rhs holds the history sums, F the load vector
 hipError_t launch_diag_solve(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
                              const double* F, hipStream_t s);
 hipError_t launch_cg_count(const double* cgs, int units, int32_t* out, hipStream_t s);
