@@ -406,6 +406,22 @@ def test_parareal_exactness(orc, alpha):
         assert np.array_equal(its[kk][: kk + 1], Us[: kk + 1]), kk
 
 
+@pytest.mark.parametrize("dim,history", [(1, 0), (2, 0), (1, 1)])
+def test_parareal_exactness_diagonal_solver(orc, dim, history):
+    """The same finite-termination property with the constant-D diagonal solve (solver = 2),
+    for the hybrid and the full-history fine propagators."""
+    P = 4
+    p = orc.problem(dim=dim, modes=4, quad=6, steps=P * 3, slices=P, alpha=0.6, d_sel=0,
+                    d_param=0.7, f_sel=2, history=history, solver=2)
+    u0 = np.random.default_rng(3).standard_normal(orc.nmodes(p)) * 0.3
+    Us = orc.solve_serial(p, u0)
+    U, k, incr, its = orc.solve_parareal(p, u0, P, tol=0.0, want_iterates=True)
+    assert k == P
+    assert np.array_equal(U, Us)
+    for kk in range(P + 1):
+        assert np.array_equal(its[kk][: kk + 1], Us[: kk + 1]), kk
+
+
 def test_parareal_single_fine_step_converges_in_one_sweep(orc):
     """S = 1 makes the fine propagator identical to the coarse one: one sweep reproduces the
     serial solution and the coarse prediction already equals it."""
