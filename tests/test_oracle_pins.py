@@ -234,6 +234,84 @@ def test_alpha_one_backward_euler_closed_form(orc, dim, history):
     assert np.max(np.abs(traj[:, 1:])) < 1e-15
 
 
+@pytest.mark.parametrize("alpha", ["0.3", "0.5", "0.6", "0.7", "1.0"])
+def test_step_size_gamma_factor_golden(orc, alpha):
+    """tau = dt^alpha Gamma(2 - alpha) (Section 2.1; the coarse step uses dT): with constant D,
+    f = 0 and a single mode the first step is c1 = c0 / (1 + tau D pi^2), so tau is read off
+    the oracle's fine step and its coarse step and compared with table values of the gamma
+    function (golden file)."""
+    g = GOLDEN["gamma_2_minus_alpha"]["values"][alpha]
+    a = float(alpha)
+    D, T, P = 0.7, 0.5, 4
+    lam = D * math.pi ** 2
+    p = orc.problem(modes=1, quad=12, steps=P, slices=P, alpha=a, d_sel=0, d_param=D, T=T)
+    U = orc.solve_serial(p, np.array([1.0]))
+    tau_fine = (1.0 / U[1, 0] - 1.0) / lam
+    assert tau_fine / (T / P) ** a == pytest.approx(g, rel=1e-13)
+    pc = orc.problem(modes=1, quad=12, steps=8 * P, slices=P, alpha=a, d_sel=0, d_param=D, T=T)
+    G0 = orc.coarse_G(pc, 0, np.array([[1.0]]))
+    tau_c = (1.0 / G0[0] - 1.0) / lam
+    assert tau_c / (T / P) ** a == pytest.approx(g, rel=1e-13)
+
+
+def _scalar_l1(alpha, lam, N, P, c0, hybrid):
+    """One mode of the step recursion with a diagonal stiffness lam, written out from the
+    paper's formulas with b_x = (x+1)^(1-a) - x^(1-a), b_0 = 1 (Section 2.1):
+    full uniform L1 (eqn L1Scheme) or the hybrid fine propagator swept slice by slice
+    (eqns L1Fine, NumericalSchemeFine); no code shared with the oracle."""
+    def b(x):
+        return 1.0 if x == 0 else (x + 1) ** (1 - alpha) - x ** (1 - alpha)
+    S = N // P
+    tau = (1.0 / N) ** alpha * math.gamma(2 - alpha)
+    c = [c0]
+    if not hybrid:
+        for m in range(N):
+            h = c[m] - sum(b(m + 1 - j) * (c[j] - c[j - 1]) for j in range(1, m + 1))
+            c.append(h / (1 + tau * lam))
+        return c
+    C = [c0]
+    for n in range(P):
+        loc = [C[n]]
+        for r in range(1, S + 1):
+            h = loc[r - 1] - sum(b(r - j) * (loc[j] - loc[j - 1]) for j in range(1, r))
+            h -= S ** (-alpha) * sum(b(n - i + r / S) * (C[i] - C[i - 1]) for i in range(1, n + 1))
+            loc.append(h / (1 + tau * lam))
+        C.append(loc[-1])
+        c.extend(loc[1:])
+    return c
+
+
+@pytest.mark.parametrize("history", [0, 1])
+@pytest.mark.parametrize("alpha", [0.3, 0.75])
+def test_constant_D_modes_follow_scalar_recursion(orc, history, alpha):
+    """Constant D, f = 0: the stiffness is diag(D (k pi)^2) in the orthonormal sine basis, so
+    the modes decouple and mode k follows the scalar L1 recursion with lambda_k = D (k pi)^2
+    (hybrid and full history), checked on every step of every mode."""
+    M, N, P, D = 5, 24, 4, 0.6
+    p = orc.problem(modes=M, quad=4 * M + 8, steps=N, slices=P, alpha=alpha, d_sel=0, d_param=D,
+                    history=history)
+    u0 = np.array([0.9, -0.4, 0.25, 0.1, -0.05])
+    _, traj = orc.solve_serial(p, u0, want_traj=True)
+    for k in range(M):
+        ref = _scalar_l1(alpha, D * ((k + 1) * math.pi) ** 2, N, P, u0[k], history == 0)
+        assert np.allclose(traj[:, k], ref, rtol=1e-12, atol=1e-15 * abs(u0[k])), k
+
+
+def test_alpha_one_first_order_to_heat_solution(orc):
+    """alpha = 1 is backward Euler for u_t = D u_xx: mode 1 of u0 = sin(pi x) tends to
+    u0_1 exp(-pi^2 D t), with error halving as dt halves (first order)."""
+    D, T = 1.0, 0.2
+    ref = math.exp(-math.pi ** 2 * D * T) / math.sqrt(2)
+    errs = []
+    for N in (32, 64, 128, 256):
+        p = orc.problem(modes=2, quad=16, steps=N, slices=4, alpha=1.0, d_sel=0, d_param=D, T=T)
+        U = orc.solve_serial(p, np.array([1 / math.sqrt(2), 0.0]))
+        errs.append(abs(U[-1, 0] - ref))
+    rates = [e0 / e1 for e0, e1 in zip(errs, errs[1:])]
+    assert errs[-1] / ref < 1e-2
+    assert all(1.85 < r < 2.15 for r in rates), (errs, rates)
+
+
 def test_alpha_half_mittag_leffler_limit(orc):
     """Full uniform L1 with constant D = 1, f = 0, u0 = sin(pi x): the first mode tends to
     u0_1 E_{1/2}(-pi^2 sqrt(t)) (continuum single-mode solution; golden value at t=1);
