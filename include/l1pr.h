@@ -361,7 +361,7 @@ l1pr_status l1pr_mlp_train_step(int32_t modes, void* params, void* state, const 
  * l1pr_profile_stop() turns recording off, waits for the recorded events, and aggregates
  * the elapsed times by "kernel/mode/units" (kernel = lag | proj | assemble | history | chol |
  * eval | blk_solve | products2d | assemble2d | rhs | prefix | cg_grid | cg_step | cg_finish |
- * mlp, mode = fine | coarse | full, units = systems per launch).  It writes up to max_out
+ * mlp | refine, mode = fine | coarse | full, units = systems per launch).  It writes up to max_out
  * entries to `out` (host memory owned by the caller) and returns the number of distinct
  * entries, or -1 on a HIP error.  With launches on several streams at once, a launch's time
  * runs from its stream reaching it to its end, so it includes any wait for CUs held by the

@@ -43,6 +43,7 @@ struct Layout {
   size_t total = 0;
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
+  size_t rhs0 = 0, xs = 0;  // 1D blocked solve: right-hand side and first solution (refinement)
   size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
   size_t b12 = 0, s2 = 0;    // 2D: stacked basis tables of the separable stiffness products
   // conjugate-gradient solves (solver = 1): x, r, p, Jacobi diagonal [units][Mp];
@@ -157,7 +158,12 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
   // back-substitution partial sums of the device-memory factorisation
   const size_t nblk = (Mp + tb.nb - 1) / tb.nb;
-  L.q = (pcg || diag || reg_path_ok(tb.Mp, tb.Qp)) ? 0 : take(cur, D * units * nblk * tb.nb);
+  const bool blocked = !(pcg || diag || reg_path_ok(tb.Mp, tb.Qp));
+  L.q = blocked ? take(cur, D * units * nblk * tb.nb) : 0;
+  if (blocked && !two) {
+    L.rhs0 = take(cur, D * units * Mp);
+    L.xs = take(cur, D * units * Mp);
+  }
   if (two) {
     L.b12 = take(cur, D * M1p * 2 * Qp);
     L.s2 = take(cur, D * 2 * Qp * M1p);
@@ -410,10 +416,20 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
     }));
     return L1PR_OK;
   }
+  // 1D beyond the register path: evaluation and history, quadrature-GEMM assembly, the blocked
+  // factorisation and solve (result left in rhs), then one step of iterative refinement with
+  // the step's own operator, whose epilogue stores the refined state
   L1PR_TRY(timed("eval", a, units, c.s, [&] { return launch_eval(c.tb, a, units, c.s); }));
   L1PR_TRY(timed("assemble", a, units, c.s, [&] { return launch_assemble(c.tb, a, units, c.s); }));
+  double* rhs0 = c.ptr(c.L.rhs0);
+  L1PR_TRY(launch_copy_rows(a.rhs, c.tb.Mp, rhs0, c.tb.Mp, 1, c.tb.Mp, units, c.s));
+  Epilogue none{};
+  none.kind = EPI_NONE;
   L1PR_TRY(timed("blk_solve", a, units, c.s, [&] {
-    return launch_blk_solve(c.tb, a, e, units, c.ptr(c.L.q), c.s);
+    return launch_blk_solve(c.tb, a, none, units, c.ptr(c.L.q), c.s);
+  }));
+  L1PR_TRY(timed("refine", a, units, c.s, [&] {
+    return launch_blk_refine1d(c.tb, a, e, units, c.ptr(c.L.q), rhs0, c.ptr(c.L.xs), c.s);
   }));
   return L1PR_OK;
 }

@@ -34,7 +34,9 @@ enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2, TUNE_NB128 = 4, TUNE_TRAIL64 = 
 enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
 
 // epilogue kinds of the solve kernel
-enum { EPI_STORE = 0, EPI_STORE2 = 1, EPI_CORRECT = 2 };
+// EPI_NONE: the solve leaves its result in the right-hand-side buffer and stores nothing else
+// (the first solve of an iteratively refined step)
+enum { EPI_STORE = 0, EPI_STORE2 = 1, EPI_CORRECT = 2, EPI_NONE = 3 };
 
 struct Tables {
   // M, Mp: coefficients per instance (M^2 in 2D) and their padded count; M1, M1p: modes per
@@ -348,6 +350,11 @@ hipError_t launch_blk_solve(const Tables& tb, const StepArgs& a, const Epilogue&
                             double* q, hipStream_t s);
 hipError_t launch_blk_diag(const Tables& tb, const StepArgs& a, int units, double* A, double* rhs,
                            int r0, int w, hipStream_t s);
+// One step of iterative refinement after launch_blk_solve (1D, epilogue EPI_NONE, so the
+// solution x is in a.rhs): xs = x, r = rhs0 - (I + tau dphi^T diag(d) dphi) x with the step's
+// own d, then L L^T e = r with the stored factor, and the epilogue e stores x + e.
+hipError_t launch_blk_refine1d(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
+                               double* q, const double* rhs0, double* xs, hipStream_t s);
 bool reg_path_ok(int Mp, int Qp);
 // skinny: 16 x 16 tiles with a split reduction (few units) instead of 64 x 64 tiles.  Both
 // give every output as a fixed-order sum over its own row, but the two orders differ, so

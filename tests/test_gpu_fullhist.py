@@ -111,7 +111,7 @@ def test_full_history_serial_blocks_match_oracle(gpu, orc, name, kw, seeds):
         Uo, tro = orc.solve_serial(po, u0[b], want_traj=True)
         assert rel(U[b], Uo) <= TOL, (name, b, rel(U[b], Uo))
         per = [rel(tr[b][m], tro[m]) for m in range(tro.shape[0])]
-        assert max(per) <= 10 * TOL, (name, b, max(per))
+        assert max(per) <= TOL, (name, b, max(per))
 
 
 def test_full_history_fixed_point_is_not_the_hybrid_one(gpu):

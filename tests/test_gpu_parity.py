@@ -81,9 +81,9 @@ def _u0(kw, seeds):
 
 GEMM_CASES = [c for c in SERIAL_CASES if c[0] in (
     "config1", "small_c2_a03", "ragged_M40_Q61", "M1", "full_history", "tiles_M128")]
-# beyond the register path: the blocked device-memory factorisation, on a horizon (T = 0.1)
-# that keeps cond(A) near 5e3 (its explicit block inverses have errors of order cond(A) eps)
-GEMM_CASES += [("beyond_register_path_M272", W.with_(W.C2, modes=272, quad=300, steps=48, slices=3, alpha=0.9, T=0.1), [18])]
+# beyond the register path: the blocked device-memory factorisation with one step of
+# iterative refinement per solve (cond(I + tau K) about 4e4 here)
+GEMM_CASES += [("beyond_register_path_M272", W.with_(W.C2, modes=272, quad=300, steps=48, slices=3, alpha=0.9), [18])]
 
 
 def _serial_case(gpu, orc, name, kw, seeds, assembly):
@@ -96,7 +96,7 @@ def _serial_case(gpu, orc, name, kw, seeds, assembly):
         assert rel(trg[b], tro) <= TOL, (name, b, rel(trg[b], tro))
         # each fine state, not only the aggregate
         per = [rel(trg[b][m], tro[m]) for m in range(tro.shape[0]) if np.linalg.norm(tro[m]) > 0]
-        assert max(per) <= 10 * TOL, (name, b, max(per))
+        assert max(per) <= TOL, (name, b, max(per))
 
 
 @pytest.mark.parametrize("name,kw,seeds", SERIAL_CASES, ids=[c[0] for c in SERIAL_CASES])
@@ -249,6 +249,27 @@ def test_full_size_serial_sampled_slices(gpu, orc, c2_full):
     for b, n in ((0, 0), (17, 1), (31, 63)):
         ref = orc.fine_F(po, n, U[b, : n + 1])
         assert rel(U[b, n + 1], ref) <= TOL, (b, n, rel(U[b, n + 1], ref))
+
+
+@pytest.fixture(scope="module", params=[0.7, 1.0], ids=["a07", "a10"])
+def c2_full_alpha(gpu, request):
+    kw = W.with_(W.C2, alpha=request.param)
+    pg = gpu.make_problem(**kw)
+    u0 = W.u0_batch_1d(256, range(W.C2_BATCH))
+    U, _ = gpu.solve_serial(pg, dev(u0))
+    torch.cuda.synchronize()
+    return kw, U.cpu().numpy()
+
+
+def test_full_size_serial_sampled_slices_other_alpha(gpu, orc, c2_full_alpha):
+    """The other two config-2 groups (alpha = 0.7 and 1.0) at full size: the oracle's fine
+    propagator on the GPU's slice ends reproduces sampled slice ends, first, middle and last
+    slice."""
+    kw, U = c2_full_alpha
+    po = orc.problem(**kw)
+    for b, n in ((3, 0), (20, 31), (30, 63)):
+        ref = orc.fine_F(po, n, U[b, : n + 1])
+        assert rel(U[b, n + 1], ref) <= TOL, (kw["alpha"], b, n, rel(U[b, n + 1], ref))
 
 
 def test_full_size_parareal_prefix_exact(gpu, c2_full):
