@@ -44,6 +44,7 @@ struct Layout {
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
   size_t rhs0 = 0, xs = 0;  // 1D blocked solve: right-hand side and first solution (refinement)
+  bool hasA = false;        // A [units][Mp][Mp] is part of the workspace
   size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
   size_t b12 = 0, s2 = 0;    // 2D: stacked basis tables of the separable stiffness products
   // conjugate-gradient solves (solver = 1): x, r, p, Jacobi diagonal [units][Mp];
@@ -150,9 +151,13 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   L.d = take(cur, D * units * nq);
   L.rhs = take(cur, D * units * Mp);
   const bool pcg = p->solver == 1, diag = p->solver == 2;
-  L.A = (pcg || diag) ? 0 : take(cur, D * units * Mp * Mp);
+  // the system matrix goes through device memory only for the quadrature-GEMM assembly and
+  // the blocked factorisation; with the cosine moments the factor kernel builds it in registers
+  const bool in_regs = !two && !pcg && !diag && p->assembly == 0 && reg_path_ok(tb.Mp, tb.Qp);
+  L.hasA = !(pcg || diag || in_regs);
+  L.A = L.hasA ? take(cur, D * units * Mp * Mp) : 0;
   L.g = take(cur, D * units * nq);
-  L.mom = (two && diag) ? 0 : take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
+  L.mom = diag ? 0 : take(cur, D * units * (two ? Jp * Jp : 2 * Mp + 1));
   L.F = take(cur, D * units * Mp);
   L.C2 = two ? take(cur, D * units * Mp) : 0;
   L.T2 = two ? take(cur, D * units * Qp * Jp) : 0;
@@ -439,7 +444,7 @@ StepArgs base_args(const Ctx& c) {
   std::memset(&a, 0, sizeof(a));
   a.d = c.ptr(c.L.d);
   a.rhs = c.ptr(c.L.rhs);
-  a.A = (c.pcg || c.diag) ? nullptr : c.ptr(c.L.A);
+  a.A = c.L.hasA ? c.ptr(c.L.A) : nullptr;
   a.g = c.ptr(c.L.g);
   a.mom = c.L.mom ? c.ptr(c.L.mom) : nullptr;
   a.F = c.ptr(c.L.F);

@@ -39,8 +39,13 @@ def test_host_entry_points(L):
     assert L.l1pr_validate(ctypes.byref(p)) == 0
     ser = L.l1pr_workspace_bytes(ctypes.byref(p), 32, 0)
     par = L.l1pr_workspace_bytes(ctypes.byref(p), 32, 1)
-    # the parareal workspace holds B*P systems of M^2 doubles
-    assert par > 32 * 64 * 256 * 256 * 8 > ser > 0
+    # the parareal workspace holds the B*P fine trajectories of S+1 states; with the cosine
+    # moments no system matrix goes through device memory, while the quadrature-GEMM assembly
+    # adds B*P matrices of M^2 doubles
+    assert par > 32 * 64 * 65 * 256 * 8 > ser > 0
+    assert par < 32 * 64 * 256 * 256 * 8
+    pg = make_problem(assembly=1, **W.C2)
+    assert L.l1pr_workspace_bytes(ctypes.byref(pg), 32, 1) - par >= 32 * 64 * 256 * 256 * 8
     # the iterative solve is 2D only; the diagonal solve needs constant D and the moment
     # assembly; solver codes past 2 are invalid
     assert L.l1pr_validate(ctypes.byref(make_problem(solver=1, **W.C2))) == -1
