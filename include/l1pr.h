@@ -163,6 +163,21 @@ l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double
                               const double* u0, double* U, double* traj,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): l1pr_solve_serial with its workspace taken
+ * from a device array of L1PR_NOALLOC_SCRATCH_BYTES that the library holds on each device for
+ * the life of the process.  The call allocates nothing and frees nothing; arguments, results
+ * and errors are those of l1pr_solve_serial, and L1PR_ENOMEM (nothing launched) when
+ * l1pr_workspace_bytes(p, batch, L1PR_OP_SERIAL) exceeds L1PR_NOALLOC_SCRATCH_BYTES (for
+ * example config 1 fits, and the 1D shape M = 256, Q = 384, N = 4096, P = 64 with up to 200
+ * instances).  All calls on one device share that device's array: calls that overlap on
+ * one device (several streams or threads) race and must be serialised by the caller.  A host
+ * alpha array is copied with a pageable hipMemcpyAsync; pass NULL (p->alpha) to capture the
+ * call into a graph. */
+#define L1PR_NOALLOC_SCRATCH_BYTES (64u << 20)
+l1pr_status l1pr_solve_serial_noalloc(const l1pr_problem* p, int32_t batch, const double* alpha,
+                                      const double* u0, double* U, double* traj, void* stream);
+
 /* The two propagators on given slice ends, for every slice at once (Section 2.2):
  *   l1pr_coarse_apply: out[b][n] = G_n(Z_b[0..n])   (one coarse L1 step of size T/P),
  *   l1pr_fine_apply:   out[b][n] = F_n(Z_b[0..n])   (S fine steps with the hybrid history),

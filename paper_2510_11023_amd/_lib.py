@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "libl1pr.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE, ESOLVE = 0, -1, -2, -3, -4, -5, -6
 OP_SERIAL, OP_PARAREAL = 0, 1
+# bytes of the per-device array that l1pr_solve_serial_noalloc works in (include/l1pr.h)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Problem(ctypes.Structure):
@@ -89,6 +91,8 @@ def lib():
         L.l1pr_validate.restype = ctypes.c_int
         L.l1pr_solve_serial.argtypes = [pp, ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.l1pr_solve_serial.restype = ctypes.c_int
+        L.l1pr_solve_serial_noalloc.argtypes = [pp, ctypes.c_int32, vp, vp, vp, vp, vp]
+        L.l1pr_solve_serial_noalloc.restype = ctypes.c_int
         L.l1pr_solve_parareal.argtypes = [pp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
                                           ctypes.c_double, vp, vp, ctypes.POINTER(ctypes.c_int32),
                                           vp, ctypes.c_size_t, vp]

@@ -82,6 +82,23 @@ def solve_serial(p: Problem, u0: torch.Tensor, alpha=None, want_traj: bool = Fal
     return U, traj
 
 
+def solve_serial_noalloc(p: Problem, u0: torch.Tensor, alpha=None, want_traj: bool = False):
+    """solve_serial without a workspace: the library's per-device scratch array is used and
+    nothing is allocated on the device beyond the outputs created here (callers that must not
+    allocate at all pass their own U and traj to the C entry point)."""
+    _check_u0(p, u0)
+    B = u0.shape[0]
+    Md = nmodes(p)
+    U = torch.empty((B, p.slices + 1, Md), dtype=torch.float64, device=u0.device)
+    traj = torch.empty((B, p.steps + 1, Md), dtype=torch.float64, device=u0.device) if want_traj else None
+    keep, aptr = _alpha_arg(alpha, B)
+    st = _lib.lib().l1pr_solve_serial_noalloc(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U),
+                                              _ptr(traj), _stream())
+    if st != _lib.OK:
+        raise _lib.L1prError(st, "l1pr_solve_serial_noalloc")
+    return U, traj
+
+
 @dataclass
 class PararealResult:
     U: torch.Tensor
