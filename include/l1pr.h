@@ -39,6 +39,11 @@
  *     (parareal with tol > 0), which synchronises the stream once per sweep.
  *   - Problems are validated on the host before anything is launched; an invalid problem
  *     returns L1PR_EINVAL and touches nothing.
+ *   - The first 256 bytes of every workspace hold the call's device status word.  Every solve
+ *     clears it when it starts, and its kernels set it when a state or an increment is NaN or
+ *     infinite, or when a bounded device wait gives up.  A call that does not synchronise
+ *     (serial solves, parareal with tol <= 0, graph-captured calls) cannot return those
+ *     conditions itself: l1pr_check(ws, stream) reports them once the call has run.
  *   - No C++ exception crosses this boundary.
  */
 #ifndef L1PR_H
@@ -57,8 +62,10 @@ typedef enum {
   L1PR_ENOMEM = -2,     /* workspace smaller than l1pr_workspace_bytes() */
   L1PR_EHIP = -3,       /* HIP runtime error */
   L1PR_ENOTCONV = -4,   /* parareal stopped at max_iter < P without meeting tol; U holds the last iterate */
-  L1PR_ENONFINITE = -5, /* a parareal increment was NaN or infinite (tol > 0 only) */
-  L1PR_ESOLVE = -6      /* an iterative step solve (solver = 1) missed its tolerance */
+  L1PR_ENONFINITE = -5, /* a slice end of a serial solve or a parareal increment was NaN or infinite */
+  L1PR_ESOLVE = -6,     /* an iterative step solve (solver = 1) missed its tolerance */
+  L1PR_EWAIT = -7       /* a bounded wait inside a kernel gave up: the results of the call are
+                           not valid (a device fault, not a property of the problem) */
 } l1pr_status;
 
 /* Diffusion selectors D(x,t,u). */
@@ -197,7 +204,7 @@ l1pr_status l1pr_fine_apply(const l1pr_problem* p, int32_t batch, const double* 
 enum { L1PR_COARSE_L1 = 0,       /* the coarse L1 step G of Section 2.1 */
        L1PR_COARSE_LEARNED = 1   /* G plus a learned residual correction (below) */ };
 
-/* Parareal solve of `batch` instances, Section 2.2.
+/* Parareal solve of `batch` instances, Section 2.2 and its flowchart.
  * history = 0: the paper's hybrid fine propagator (coarse-grid history of earlier slices);
  * the fixed point is l1pr_solve_serial with history 0.
  * history = 1: full-history fine propagators: slice n's L1 history runs over the whole fine
@@ -207,32 +214,46 @@ enum { L1PR_COARSE_L1 = 0,       /* the coarse L1 step G of Section 2.1 */
  * ends after k sweeps).  Costs B*P*(2S+1)*Md doubles more workspace and one prefix launch
  * per sweep.  Not with the learned coarse propagator, uneven batches or the batch call.
  *   max_iter : number of fine sweeps allowed, 0 <= max_iter <= P.
- *   tol      : > 0 stops after the sweep whose relative increment
- *              max_b ||U^{k+1}_b - U^k_b|| / ||U^{k+1}_b|| (Frobenius over all P+1 slice ends)
- *              is <= tol (one stream synchronisation per sweep); <= 0 runs exactly
- *              min(max_iter, P) sweeps with no synchronisation.
- *   U        : device [batch][P+1][Md]   output: the last iterate.
- *   U_iters  : device [max_iter+1][batch][P+1][Md] every iterate (0 = coarse prediction), or NULL.
+ *   tol      : > 0: the stop rule of the flowchart, per instance.  After each sweep the
+ *              relative increment ||U^{k+1}_b - U^k_b|| / ||U^{k+1}_b|| (Frobenius over all
+ *              P+1 slice ends) is formed; an instance whose increment is <= tol is finished:
+ *              later sweeps keep its slice ends and skip its units.  The host synchronises
+ *              once per sweep and stops when every instance is finished.
+ *              <= 0: exactly min(max_iter, P) sweeps for every instance, no synchronisation
+ *              (graph-capturable).
+ *   coarse   : L1PR_COARSE_L1 (the coarse L1 step G of Section 2.1) or L1PR_COARSE_LEARNED:
+ *              G_L,n = G_n + r with the residual r from the network in `mlp_params` (device,
+ *              layout from l1pr_mlp_layout for M = p->modes, 1D, M <= 256, history 0,
+ *              256-byte aligned).  The network is a deterministic function of its input, so
+ *              parareal keeps its exactness (after k sweeps the first k+1 slice ends equal
+ *              the serial solution).  A unit whose correction is not finite or larger than
+ *              ||G_n|| + 1 uses the plain G_n (the plain coarse step is the fallback).
+ *              ws_bytes must then also cover l1pr_parareal_learned_extra_bytes(p, batch).
+ *   iters    : device int32 [batch] or NULL: each instance's status after the call: the
+ *              number of sweeps after which it was finished (tol > 0) or that it ran (tol <= 0,
+ *              or P sweeps: exact), L1PR_ENOTCONV if tol > 0 was not met within max_iter < P
+ *              sweeps, L1PR_ENONFINITE if its increment became NaN or infinite (the instance
+ *              is frozen at that sweep).
  *   incr     : device [batch][max_iter] relative increment of each sweep, or NULL.
- *   iters    : host int32, number of sweeps done, or NULL.
- * Returns L1PR_ENOTCONV if tol > 0 was not met within max_iter < P sweeps. */
+ *   U_iters  : device [max_iter+1][batch][P+1][Md] every iterate (0 = coarse prediction), or NULL.
+ *   U        : device [batch][P+1][Md]   output: each instance's last iterate.
+ *   sweeps   : host int32, the number of sweeps run, or NULL.
+ * Returns, for tol > 0: L1PR_ENONFINITE if an instance's increment was not finite,
+ * L1PR_ENOTCONV if an instance did not meet tol within max_iter < P sweeps, L1PR_EWAIT if a
+ * device wait gave up; for tol <= 0 those conditions are left in `iters` and the status word
+ * (l1pr_check). */
 l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const double* alpha,
                                 const double* u0, double* U, int32_t max_iter, double tol,
-                                double* U_iters, double* incr, int32_t* iters,
+                                int32_t coarse, const void* mlp_params, int32_t* iters,
+                                double* incr, double* U_iters, int32_t* sweeps,
                                 void* ws, size_t ws_bytes, void* stream);
 
-/* Parareal with a chosen coarse propagator.  coarse = L1PR_COARSE_L1 is l1pr_solve_parareal;
- * coarse = L1PR_COARSE_LEARNED uses G_L,n = G_n + r with the residual r from the network in
- * `mlp_params` (device, layout from l1pr_mlp_layout for M = p->modes, 1D, M <= 256).  The
- * network is a deterministic function of its input, so parareal keeps its exactness (after k
- * sweeps the first k+1 slice ends equal the serial solution).  A unit whose correction is not
- * finite or larger than ||G_n|| + 1 uses the plain G_n (the plain coarse step is the fallback).
- * ws_bytes must also cover l1pr_parareal_learned_extra_bytes(p, batch) more bytes. */
-l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const double* alpha,
-                                   const double* u0, double* U, int32_t max_iter, double tol,
-                                   int32_t coarse, const void* mlp_params, double* U_iters,
-                                   double* incr, int32_t* iters, void* ws, size_t ws_bytes,
-                                   void* stream);
+/* Waits for `stream` and reports the device status word of the last call that used the
+ * workspace `ws` (device, the call's workspace): L1PR_OK, L1PR_ENONFINITE (a slice end of a
+ * serial solve, or a parareal increment, was NaN or infinite), L1PR_EWAIT (a bounded device
+ * wait gave up: the results are not valid), or L1PR_EHIP. */
+l1pr_status l1pr_check(const void* ws, void* stream);
+
 /* Uneven batches (instances that differ in modes, fine steps per slice and order under one
  * problem).  All arrays are device arrays of `batch` entries; any may be NULL.
  *   modes : instance b's own modes M_b, 1 <= M_b <= p->modes (coefficients k >= M_b are

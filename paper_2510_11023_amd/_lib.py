@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libl1pr.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE, ESOLVE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, ENONFINITE, ESOLVE, EWAIT = 0, -1, -2, -3, -4, -5, -6, -7
 OP_SERIAL, OP_PARAREAL = 0, 1
 # bytes of the per-device array that l1pr_solve_serial_noalloc works in (include/l1pr.h)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -94,13 +94,11 @@ def lib():
         L.l1pr_solve_serial_noalloc.argtypes = [pp, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.l1pr_solve_serial_noalloc.restype = ctypes.c_int
         L.l1pr_solve_parareal.argtypes = [pp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
-                                          ctypes.c_double, vp, vp, ctypes.POINTER(ctypes.c_int32),
-                                          vp, ctypes.c_size_t, vp]
+                                          ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp,
+                                          ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
         L.l1pr_solve_parareal.restype = ctypes.c_int
-        L.l1pr_solve_parareal_ex.argtypes = [pp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
-                                             ctypes.c_double, ctypes.c_int32, vp, vp, vp,
-                                             ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp]
-        L.l1pr_solve_parareal_ex.restype = ctypes.c_int
+        L.l1pr_check.argtypes = [vp, vp]
+        L.l1pr_check.restype = ctypes.c_int
         L.l1pr_parareal_learned_extra_bytes.argtypes = [pp, ctypes.c_int32]
         L.l1pr_parareal_learned_extra_bytes.restype = ctypes.c_size_t
         for name in ("l1pr_coarse_apply", "l1pr_fine_apply"):

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -41,6 +42,8 @@ constexpr double kCgTolFine = 1e-14, kCgTolCoarse = 1e-10;
 
 struct Layout {
   size_t total = 0;
+  size_t flags = 0;  // the call's device status word: offset 0 of every workspace (l1pr_check)
+  size_t done = 0, conv = 0;  // parareal: per-instance finished flags and stop records [B]
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
   size_t rhs0 = 0, xs = 0;  // 1D blocked solve: right-hand side and first solution (refinement)
@@ -120,6 +123,7 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   const size_t Jp = 2 * M1p + 1;
   const bool two = p->dim == 2;
   size_t cur = 0;
+  L.flags = take(cur, 256);
   L.xq = take(cur, D * Qp);
   L.wq = take(cur, D * Qp);
   L.phi = take(cur, D * Qp * M1p);
@@ -184,6 +188,10 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
     L.cgcnt = take(cur, 2 * sizeof(int32_t));
   }
   L.incrk = take(cur, D * B);
+  if (para) {
+    L.done = take(cur, sizeof(int32_t) * B);
+    L.conv = take(cur, sizeof(int32_t) * B);
+  }
   L.total = cur;
 }
 
@@ -195,6 +203,7 @@ struct Ctx {
   bool full;     // parareal with full-history fine propagators
   bool pcg;      // 2D step systems by preconditioned conjugate gradients
   bool diag;     // constant D: the diagonal solve in the sine basis
+  const int32_t* done = nullptr;  // parareal: finished instances (skip their units)
   char* ws;
   hipStream_t s;
   double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -211,6 +220,10 @@ struct Uneven {
   const int32_t* modes = nullptr;
   const int32_t* spp = nullptr;
 };
+
+// Set while l1pr_solve_batch runs its groups: the groups share one status word, cleared once
+// by the batch call, so each group's setup leaves it as it is.
+thread_local bool t_keep_flag = false;
 
 l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, void* ws,
                   size_t ws_bytes, void* stream, Ctx& c, const Uneven& un = Uneven()) {
@@ -238,6 +251,12 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
   tb.cosq = c.ptr(c.L.cosq);
   tb.b12 = c.L.b12 ? c.ptr(c.L.b12) : nullptr;
   tb.s2 = c.L.s2 ? c.ptr(c.L.s2) : nullptr;
+  tb.flag = reinterpret_cast<int*>(c.ws + c.L.flags);
+  // bounded device waits poll up to 2^18 times; L1PR_TEST_SPIN_LIMIT lowers the bound so that
+  // tests can exercise the give-up path (the kernels still run to their end)
+  tb.spin = 1 << 18;
+  if (const char* e = std::getenv("L1PR_TEST_SPIN_LIMIT")) tb.spin = std::max(0, std::atoi(e));
+  if (!t_keep_flag) L1PR_TRY(launch_fill_int(tb.flag, 1, 0, c.s));
   c.pcg = p->solver == 1;
   c.diag = p->solver == 2;
   c.reg = reg_path_ok(tb.Mp, tb.Qp);
@@ -450,6 +469,7 @@ StepArgs base_args(const Ctx& c) {
   a.F = c.ptr(c.L.F);
   a.C2 = c.L.C2 ? c.ptr(c.L.C2) : nullptr;
   a.T2 = c.L.T2 ? c.ptr(c.L.T2) : nullptr;
+  a.done = c.done;
   return a;
 }
 
@@ -487,6 +507,7 @@ l1pr_status serial_hybrid(const Ctx& c, const double* u0, double* U, double* tra
                              (long)(tb.N + 1) * M, S, B, c.s));
   }
   L1PR_TRY(launch_unpack(Z, Mp, vecP, U, M, (long)(P + 1) * M, P + 1, B, c.s));
+  L1PR_TRY(launch_check_finite(U, (long)B * (P + 1) * M, tb.flag, c.s));
   return L1PR_OK;
 }
 
@@ -530,6 +551,7 @@ l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_
     L1PR_TRY(launch_unpack(traj + (long)n * S * Mp, Mp, trajN, U + (long)n * M, M,
                            (long)(P + 1) * M, 1, B, c.s));
   if (traj_out) L1PR_TRY(launch_unpack(traj, Mp, trajN, traj_out, M, (long)(N + 1) * M, N + 1, B, c.s));
+  L1PR_TRY(launch_check_finite(U, (long)B * (P + 1) * M, tb.flag, c.s));
   return L1PR_OK;
 }
 
@@ -564,7 +586,7 @@ l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e, const
   if (st != L1PR_OK) return st;
   L1PR_TRY(timed("mlp", a, c.tb.B, c.s, [&] {
     return mlp_coarse_apply(lg->L, lg->params, lg->G, c.tb.Mp, c.tb.inst, c.tb.B, c.tb.M, c.tb.Mp,
-                            n, c.tb.P, e, lg->ws, c.s);
+                            n, c.tb.P, e, lg->ws, c.s, c.done);
   }));
   return L1PR_OK;
 }
@@ -622,18 +644,26 @@ l1pr_status fine_sweep(const Ctx& c, const double* Z, double* traj, const double
   return L1PR_OK;
 }
 
-// Device-side convergence record: conv[b] = the first sweep whose increment is <= conv_tol
-// (-1 if none); stamps[k] = device wall clock at the end of sweep k (k = 0: initial coarse
-// sweep).  Both optional; neither needs the host, so the whole loop can be graph-captured.
+// Uneven batches' convergence record: conv[b] = the first sweep whose increment is <=
+// conv_tol (-1 if none; the instance is finished from then on); stamps[k] = device wall clock
+// at the end of sweep k (k = 0: initial coarse sweep).  Both optional; neither needs the host,
+// so the whole loop can be graph-captured.
 struct Track {
+  bool uneven = false;  // the stop test is conv_tol (no host synchronisation)
   int32_t* conv = nullptr;
-  double conv_tol = 0.0;
+  double conv_tol = -1.0;
   int64_t* stamps = nullptr;
 };
 
-l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, double tol,
-                     double* U_iters, double* incr, int* iters_out, const Learned* lg,
-                     const Track& tr = Track()) {
+// Parareal (Section 2.2 and its flowchart) with a per-instance stop: an instance whose
+// increment meets the stop test (tol > 0, or the uneven batch's conv_tol) is finished; later
+// sweeps keep its slice ends, and its units skip the factorisation and store nothing.  The
+// status of each instance goes to status_out (device [B], may be null); the number of sweeps
+// run to *sweeps_out.
+l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, double tol,
+                     double* U_iters, double* incr, int* sweeps_out, int32_t* status_out,
+                     const Learned* lg, const Track& tr = Track()) {
+  Ctx c = c0;
   const Tables& tb = c.tb;
   const int B = tb.B, P = tb.P, S = tb.S, Mp = tb.Mp, M = tb.M;
   const long vecP = (long)(P + 1) * Mp, slotS = (long)(S + 1) * Mp;
@@ -644,9 +674,13 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   // full history: the previous iterate's fine trajectories (swapped with traj every sweep)
   double* prev = c.full ? c.ptr(c.L.prev) : nullptr;
   double* incrk = c.ptr(c.L.incrk);
+  int32_t* done = reinterpret_cast<int32_t*>(c.ws + c.L.done);
+  int32_t* conv = tr.conv ? tr.conv : reinterpret_cast<int32_t*>(c.ws + c.L.conv);
+  const double exit_tol = tr.uneven ? tr.conv_tol : (tol > 0.0 ? tol : -1.0);
   const long iterStride = (long)B * (P + 1) * M;
 
-  if (tr.conv) L1PR_TRY(launch_fill_int(tr.conv, B, -1, c.s));
+  L1PR_TRY(launch_fill_int(done, B, 0, c.s));
+  L1PR_TRY(launch_fill_int(conv, B, -1, c.s));
   // coarse initial sweep: U^0_{n+1} = G_n(U^0_0..U^0_n), G_old(n) = the same value
   L1PR_TRY(launch_pack(u0, M, B, M, Zk, Mp, vecP, c.s));
   for (int n = 0; n < P; ++n) {
@@ -664,8 +698,11 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
   // before the first sweep the history of earlier slices is the interpolated coarse iterate
   if (prev) L1PR_TRY(launch_interp_slots(tb, Zk, prev, c.s));
 
-  int done = 0;
+  // from here on the steps skip the units of finished instances
+  c.done = done;
+  int sweeps = 0;
   bool met = false;
+  int hflag = 0;
   std::vector<double> h_incr(B);
   for (int k = 0; k < max_iter; ++k) {
     // parallel stage: F_old(n) = F_n(U^k_0..U^k_n) for all (b, n).  After k sweeps the slice
@@ -679,12 +716,13 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
     // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n)).
     // For n <= k the inputs of G_n are the converged slice ends, the same as when G_old(n) was
     // formed, so the bracket is exactly zero: those rows are F_old(n), copied, and G_old(n)
-    // stays.
+    // stays.  Finished instances then take back their slice ends whole.
     L1PR_TRY(launch_pack(u0, M, B, M, Zk1, Mp, vecP, c.s));
     const int n_conv = std::min(k + 1, P);
     for (int n = 0; n < n_conv; ++n)
       L1PR_TRY(launch_copy_rows(traj + ((long)n * (S + 1) + S) * Mp, (long)P * slotS,
                                 Zk1 + (long)(n + 1) * Mp, vecP, 1, Mp, B, c.s));
+    L1PR_TRY(launch_copy_done(Zk, Zk1, done, B, vecP, c.s));
     for (int n = n_conv; n < P; ++n) {
       Epilogue e{};
       e.kind = EPI_CORRECT;
@@ -697,30 +735,27 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
       l1pr_status st = coarse_step(c, Zk1, n, e, lg);
       if (st != L1PR_OK) return st;
     }
-    L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, tr.conv,
-                              tr.conv_tol, c.s));
+    L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, done, conv,
+                              exit_tol, tb.flag, c.s));
     if (tr.stamps) L1PR_TRY(launch_stamp(tr.stamps + k + 1, c.s));
     if (U_iters)
       L1PR_TRY(launch_unpack(Zk1, Mp, vecP, U_iters + (long)(k + 1) * iterStride, M,
                              (long)(P + 1) * M, P + 1, B, c.s));
     std::swap(Zk, Zk1);
     if (prev) std::swap(traj, prev);
-    done = k + 1;
-    if (done >= P) {
+    sweeps = k + 1;
+    if (sweeps >= P) {
       met = true;
       break;
     }
     if (tol > 0.0) {
+      // host stop test: every instance finished (a finished instance's increment reads 0)
       L1PR_TRY(hipMemcpyAsync(h_incr.data(), incrk, sizeof(double) * B, hipMemcpyDeviceToHost, c.s));
+      L1PR_TRY(hipMemcpyAsync(&hflag, tb.flag, sizeof(int), hipMemcpyDeviceToHost, c.s));
       L1PR_TRY(hipStreamSynchronize(c.s));
+      if (hflag & FLAG_WAIT) break;
       double mx = 0.0;
-      for (double v : h_incr) {
-        if (!std::isfinite(v)) {
-          if (iters_out) *iters_out = done;
-          return L1PR_ENONFINITE;
-        }
-        mx = std::max(mx, v);
-      }
+      for (double v : h_incr) mx = std::max(mx, v);
       if (mx <= tol) {
         met = true;
         break;
@@ -728,8 +763,17 @@ l1pr_status parareal(const Ctx& c, const double* u0, double* U, int max_iter, do
     }
   }
   L1PR_TRY(launch_unpack(Zk, Mp, vecP, U, M, (long)(P + 1) * M, P + 1, B, c.s));
-  if (iters_out) *iters_out = done;
-  if (tol > 0.0 && !met) return L1PR_ENOTCONV;
+  if (status_out)
+    L1PR_TRY(launch_finish_status(done, conv, status_out, B, sweeps, tol > 0.0 && !met, c.s));
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (tol > 0.0) {
+    // the host synchronised every sweep: report the device status word now
+    L1PR_TRY(hipMemcpyAsync(&hflag, tb.flag, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    L1PR_TRY(hipStreamSynchronize(c.s));
+    if (hflag & FLAG_WAIT) return L1PR_EWAIT;
+    if (hflag & FLAG_NONFINITE) return L1PR_ENONFINITE;
+    if (!met) return L1PR_ENOTCONV;
+  }
   return L1PR_OK;
 }
 
@@ -764,11 +808,11 @@ l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double
   }
 }
 
-l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const double* alpha,
-                                   const double* u0, double* U, int32_t max_iter, double tol,
-                                   int32_t coarse, const void* mlp_params, double* U_iters,
-                                   double* incr, int32_t* iters, void* ws, size_t ws_bytes,
-                                   void* stream) {
+l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const double* alpha,
+                                const double* u0, double* U, int32_t max_iter, double tol,
+                                int32_t coarse, const void* mlp_params, int32_t* iters,
+                                double* incr, double* U_iters, int32_t* sweeps, void* ws,
+                                size_t ws_bytes, void* stream) {
   try {
     if (!u0 || !U || !p) return L1PR_EINVAL;
     if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
@@ -789,20 +833,12 @@ l1pr_status l1pr_solve_parareal_ex(const l1pr_problem* p, int32_t batch, const d
       lg.ws = c.ws + c.L.total + (sizeof(double) * (size_t)c.tb.B * c.tb.Mp + 255) / 256 * 256;
     }
     int it = 0;
-    st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it, learned ? &lg : nullptr);
-    if (iters) *iters = it;
+    st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it, iters, learned ? &lg : nullptr);
+    if (sweeps) *sweeps = it;
     return st;
   } catch (...) {
     return L1PR_EHIP;
   }
-}
-
-l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const double* alpha,
-                                const double* u0, double* U, int32_t max_iter, double tol,
-                                double* U_iters, double* incr, int32_t* iters, void* ws,
-                                size_t ws_bytes, void* stream) {
-  return l1pr_solve_parareal_ex(p, batch, alpha, u0, U, max_iter, tol, L1PR_COARSE_L1, nullptr,
-                                U_iters, incr, iters, ws, ws_bytes, stream);
 }
 
 l1pr_status l1pr_solve_serial_uneven(const l1pr_problem* p, int32_t batch,
@@ -843,11 +879,12 @@ l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
     if (st != L1PR_OK) return st;
     if (!c.reg) return L1PR_EINVAL;
     Track tr;
+    tr.uneven = true;
     tr.conv = conv;
     tr.conv_tol = conv_tol;
     tr.stamps = stamps;
     int it = 0;
-    return parareal(c, u0, U, sweeps, 0.0, nullptr, incr, &it, nullptr, tr);
+    return parareal(c, u0, U, sweeps, 0.0, nullptr, incr, &it, nullptr, nullptr, tr);
   } catch (...) {
     return L1PR_EHIP;
   }
@@ -1087,6 +1124,16 @@ int64_t l1pr_wall_clock_khz(void) {
   return khz;
 }
 
+l1pr_status l1pr_check(const void* ws, void* stream) {
+  if (!ws) return L1PR_EINVAL;
+  int f = 0;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return L1PR_EHIP;
+  if (hipMemcpy(&f, ws, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return L1PR_EHIP;
+  if (f & FLAG_WAIT) return L1PR_EWAIT;
+  if (f & FLAG_NONFINITE) return L1PR_ENONFINITE;
+  return L1PR_OK;
+}
+
 const char* l1pr_status_string(l1pr_status s) {
   switch (s) {
     case L1PR_OK: return "ok";
@@ -1094,8 +1141,9 @@ const char* l1pr_status_string(l1pr_status s) {
     case L1PR_ENOMEM: return "workspace too small";
     case L1PR_EHIP: return "HIP runtime error";
     case L1PR_ENOTCONV: return "parareal did not meet the tolerance within max_iter sweeps";
-    case L1PR_ENONFINITE: return "non-finite parareal increment";
+    case L1PR_ENONFINITE: return "non-finite state or parareal increment";
     case L1PR_ESOLVE: return "iterative step solve missed its tolerance";
+    case L1PR_EWAIT: return "a bounded device wait gave up; the results of the call are not valid";
   }
   return "unknown status";
 }
@@ -1204,6 +1252,12 @@ l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t o
       if (group_ws(G, op).total > ws_bytes) return L1PR_ENOMEM;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
+    // one status word for the whole call (offset 0, as in every group's workspace)
+    L1PR_TRY(launch_fill_int(reinterpret_cast<int*>(base), 1, 0, s));
+    struct KeepFlag {
+      KeepFlag() { t_keep_flag = true; }
+      ~KeepFlag() { t_keep_flag = false; }
+    } keep;
     for (const BatchGroup& G : groups) {
       const int B = (int)G.members.size(), Md = batch_md(G.p), P = G.p.slices;
       const GroupWs w = group_ws(G, op);
@@ -1239,8 +1293,9 @@ l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t o
       } else {
         st = (op == L1PR_OP_SERIAL)
                  ? l1pr_solve_serial(&G.p, B, alpha.data(), u0p, Up, nullptr, base, w.solver, stream)
-                 : l1pr_solve_parareal(&G.p, B, alpha.data(), u0p, Up, k, 0.0, nullptr, nullptr,
-                                       nullptr, base, w.solver, stream);
+                 : l1pr_solve_parareal(&G.p, B, alpha.data(), u0p, Up, k, 0.0, L1PR_COARSE_L1,
+                                       nullptr, nullptr, nullptr, nullptr, nullptr, base, w.solver,
+                                       stream);
       }
       if (st != L1PR_OK) return st;
       // scatter each member's slice ends (its own Md columns of every row)

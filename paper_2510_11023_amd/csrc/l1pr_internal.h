@@ -38,6 +38,9 @@ enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
 // (the first solve of an iteratively refined step)
 enum { EPI_STORE = 0, EPI_STORE2 = 1, EPI_CORRECT = 2, EPI_NONE = 3 };
 
+// bits of the call's device status word (the first bytes of every workspace)
+enum { FLAG_NONFINITE = 1, FLAG_WAIT = 2 };
+
 struct Tables {
   // M, Mp: coefficients per instance (M^2 in 2D) and their padded count; M1, M1p: modes per
   // direction (the basis tables' width); Q, Qp: Gauss points per direction
@@ -56,6 +59,8 @@ struct Tables {
   const double* cosq;  // [Qp][2 Mp + 1] = cos(j pi x_q) (zero for padding nodes)
   const double* b12;   // 2D: [M1p][2 Qp] = [phi^T | dphi^T]
   const double* s2;    // 2D: [2 Qp][M1p] = [dphi; phi]
+  int* flag;           // the call's device status word (FLAG_* bits, set with atomicOr)
+  int spin;            // polls of a bounded device wait before it gives up (sets FLAG_WAIT)
 };
 
 // What one step-launch computes for each of its units.
@@ -84,7 +89,19 @@ struct StepArgs {
   const double* prev;
   const double* hp;
   int hw;
+  // parareal: instances that have met their stop test (nonzero) keep their slice ends; their
+  // units skip the factorisation and store nothing (nullptr: no instance is finished)
+  const int32_t* done;
 };
+
+// instance of unit u in a step launch
+__host__ __device__ inline int unit_instance(const StepArgs& a, int u) {
+  return a.mode == MODE_FINE ? u / a.nP : u;
+}
+
+__device__ inline bool unit_done(const StepArgs& a, int u) {
+  return a.done != nullptr && a.done[unit_instance(a, u)] != 0;
+}
 
 struct Epilogue {
   int kind;
@@ -288,6 +305,7 @@ __device__ inline double full_serial_history(const Tables& tb, const StepArgs& a
 // CORRECT = the parareal update F_old + (x - G_old), then G_old = x).
 __device__ inline void epi_store(const StepArgs& a, const Epilogue& ep, int u, long slot,
                                  bool last_fine, int k, double x) {
+  if (ep.kind == EPI_NONE || unit_done(a, u)) return;
   if (ep.kind == EPI_CORRECT) {
     const double go = ep.gold[(long)u * ep.gold_stride + k];
     ep.out[(long)u * ep.out_stride + k] = ep.fold[(long)u * ep.fold_stride + k] + (x - go);
@@ -379,9 +397,23 @@ hipError_t launch_unpack(const double* src, int Mp, long src_stride, double* dst
                          long dst_stride, int rows_per_unit, int units, hipStream_t s);
 hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* dst, int Mp,
                              long dst_stride, int rows_per_unit, int units, hipStream_t s);
+// Per-instance relative increment ||Znew_b - Zold_b|| / ||Znew_b|| of sweep k (0-based), and
+// the per-instance stop test: an unfinished instance whose increment is <= exit_tol is marked
+// done (done[b] = 1, conv[b] = k + 1); a non-finite increment marks it done with
+// conv[b] = L1PR_ENONFINITE and sets FLAG_NONFINITE.  Finished instances keep their record.
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
-                            int32_t* conv, double conv_tol, hipStream_t s);
+                            int32_t* done, int32_t* conv, double exit_tol, int* flag,
+                            hipStream_t s);
+// Zdst[b] = Zsrc[b] (rows x Mp) for the finished instances
+hipError_t launch_copy_done(const double* Zsrc, double* Zdst, const int32_t* done, int B, long per,
+                            hipStream_t s);
+// per-instance status after `sweeps` sweeps: finished instances keep conv[b]; the others get
+// `sweeps` if notconv is false, else L1PR_ENOTCONV
+hipError_t launch_finish_status(const int32_t* done, const int32_t* conv, int32_t* out, int B,
+                                int sweeps, bool notconv, hipStream_t s);
+// sets FLAG_NONFINITE if any of x[0..n) is NaN or infinite
+hipError_t launch_check_finite(const double* x, long n, int* flag, hipStream_t s);
 hipError_t launch_fill_int(int32_t* x, int n, int32_t v, hipStream_t s);
 hipError_t launch_stamp(int64_t* t, hipStream_t s);
 

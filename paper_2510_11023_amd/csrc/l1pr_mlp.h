@@ -1,6 +1,7 @@
 // Internal layout of the learned coarse propagator's parameters (see mlp.hip).
 #pragma once
 #include <stddef.h>
+#include <stdint.h>
 
 #include "l1pr.h"
 
@@ -30,6 +31,7 @@ size_t mlp_infer_ws_bytes(const MlpLayout& L, int n);
 struct Epilogue;
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,
-                            const Epilogue& ep, void* ws, hipStream_t s);
+                            const Epilogue& ep, void* ws, hipStream_t s,
+                            const int32_t* done = nullptr);
 
 }  // namespace l1pr

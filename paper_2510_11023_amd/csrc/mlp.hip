@@ -456,8 +456,10 @@ __global__ void k_norm_f64(const double* x, int ldx, int ncols, int n, const flo
 // not finite or larger than ||G_L1|| + 1.  Then the step epilogue.  One work-group per unit.
 __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstride, const double* O,
                                                      int outp, int M, int Mp, const float* om,
-                                                     const float* osd, Epilogue ep) {
+                                                     const float* osd, Epilogue ep,
+                                                     const int32_t* done) {
   const int u = blockIdx.x;
+  if (done && done[u]) return;  // a finished parareal instance keeps its slice ends
   __shared__ double rc[256], rg[256];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -625,7 +627,7 @@ hipError_t mlp_forward_ws(const MlpLayout& L, const char* params, int n, MlpWs& 
 // learned correction and epilogue for B units whose plain coarse values are in G
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,
-                            const Epilogue& ep, void* ws, hipStream_t s) {
+                            const Epilogue& ep, void* ws, hipStream_t s, const int32_t* done) {
   const char* pp = (const char*)params;
   const InferWs W = carve_infer(L, B, ws);
   k_infer_input<<<nblk((long)B * L.inp), 256, 0, s>>>(G, gstride, inst, B, M, n, P,
@@ -634,7 +636,7 @@ hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double
   hipError_t r = mlp_forward_f64(L, pp, B, W.X, W.Ha, W.Hb, W.O, s);
   if (r != hipSuccess) return r;
   k_infer_apply<<<B, 256, 0, s>>>(G, gstride, W.O, L.outp, M, Mp, (const float*)(pp + L.out_mean),
-                                  (const float*)(pp + L.out_std), ep);
+                                  (const float*)(pp + L.out_std), ep, done);
   return hipGetLastError();
 }
 

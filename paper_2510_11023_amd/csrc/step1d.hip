@@ -252,10 +252,11 @@ hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* 
 }
 
 // Relative increment ||Znew_b - Zold_b|| / ||Znew_b|| per instance, fixed-order tree
-// reduction (one work-group per instance).
+// reduction (one work-group per instance), then the instance's stop test.
 __global__ __launch_bounds__(256) void k_increment(const double* Znew, const double* Zold, int rows,
                                                    int Mp, double* incr_out, int incr_stride, int k,
-                                                   double* incr_k, int32_t* conv, double conv_tol) {
+                                                   double* incr_k, int32_t* done, int32_t* conv,
+                                                   double exit_tol, int* flag) {
   __shared__ double sd[256], su[256];
   const int b = blockIdx.x, tid = threadIdx.x;
   const long per = (long)rows * Mp;
@@ -278,18 +279,71 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
     __syncthreads();
   }
   if (tid == 0) {
-    const double rel = su[0] > 0.0 ? sqrt(sd[0]) / sqrt(su[0]) : sqrt(sd[0]);
+    const bool finished = done && done[b] != 0;
+    // a finished instance keeps its slice ends: its increment is 0 from then on
+    const double rel = finished ? 0.0 : (su[0] > 0.0 ? sqrt(sd[0]) / sqrt(su[0]) : sqrt(sd[0]));
     if (incr_out) incr_out[(long)b * incr_stride + k] = rel;
     incr_k[b] = rel;
-    if (conv && conv[b] < 0 && rel <= conv_tol) conv[b] = k + 1;
+    if (!finished) {
+      if (!isfinite(rel)) {
+        if (done) done[b] = 1;
+        if (conv) conv[b] = L1PR_ENONFINITE;
+        if (flag) atomicOr(flag, FLAG_NONFINITE);
+      } else if (rel <= exit_tol) {
+        if (done) done[b] = 1;
+        if (conv) conv[b] = k + 1;
+      }
+    }
   }
 }
 
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
-                            int32_t* conv, double conv_tol, hipStream_t s) {
-  k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k, conv,
-                                conv_tol);
+                            int32_t* done, int32_t* conv, double exit_tol, int* flag,
+                            hipStream_t s) {
+  k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k, done,
+                                conv, exit_tol, flag);
+  return hipGetLastError();
+}
+
+// one work-group per instance: the finished ones copy their slice ends
+__global__ __launch_bounds__(256) void k_copy_done(const double* Zsrc, double* Zdst,
+                                                   const int32_t* done, long per) {
+  const int b = blockIdx.x;
+  if (!done[b]) return;
+  for (long e = threadIdx.x; e < per; e += 256) Zdst[b * per + e] = Zsrc[b * per + e];
+}
+
+hipError_t launch_copy_done(const double* Zsrc, double* Zdst, const int32_t* done, int B, long per,
+                            hipStream_t s) {
+  k_copy_done<<<B, 256, 0, s>>>(Zsrc, Zdst, done, per);
+  return hipGetLastError();
+}
+
+__global__ void k_finish_status(const int32_t* done, const int32_t* conv, int32_t* out, int B,
+                                int sweeps, int notconv) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  out[b] = done[b] ? conv[b] : (notconv ? (int32_t)L1PR_ENOTCONV : sweeps);
+}
+
+hipError_t launch_finish_status(const int32_t* done, const int32_t* conv, int32_t* out, int B,
+                                int sweeps, bool notconv, hipStream_t s) {
+  k_finish_status<<<(B + 255) / 256, 256, 0, s>>>(done, conv, out, B, sweeps, notconv ? 1 : 0);
+  return hipGetLastError();
+}
+
+__global__ void k_check_finite(const double* x, long n, int* flag) {
+  int bad = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) atomicOr(flag, FLAG_NONFINITE);
+}
+
+hipError_t launch_check_finite(const double* x, long n, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long blocks = (n + 255) / 256;
+  k_check_finite<<<(unsigned)(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(x, n, flag);
   return hipGetLastError();
 }
 

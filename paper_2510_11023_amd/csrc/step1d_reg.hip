@@ -370,6 +370,8 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   const double* ins = tb.inst + (long)b * NSCAL;
   // past the instance's last fine step of the slice (uneven batches): nothing to do
   if (a.mode == MODE_FINE && a.r > (int)ins[IS_SB]) return;
+  // a finished parareal instance keeps its slice ends: nothing to factor or store
+  if (unit_done(a, u)) return;
   // the instance's own modes: entries k >= Mb are identity rows with zero right-hand side
   const int Mb = (int)ins[IS_MB];
   const double tau = ins[(a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU];
@@ -428,16 +430,20 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
   // subtracts L_jK^T x_j from z_K for K = j-1, j-2, ..., 0.  Each of those subtractions first
   // waits for its turn on block K (tok[K] == nt-1-j), so the parts reach z_K in a fixed order
   // (rows from the last down) whatever the timing.  A row only waits on higher rows, and each
-  // wave takes its higher row first, so every wait ends (the spins are bounded all the same).
+  // wave takes its higher row first, so every wait ends.  The spins are bounded all the same:
+  // a wait that gives up sets FLAG_WAIT in the call's status word (the unit's result is then
+  // invalid and the call reports L1PR_EWAIT), and the kernel still runs to its end.
   {
     const int ra = wave, rb = nt - 1 - wave;
 #define L1PR_WAIT_TOKEN(K, WANT)                                                              \
   if (lane == 0) {                                                                             \
-    for (int it = 0; it < (1 << 18); ++it) {                                                   \
+    int it = 0;                                                                                \
+    for (; it < tb.spin; ++it) {                                                               \
       if (__hip_atomic_load(&tok[(K)], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= (WANT)) \
         break;                                                                                 \
       __builtin_amdgcn_s_sleep(1);                                                             \
     }                                                                                          \
+    if (it >= tb.spin && tb.flag) atomicOr(tb.flag, FLAG_WAIT);                                \
   }                                                                                            \
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll

@@ -106,6 +106,10 @@ class PararealResult:
     status: int
     incr: torch.Tensor | None
     iterates: torch.Tensor | None
+    # per-instance status on the device: sweeps after which each instance was finished (or
+    # that it ran), or a negative status (ENOTCONV, ENONFINITE)
+    inst: torch.Tensor | None = None
+    workspace: torch.Tensor | None = None
 
 
 COARSE_L1 = 0
@@ -150,9 +154,12 @@ def fine_apply(p: Problem, Z: torch.Tensor, alpha=None, workspace=None) -> torch
 def solve_parareal(p: Problem, u0: torch.Tensor, max_iter: int, tol: float = 0.0, alpha=None,
                    want_iterates: bool = False, want_incr: bool = True,
                    workspace: torch.Tensor | None = None, allow_notconv: bool = True,
-                   coarse: int = COARSE_L1, mlp_params: torch.Tensor | None = None):
+                   coarse: int = COARSE_L1, mlp_params: torch.Tensor | None = None,
+                   want_status: bool = True):
     """Parareal solve.  Returns a PararealResult; iterates is [iters+1, B, P+1, Md].
-    coarse = COARSE_LEARNED uses the residual network in mlp_params (LearnedCoarse.params)."""
+    tol > 0 stops each instance at its own first sweep whose increment is <= tol (the others
+    go on); coarse = COARSE_LEARNED uses the residual network in mlp_params
+    (LearnedCoarse.params)."""
     _check_u0(p, u0)
     B = u0.shape[0]
     Md = nmodes(p)
@@ -161,21 +168,29 @@ def solve_parareal(p: Problem, u0: torch.Tensor, max_iter: int, tol: float = 0.0
     its = torch.empty((max_iter + 1, B, p.slices + 1, Md), dtype=torch.float64, device=dev) \
         if want_iterates else None
     incr = torch.zeros((B, max(max_iter, 1)), dtype=torch.float64, device=dev) if want_incr else None
+    inst = torch.empty(B, dtype=torch.int32, device=dev) if want_status else None
     if workspace is None:
         workspace = parareal_workspace(p, B, dev, learned=(coarse == COARSE_LEARNED))
     n = workspace.numel() * workspace.element_size()
     keep, aptr = _alpha_arg(alpha, B)
     it = ctypes.c_int32(0)
-    st = _lib.lib().l1pr_solve_parareal_ex(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U),
-                                           int(max_iter), float(tol), int(coarse), _ptr(mlp_params),
-                                           _ptr(its), _ptr(incr), ctypes.byref(it),
-                                           _ptr(workspace), n, _stream())
+    st = _lib.lib().l1pr_solve_parareal(ctypes.byref(p), B, aptr, _ptr(u0), _ptr(U),
+                                        int(max_iter), float(tol), int(coarse), _ptr(mlp_params),
+                                        _ptr(inst), _ptr(incr), _ptr(its), ctypes.byref(it),
+                                        _ptr(workspace), n, _stream())
     if st != _lib.OK and not (allow_notconv and st == _lib.ENOTCONV):
         raise _lib.L1prError(st, "l1pr_solve_parareal")
     k = it.value
     return PararealResult(U=U, iters=k, status=st,
                           incr=None if incr is None else incr[:, :k],
-                          iterates=None if its is None else its[: k + 1])
+                          iterates=None if its is None else its[: k + 1], inst=inst,
+                          workspace=workspace)
+
+
+def check(workspace: torch.Tensor) -> int:
+    """Device status word of the last call on `workspace` (l1pr_check): OK, ENONFINITE or
+    EWAIT; waits for the current stream."""
+    return int(_lib.lib().l1pr_check(_ptr(workspace), _stream()))
 
 
 # ---------------------------------------------------------------- uneven batches

@@ -73,13 +73,19 @@ def test_host_entry_points(L):
     assert L.l1pr_validate(ctypes.byref(bad)) == -1
     assert L.l1pr_workspace_bytes(ctypes.byref(bad), 32, 1) == 0
     assert L.l1pr_workspace_bytes(ctypes.byref(p), 0, 1) == 0
-    for s in (0, -1, -2, -3, -4, -5, -6):
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.l1pr_status_string(s)
     # invalid problems are rejected before any device work
     u = ctypes.c_void_p(1)
     assert L.l1pr_solve_serial(ctypes.byref(bad), 1, None, u, u, None, u, 1 << 30, None) == -1
-    assert L.l1pr_solve_parareal(ctypes.byref(p), 1, None, u, u, 65, 0.0, None, None, None, u,
-                                 1 << 30, None) == -1
+    assert L.l1pr_solve_parareal(ctypes.byref(p), 1, None, u, u, 65, 0.0, 0, None, None, None,
+                                 None, None, u, 1 << 30, None) == -1
+    # unknown coarse propagator; learned coarse step without a network
+    assert L.l1pr_solve_parareal(ctypes.byref(p), 1, None, u, u, 2, 0.0, 2, None, None, None,
+                                 None, None, u, 1 << 30, None) == -1
+    assert L.l1pr_solve_parareal(ctypes.byref(p), 1, None, u, u, 2, 0.0, 1, None, None, None,
+                                 None, None, u, 1 << 30, None) == -1
+    assert L.l1pr_check(None, None) == -1
 
 
 def test_full_history_parareal_workspace_and_limits(L):
@@ -95,8 +101,8 @@ def test_full_history_parareal_workspace_and_limits(L):
     assert extra <= full - hyb <= extra + B * (120 + 130) * 8 + 3 * 256
     u = ctypes.c_void_p(256)
     ph = make_problem(**W.with_(kw, history=1))
-    assert L.l1pr_solve_parareal_ex(ctypes.byref(ph), B, None, u, u, 2, 0.0, 1, u, None, None,
-                                    None, u, 1 << 30, None) == -1
+    assert L.l1pr_solve_parareal(ctypes.byref(ph), B, None, u, u, 2, 0.0, 1, u, None, None,
+                                 None, None, u, 1 << 30, None) == -1
 
 
 def test_product_path_has_no_cpu_fallback():
