@@ -262,11 +262,22 @@ l1pr_status l1pr_check(const void* ws, void* stream);
  *   spp   : instance b's own fine steps per slice S_b, 1 <= S_b <= p->steps / p->slices; its
  *           fine grid has P S_b steps (dt = T / (P S_b)).
  *   alpha : instance b's order (else p->alpha).
- * Entries outside the ranges are clamped into them. */
+ * Entries outside the ranges are clamped into them.
+ * The coarse propagator of l1pr_solve_parareal_uneven:
+ *   coarse    : L1PR_COARSE_L1, or L1PR_COARSE_LEARNED with
+ *   mlp       : device blob of a network for mlp_modes modes (layout from l1pr_mlp_layout,
+ *               256-byte aligned), p->modes <= mlp_modes <= 256: one network serves every
+ *               instance; the coefficients an instance does not carry (k >= M_b) enter it as
+ *               zeros and only its outputs for k < M_b are used.  A unit whose correction is
+ *               not finite or larger than ||G_n|| + 1 keeps the plain G_n (the fallback).
+ *               ws_bytes must also cover l1pr_parareal_learned_extra_bytes(p, batch). */
 typedef struct {
   const int32_t* modes;
   const int32_t* spp;
   const double* alpha;
+  int32_t coarse;
+  const void* mlp;
+  int32_t mlp_modes;
 } l1pr_uneven;
 
 /* Serial (hybrid) solve of an uneven batch; the other arguments as in l1pr_solve_serial.
@@ -276,11 +287,14 @@ l1pr_status l1pr_solve_serial_uneven(const l1pr_problem* p, int32_t batch,
                                      const l1pr_uneven* desc, const double* u0, double* U,
                                      void* ws, size_t ws_bytes, void* stream);
 
-/* Parareal over an uneven batch with a fixed number of sweeps and no host synchronisation
- * (the whole call can be captured into a HIP graph): the same algorithm as
- * l1pr_solve_parareal with tol = 0.  Convergence is recorded on the device:
+/* Parareal over an uneven batch with at most `sweeps` sweeps and no host synchronisation
+ * (the whole call can be captured into a HIP graph): the algorithm of l1pr_solve_parareal,
+ * with the per-instance stop test on conv_tol: an instance whose increment is <= conv_tol is
+ * finished at that sweep (later sweeps keep its slice ends and skip its units); the others
+ * run `sweeps` sweeps.  The coarse propagator is desc->coarse (plain or learned).
  *   conv   : device int32 [batch] or NULL: the first sweep k (1-based) whose increment
- *            max-relative ||U^k - U^(k-1)|| / ||U^k|| is <= conv_tol, -1 if none;
+ *            relative ||U^k - U^(k-1)|| / ||U^k|| is <= conv_tol (the instance's finishing
+ *            sweep), -1 if none, L1PR_ENONFINITE if its increment was not finite;
  *   stamps : device int64 [sweeps + 1] or NULL: the device wall clock (constant rate, see
  *            hipDeviceAttributeWallClockRate) at the end of the initial coarse sweep and of
  *            each sweep;
@@ -299,8 +313,12 @@ l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
  *    batch (each with its own modes, fine steps per slice steps/slices and order);
  *  - every other problem is grouped with the problems equal to it up to alpha.
  * Each problem's result equals its own l1pr_solve_serial / l1pr_solve_parareal run bit for bit.
- *   op     : L1PR_OP_SERIAL (the serial solutions) or L1PR_OP_PARAREAL (min(sweeps, P_i) plain
+ *   op     : L1PR_OP_SERIAL (the serial solutions) or L1PR_OP_PARAREAL (min(sweeps, P_i)
  *            parareal sweeps, no tolerance test, no host synchronisation per sweep)
+ *   coarse, mlp_params, mlp_modes : parareal's coarse propagator for every group
+ *            (L1PR_COARSE_LEARNED: one network of mlp_modes modes for all problems, each
+ *            1D with history 0 and modes <= mlp_modes, zero-padded as in l1pr_uneven;
+ *            EINVAL otherwise); ignored for L1PR_OP_SERIAL
  *   u0     : device; problem i's initial coefficients at u0 + u0_off[i] (Md_i values)
  *   U      : device; problem i's slice ends at U + U_off[i] ((P_i + 1) x Md_i values, row-major)
  *   u0_off, U_off : host int64 [count], offsets in doubles
@@ -311,6 +329,7 @@ l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
  * graph capture (the uneven entry points above are). */
 size_t      l1pr_batch_workspace_bytes(const l1pr_problem* probs, int32_t count, int32_t op);
 l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t op, int32_t sweeps,
+                             int32_t coarse, const void* mlp_params, int32_t mlp_modes,
                              const double* u0, const int64_t* u0_off, double* U,
                              const int64_t* U_off, void* ws, size_t ws_bytes, void* stream);
 

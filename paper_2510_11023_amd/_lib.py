@@ -41,9 +41,10 @@ class Problem(ctypes.Structure):
 
 
 class Uneven(ctypes.Structure):
-    """Mirror of l1pr_uneven (device pointers)."""
+    """Mirror of l1pr_uneven (device pointers, the coarse propagator and its network)."""
 
-    _fields_ = [("modes", ctypes.c_void_p), ("spp", ctypes.c_void_p), ("alpha", ctypes.c_void_p)]
+    _fields_ = [("modes", ctypes.c_void_p), ("spp", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("coarse", ctypes.c_int32), ("mlp", ctypes.c_void_p), ("mlp_modes", ctypes.c_int32)]
 
 
 class KernelStat(ctypes.Structure):
@@ -133,7 +134,8 @@ def lib():
         L.l1pr_batch_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32]
         L.l1pr_batch_workspace_bytes.restype = ctypes.c_size_t
         L.l1pr_solve_batch.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32,
-                                       ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64), vp,
+                                       ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32, vp,
+                                       ctypes.POINTER(ctypes.c_int64), vp,
                                        ctypes.POINTER(ctypes.c_int64), vp, ctypes.c_size_t, vp]
         L.l1pr_solve_batch.restype = ctypes.c_int
         L.l1pr_device_stamp.argtypes = [vp, vp]

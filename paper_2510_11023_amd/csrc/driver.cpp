@@ -564,9 +564,25 @@ struct Learned {
   void* ws = nullptr;
 };
 
+// Scratch of the learned coarse step: the plain G values and the inference activations of a
+// network of up to kMlpMaxModes modes (a network may cover more modes than the batch).
 size_t learned_extra_bytes(const Tables& tb) {
-  const MlpLayout L = mlp_layout(tb.M);
+  const MlpLayout L = mlp_layout(kMlpMaxModes);
   return (sizeof(double) * (size_t)tb.B * tb.Mp + 255) / 256 * 256 + mlp_infer_ws_bytes(L, tb.B);
+}
+
+// The learned coarse step of a parareal call: network `params` for `mnet` >= M modes (1D,
+// history 0), scratch after the solver's workspace.
+l1pr_status make_learned(const Ctx& c, const void* params, int mnet, size_t ws_bytes, Learned& lg) {
+  if (!params || ((uintptr_t)params & 255) || c.tb.dim != 1 || c.full || mnet < c.tb.M ||
+      mnet > kMlpMaxModes)
+    return L1PR_EINVAL;
+  if (ws_bytes < c.L.total + learned_extra_bytes(c.tb)) return L1PR_ENOMEM;
+  lg.params = params;
+  lg.L = mlp_layout(mnet);
+  lg.G = c.ptr(c.L.total);
+  lg.ws = c.ws + c.L.total + (sizeof(double) * (size_t)c.tb.B * c.tb.Mp + 255) / 256 * 256;
+  return L1PR_OK;
 }
 
 // One coarse step G_n over all instances; `e` decides what is stored.  With a learned
@@ -777,6 +793,31 @@ l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, d
   return L1PR_OK;
 }
 
+// l1pr_solve_parareal with a network of mnet >= M modes (0: M)
+l1pr_status solve_parareal_net(const l1pr_problem* p, int32_t batch, const double* alpha,
+                               const double* u0, double* U, int32_t max_iter, double tol,
+                               int32_t coarse, const void* mlp_params, int32_t mnet, int32_t* iters,
+                               double* incr, double* U_iters, int32_t* sweeps, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!u0 || !U || !p) return L1PR_EINVAL;
+  if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
+  if (coarse != L1PR_COARSE_L1 && coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
+  const bool learned = coarse == L1PR_COARSE_LEARNED;
+  if (learned && (!mlp_params || p->dim != 1 || p->modes > kMlpMaxModes || p->history != 0))
+    return L1PR_EINVAL;
+  Ctx c;
+  l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
+  if (st != L1PR_OK) return st;
+  Learned lg;
+  if (learned) {
+    st = make_learned(c, mlp_params, mnet > 0 ? mnet : c.tb.M, ws_bytes, lg);
+    if (st != L1PR_OK) return st;
+  }
+  int it = 0;
+  st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it, iters, learned ? &lg : nullptr);
+  if (sweeps) *sweeps = it;
+  return st;
+}
 }  // namespace
 }  // namespace l1pr
 
@@ -814,28 +855,8 @@ l1pr_status l1pr_solve_parareal(const l1pr_problem* p, int32_t batch, const doub
                                 double* incr, double* U_iters, int32_t* sweeps, void* ws,
                                 size_t ws_bytes, void* stream) {
   try {
-    if (!u0 || !U || !p) return L1PR_EINVAL;
-    if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
-    if (coarse != L1PR_COARSE_L1 && coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
-    const bool learned = coarse == L1PR_COARSE_LEARNED;
-    if (learned && (!mlp_params || ((uintptr_t)mlp_params & 255) || p->dim != 1 ||
-                    p->modes > kMlpMaxModes || p->history != 0))
-      return L1PR_EINVAL;
-    Ctx c;
-    l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, alpha, ws, ws_bytes, stream, c);
-    if (st != L1PR_OK) return st;
-    Learned lg;
-    if (learned) {
-      if (ws_bytes < c.L.total + learned_extra_bytes(c.tb)) return L1PR_ENOMEM;
-      lg.params = mlp_params;
-      lg.L = mlp_layout(c.tb.M);
-      lg.G = c.ptr(c.L.total);
-      lg.ws = c.ws + c.L.total + (sizeof(double) * (size_t)c.tb.B * c.tb.Mp + 255) / 256 * 256;
-    }
-    int it = 0;
-    st = parareal(c, u0, U, max_iter, tol, U_iters, incr, &it, iters, learned ? &lg : nullptr);
-    if (sweeps) *sweeps = it;
-    return st;
+    return solve_parareal_net(p, batch, alpha, u0, U, max_iter, tol, coarse, mlp_params, 0, iters,
+                              incr, U_iters, sweeps, ws, ws_bytes, stream);
   } catch (...) {
     return L1PR_EHIP;
   }
@@ -878,13 +899,20 @@ l1pr_status l1pr_solve_parareal_uneven(const l1pr_problem* p, int32_t batch,
     l1pr_status st = setup(p, batch, L1PR_OP_PARAREAL, nullptr, ws, ws_bytes, stream, c, un);
     if (st != L1PR_OK) return st;
     if (!c.reg) return L1PR_EINVAL;
+    if (desc->coarse != L1PR_COARSE_L1 && desc->coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
+    Learned lg;
+    if (desc->coarse == L1PR_COARSE_LEARNED) {
+      st = make_learned(c, desc->mlp, desc->mlp_modes, ws_bytes, lg);
+      if (st != L1PR_OK) return st;
+    }
     Track tr;
     tr.uneven = true;
     tr.conv = conv;
     tr.conv_tol = conv_tol;
     tr.stamps = stamps;
     int it = 0;
-    return parareal(c, u0, U, sweeps, 0.0, nullptr, incr, &it, nullptr, nullptr, tr);
+    return parareal(c, u0, U, sweeps, 0.0, nullptr, incr, &it, nullptr,
+                    desc->coarse == L1PR_COARSE_LEARNED ? &lg : nullptr, tr);
   } catch (...) {
     return L1PR_EHIP;
   }
@@ -1212,7 +1240,8 @@ struct GroupWs {
 GroupWs group_ws(const BatchGroup& G, int op) {
   const int B = (int)G.members.size(), Md = batch_md(G.p);
   GroupWs w;
-  w.solver = al256(l1pr_workspace_bytes(&G.p, B, op));
+  w.solver = al256(l1pr_workspace_bytes(&G.p, B, op) +
+                   (op == L1PR_OP_PARAREAL ? l1pr_parareal_learned_extra_bytes(&G.p, B) : 0));
   w.u0p = w.solver;
   w.Up = w.u0p + al256(sizeof(double) * (size_t)B * Md);
   w.modes = w.Up + al256(sizeof(double) * (size_t)B * (G.p.slices + 1) * Md);
@@ -1236,11 +1265,19 @@ size_t l1pr_batch_workspace_bytes(const l1pr_problem* probs, int32_t count, int3
 }
 
 l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t op, int32_t sweeps,
+                             int32_t coarse, const void* mlp_params, int32_t mlp_modes,
                              const double* u0, const int64_t* u0_off, double* U,
                              const int64_t* U_off, void* ws, size_t ws_bytes, void* stream) {
   try {
     if (!probs || count < 0 || (op != L1PR_OP_SERIAL && op != L1PR_OP_PARAREAL) || sweeps < 0)
       return L1PR_EINVAL;
+    const bool learned = op == L1PR_OP_PARAREAL && coarse == L1PR_COARSE_LEARNED;
+    if (op == L1PR_OP_PARAREAL && coarse != L1PR_COARSE_L1 && !learned) return L1PR_EINVAL;
+    if (learned) {
+      if (!mlp_params || mlp_modes < 1 || mlp_modes > kMlpMaxModes) return L1PR_EINVAL;
+      for (int i = 0; i < count; ++i)
+        if (probs[i].dim != 1 || probs[i].modes > mlp_modes) return L1PR_EINVAL;
+    }
     if (count == 0) return L1PR_OK;
     if (!u0 || !u0_off || !U || !U_off || !ws) return L1PR_EINVAL;
     for (int i = 0; i < count; ++i)
@@ -1285,7 +1322,8 @@ l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t o
         L1PR_TRY(hipMemcpyAsync(dm, modes.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
         L1PR_TRY(hipMemcpyAsync(ds, spp.data(), sizeof(int32_t) * B, hipMemcpyHostToDevice, s));
         L1PR_TRY(hipMemcpyAsync(da, alpha.data(), sizeof(double) * B, hipMemcpyHostToDevice, s));
-        l1pr_uneven desc{dm, ds, da};
+        l1pr_uneven desc{dm, ds, da, learned ? L1PR_COARSE_LEARNED : L1PR_COARSE_L1,
+                         learned ? mlp_params : nullptr, learned ? mlp_modes : 0};
         st = (op == L1PR_OP_SERIAL)
                  ? l1pr_solve_serial_uneven(&G.p, B, &desc, u0p, Up, base, w.solver, stream)
                  : l1pr_solve_parareal_uneven(&G.p, B, &desc, u0p, Up, k, 0.0, nullptr, nullptr,
@@ -1293,9 +1331,10 @@ l1pr_status l1pr_solve_batch(const l1pr_problem* probs, int32_t count, int32_t o
       } else {
         st = (op == L1PR_OP_SERIAL)
                  ? l1pr_solve_serial(&G.p, B, alpha.data(), u0p, Up, nullptr, base, w.solver, stream)
-                 : l1pr_solve_parareal(&G.p, B, alpha.data(), u0p, Up, k, 0.0, L1PR_COARSE_L1,
-                                       nullptr, nullptr, nullptr, nullptr, nullptr, base, w.solver,
-                                       stream);
+                 : solve_parareal_net(&G.p, B, alpha.data(), u0p, Up, k, 0.0,
+                                      learned ? L1PR_COARSE_LEARNED : L1PR_COARSE_L1,
+                                      learned ? mlp_params : nullptr, learned ? mlp_modes : 0,
+                                      nullptr, nullptr, nullptr, nullptr, base, w.solver, stream);
       }
       if (st != L1PR_OK) return st;
       // scatter each member's slice ends (its own Md columns of every row)

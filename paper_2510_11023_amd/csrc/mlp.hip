@@ -431,17 +431,20 @@ __global__ void k_features(const double* Z, const double* G, const double* alpha
   if (c < M) t[s * M + c] = (float)(Z[((long)b * (P + 1) + n + 1) * Mz + c] - g[c]);
 }
 
-// Inference input: x = normalise([G_L1 ; alpha_b ; n/P]) in FP64 for B rows
+// Inference input: x = normalise([G_L1 ; alpha_b ; n/P]) in FP64 for B rows.  The network
+// has Mn >= M mode inputs: coefficients of modes the batch does not carry (k >= M) enter as
+// zeros, as do the modes above an uneven instance's own count (its G is exactly zero there).
 __global__ void k_infer_input(const double* G, long gstride, const double* inst, int B, int M,
-                              int n, int P, const float* mean, const float* sd, double* X0, int ldo) {
+                              int Mn, int n, int P, const float* mean, const float* sd, double* X0,
+                              int ldo) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)B * ldo) return;
   const int b = (int)(e / ldo), c = (int)(e % ldo);
   double v = 0.0;
   if (c < M) v = G[b * gstride + c];
-  else if (c == M) v = inst[(long)b * NSCAL + IS_ALPHA];
-  else if (c == M + 1) v = (double)n / (double)P;
-  X0[e] = c < M + 2 ? (v - (double)mean[c]) / (double)sd[c] : 0.0;
+  else if (c == Mn) v = inst[(long)b * NSCAL + IS_ALPHA];
+  else if (c == Mn + 1) v = (double)n / (double)P;
+  X0[e] = c < Mn + 2 ? (v - (double)mean[c]) / (double)sd[c] : 0.0;
 }
 
 __global__ void k_norm_f64(const double* x, int ldx, int ncols, int n, const float* mean,
@@ -452,14 +455,20 @@ __global__ void k_norm_f64(const double* x, int ldx, int ncols, int n, const flo
   X0[e] = (c < ncols) ? (x[(long)i * ldx + c] - (double)mean[c]) / (double)sd[c] : 0.0;
 }
 
-// G_L = G_L1 + (O * out_std + out_mean); falls back to G_L1 for a unit whose correction is
-// not finite or larger than ||G_L1|| + 1.  Then the step epilogue.  One work-group per unit.
+// G_L = G_L1 + (O * out_std + out_mean) on the unit's own modes (k < M_b, the instance's
+// count; the network's outputs for other modes are not used); falls back to G_L1 for a unit
+// whose correction is not finite or larger than ||G_L1|| + 1.  Then the step epilogue.  One
+// work-group per unit.
 __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstride, const double* O,
                                                      int outp, int M, int Mp, const float* om,
                                                      const float* osd, Epilogue ep,
-                                                     const int32_t* done) {
+                                                     const int32_t* done, const double* inst) {
   const int u = blockIdx.x;
   if (done && done[u]) return;  // a finished parareal instance keeps its slice ends
+  {
+    const int mb = (int)inst[(long)u * NSCAL + IS_MB];
+    M = mb < M ? mb : M;
+  }
   __shared__ double rc[256], rg[256];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -628,15 +637,16 @@ hipError_t mlp_forward_ws(const MlpLayout& L, const char* params, int n, MlpWs& 
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,
                             const Epilogue& ep, void* ws, hipStream_t s, const int32_t* done) {
+  if (M > L.out) return hipErrorInvalidValue;  // the network covers at least the batch's modes
   const char* pp = (const char*)params;
   const InferWs W = carve_infer(L, B, ws);
-  k_infer_input<<<nblk((long)B * L.inp), 256, 0, s>>>(G, gstride, inst, B, M, n, P,
+  k_infer_input<<<nblk((long)B * L.inp), 256, 0, s>>>(G, gstride, inst, B, M, L.out, n, P,
                                                        (const float*)(pp + L.in_mean),
                                                        (const float*)(pp + L.in_std), W.X, L.inp);
   hipError_t r = mlp_forward_f64(L, pp, B, W.X, W.Ha, W.Hb, W.O, s);
   if (r != hipSuccess) return r;
   k_infer_apply<<<B, 256, 0, s>>>(G, gstride, W.O, L.outp, M, Mp, (const float*)(pp + L.out_mean),
-                                  (const float*)(pp + L.out_std), ep, done);
+                                  (const float*)(pp + L.out_std), ep, done, inst);
   return hipGetLastError();
 }
 

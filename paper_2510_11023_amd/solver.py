@@ -195,7 +195,7 @@ def check(workspace: torch.Tensor) -> int:
 
 # ---------------------------------------------------------------- uneven batches
 
-def _uneven(modes, spp, alpha):
+def _uneven(modes, spp, alpha, coarse=COARSE_L1, mlp_params=None, mlp_modes=0):
     """Descriptor and the device tensors it points to (kept alive by the caller)."""
     keep = []
 
@@ -207,7 +207,8 @@ def _uneven(modes, spp, alpha):
         keep.append(t)
         return ctypes.c_void_p(t.data_ptr())
 
-    d = _lib.Uneven(dev(modes, torch.int32), dev(spp, torch.int32), dev(alpha, torch.float64))
+    d = _lib.Uneven(dev(modes, torch.int32), dev(spp, torch.int32), dev(alpha, torch.float64),
+                    int(coarse), _ptr(mlp_params), int(mlp_modes))
     return d, keep
 
 
@@ -228,21 +229,29 @@ def solve_serial_uneven(p: Problem, u0: torch.Tensor, modes=None, spp=None, alph
     return U
 
 
+def uneven_workspace(p: Problem, batch: int, device, learned: bool = False) -> torch.Tensor:
+    return parareal_workspace(p, batch, device, learned=learned)
+
+
 def solve_parareal_uneven(p: Problem, u0: torch.Tensor, sweeps: int, modes=None, spp=None,
                           alpha=None, conv_tol: float = 0.0, workspace=None, out=None,
-                          conv=None, stamps=None, incr=None):
-    """Parareal over an uneven batch with `sweeps` sweeps and no host synchronisation.
-    Returns (U, conv, stamps): conv[b] = first sweep whose increment is <= conv_tol (-1 if
-    none), stamps[k] = device wall clock at the end of sweep k (k = 0: initial coarse sweep)."""
+                          conv=None, stamps=None, incr=None, coarse: int = COARSE_L1,
+                          mlp_params=None, mlp_modes: int = 0):
+    """Parareal over an uneven batch with at most `sweeps` sweeps and no host synchronisation;
+    an instance is finished at its first sweep whose increment is <= conv_tol.  Returns
+    (U, conv, stamps): conv[b] = that sweep (-1 if none), stamps[k] = device wall clock at
+    the end of sweep k (k = 0: initial coarse sweep).  coarse = COARSE_LEARNED uses the
+    network mlp_params of mlp_modes >= p.modes modes for every instance."""
     _check_u0(p, u0)
     B = u0.shape[0]
     dev = u0.device
-    ws = workspace if workspace is not None else _workspace(p, B, _lib.OP_PARAREAL, dev)[0]
+    learned = coarse == COARSE_LEARNED
+    ws = workspace if workspace is not None else uneven_workspace(p, B, dev, learned=learned)
     U = out if out is not None else torch.empty((B, p.slices + 1, nmodes(p)), dtype=torch.float64,
                                                 device=dev)
     conv = conv if conv is not None else torch.empty(B, dtype=torch.int32, device=dev)
     stamps = stamps if stamps is not None else torch.zeros(sweeps + 1, dtype=torch.int64, device=dev)
-    d, keep = _uneven(modes, spp, alpha)
+    d, keep = _uneven(modes, spp, alpha, coarse, mlp_params, mlp_modes)
     st = _lib.lib().l1pr_solve_parareal_uneven(ctypes.byref(p), B, ctypes.byref(d), _ptr(u0),
                                                _ptr(U), sweeps, float(conv_tol), _ptr(conv),
                                                _ptr(stamps), _ptr(incr), _ptr(ws), ws.numel(),
@@ -264,7 +273,8 @@ def autotune(p: Problem, batch: int, workspace=None) -> int:
     return int(out.value)
 
 
-def solve_batch(problems, u0s, parareal_sweeps: int | None = None, workspace=None):
+def solve_batch(problems, u0s, parareal_sweeps: int | None = None, workspace=None,
+                coarse: int = COARSE_L1, mlp_params=None, mlp_modes: int = 0):
     """Heterogeneous batch: problems[i] (each with its own parameters and alpha) from u0s[i]
     (device float64 [Md_i]).  Serial solutions, or parareal_sweeps plain parareal sweeps.
     Returns a list of slice-end tensors [P_i + 1, Md_i] (views of one output buffer)."""
@@ -288,7 +298,8 @@ def solve_batch(problems, u0s, parareal_sweeps: int | None = None, workspace=Non
         raise _lib.L1prError(_lib.EINVAL, "l1pr_batch_workspace_bytes")
     ws = workspace if workspace is not None else torch.empty(nb, dtype=torch.uint8, device=dev)
     i64 = ctypes.POINTER(ctypes.c_int64)
-    st = _lib.lib().l1pr_solve_batch(arr, n, op, int(parareal_sweeps or 0), _ptr(u0),
+    st = _lib.lib().l1pr_solve_batch(arr, n, op, int(parareal_sweeps or 0), int(coarse),
+                                     _ptr(mlp_params), int(mlp_modes), _ptr(u0),
                                      u0_off.ctypes.data_as(i64), _ptr(U), U_off.ctypes.data_as(i64),
                                      _ptr(ws), ws.numel() * ws.element_size(), _stream())
     if st != _lib.OK:

@@ -146,3 +146,85 @@ def test_graph_captured_uneven_parareal_replays(gpu):
         torch.cuda.synchronize()
         assert torch.equal(out, eager), rep
         assert float(junk) == float(junk)
+
+
+# ------------------------------------------------------- learned coarse step, uneven batches
+
+def _net(gpu, modes, seed=3, train_kw=None):
+    """A residual network for `modes` modes: statistics and one epoch on the plain coarse/fine
+    pairs of a uniform problem (its quality does not matter here, only that it corrects)."""
+    from paper_2510_11023_amd.learned import LearnedCoarse, training_data
+
+    model = LearnedCoarse(modes, seed=seed)
+    kw = dict(BASE, modes=modes, quad=2 * modes)
+    if train_kw:
+        kw.update(train_kw)
+    pg = gpu.make_problem(**kw)
+    u0 = torch.tensor(W.u0_batch_1d(modes, range(16)), device="cuda")
+    x, t = training_data(pg, u0, list(W.alphas_uniform(16, seed=seed)), model)
+    model.set_stats(x, t)
+    model.train(x, t, epochs=1, batch=64, lr=1e-3, seed=1)
+    return model
+
+
+def test_learned_uneven_exact_and_equals_own_runs(gpu):
+    p = gpu.make_problem(**BASE)
+    u0 = torch.tensor(u0_for(BASE["modes"], MODES), device="cuda")
+    model = _net(gpu, BASE["modes"])
+    L = dict(coarse=gpu.COARSE_LEARNED, mlp_params=model.params, mlp_modes=BASE["modes"])
+    Us = gpu.solve_serial_uneven(p, u0, MODES, SPP, ALPHA)
+    plain0, _, _ = gpu.solve_parareal_uneven(p, u0, 0, MODES, SPP, ALPHA)
+    for k in (0, 1, 3, BASE["slices"]):
+        U, conv, _ = gpu.solve_parareal_uneven(p, u0, k, MODES, SPP, ALPHA, **L)
+        assert torch.equal(U[:, : k + 1], Us[:, : k + 1]), k
+        if k == 0:
+            assert not torch.equal(U, plain0)  # the correction is applied
+        # instances with the group's own mode count reproduce their own learned runs
+        for b in (0, 4):
+            pb, _ = own_problem(gpu, b)
+            r = gpu.solve_parareal(pb, u0[b:b + 1, :MODES[b]].contiguous(), k, tol=0.0,
+                                   coarse=gpu.COARSE_LEARNED, mlp_params=model.params)
+            assert torch.equal(U[b, :, :MODES[b]], r.U[0]), (k, b)
+        # coefficients above an instance's own modes stay exactly zero
+        for b in range(len(MODES)):
+            assert not torch.any(U[b, :, MODES[b]:]), (k, b)
+
+
+def test_learned_uneven_falls_back_to_plain(gpu):
+    """A network with a non-finite output: every unit keeps the plain coarse value, bit for bit."""
+    from paper_2510_11023_amd.learned import LearnedCoarse
+
+    p = gpu.make_problem(**BASE)
+    u0 = torch.tensor(u0_for(BASE["modes"], MODES), device="cuda")
+    model = LearnedCoarse(BASE["modes"], seed=2)
+    bad = model.masters()
+    bad[model.info.flat_b[3]] = np.nan
+    model.set_masters(bad)
+    a, ca, _ = gpu.solve_parareal_uneven(p, u0, 3, MODES, SPP, ALPHA, conv_tol=1e-9,
+                                         coarse=gpu.COARSE_LEARNED, mlp_params=model.params,
+                                         mlp_modes=BASE["modes"])
+    b, cb, _ = gpu.solve_parareal_uneven(p, u0, 3, MODES, SPP, ALPHA, conv_tol=1e-9)
+    assert torch.equal(a, b) and torch.equal(ca, cb)
+
+
+def test_learned_network_wider_than_the_batch(gpu):
+    """One network of 64 modes serves a batch of at most 48 (zero-padded inputs): the uneven
+    call stays exact, and the batch call running the same network over one of its problems
+    gives that instance's result bit for bit."""
+    p = gpu.make_problem(**BASE)
+    u0 = torch.tensor(u0_for(BASE["modes"], MODES), device="cuda")
+    model = _net(gpu, 64, seed=4)
+    L = dict(coarse=gpu.COARSE_LEARNED, mlp_params=model.params, mlp_modes=64)
+    Us = gpu.solve_serial_uneven(p, u0, MODES, SPP, ALPHA)
+    U, _, _ = gpu.solve_parareal_uneven(p, u0, 2, MODES, SPP, ALPHA, **L)
+    assert torch.equal(U[:, :3], Us[:, :3])
+    b = 1
+    kw = dict(BASE, modes=MODES[b], steps=BASE["slices"] * SPP[b], alpha=ALPHA[b])
+    out = gpu.solve_batch([gpu.make_problem(**kw)], [u0[b, :MODES[b]].contiguous()],
+                          parareal_sweeps=2, **L)
+    assert torch.equal(out[0], U[b, :, :MODES[b]])
+    from paper_2510_11023_amd import _lib
+
+    with pytest.raises(_lib.L1prError):  # a network narrower than the batch's modes
+        gpu.solve_parareal_uneven(p, u0, 1, MODES, SPP, ALPHA, coarse=gpu.COARSE_LEARNED,
+                                  mlp_params=model.params, mlp_modes=32)
