@@ -368,21 +368,33 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
 
   const int b = (a.mode == MODE_FINE) ? u / a.nP : u;
   const double* ins = tb.inst + (long)b * NSCAL;
-  // past the instance's last fine step of the slice (uneven batches): nothing to do
-  if (a.mode == MODE_FINE && a.r > (int)ins[IS_SB]) return;
-  // a finished parareal instance keeps its slice ends: nothing to factor or store
-  if (unit_done(a, u)) return;
-  // the instance's own modes: entries k >= Mb are identity rows with zero right-hand side
-  const int Mb = (int)ins[IS_MB];
+  // every global read of the set-up is issued before any of them is needed
+  const double ins_sb = ins[IS_SB], ins_mb = ins[IS_MB];
   const double tau = ins[(a.mode == MODE_COARSE) ? IS_TAUC : IS_TAU];
-  for (int k = tid; k < Mp; k += RT)
-    sb[k] = (k < Mb) ? hist[(long)u * Mp + k] + tau * F[(long)u * Mp + k] : 0.0;
+  const int fin = a.done ? a.done[b] : 0;
+  const int Jm = 2 * Mp + 1;
+  double hv = 0.0, fv = 0.0, m0 = 0.0, m1 = 0.0;
+  if (tid < Mp) {
+    hv = hist[(long)u * Mp + tid];
+    fv = F[(long)u * Mp + tid];
+  }
+  if (SRC == SRC_MOMENTS) {
+    if (tid < Jm) m0 = mom[(long)u * Jm + tid];
+    if (tid + RT < Jm) m1 = mom[(long)u * Jm + tid + RT];
+  }
+  // past the instance's last fine step of the slice (uneven batches): nothing to do
+  if (a.mode == MODE_FINE && a.r > (int)ins_sb) return;
+  // a finished parareal instance keeps its slice ends: nothing to factor or store
+  if (fin) return;
+  // the instance's own modes: entries k >= Mb are identity rows with zero right-hand side
+  const int Mb = (int)ins_mb;
+  if (tid < Mp) sb[tid] = (tid < Mb) ? hv + tau * fv : 0.0;
 
   // slot (I, K) element v of lane l holds A[16 I + l%16][16 K + l/16 + 4v]
   if (SRC == SRC_MOMENTS) {
-    const int Jm = 2 * Mp + 1;
     double* sm = sP;
-    for (int j = tid; j < Jm; j += RT) sm[j] = mom[(long)u * Jm + j];
+    if (tid < Jm) sm[tid] = m0;
+    if (tid + RT < Jm) sm[tid + RT] = m1;
     __syncthreads();
     const double pi2 = kPi * kPi;
 #pragma unroll
