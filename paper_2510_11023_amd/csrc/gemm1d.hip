@@ -139,9 +139,10 @@ __global__ __launch_bounds__(256) void k_proj_gemm1d(Tables tb, int units, const
     }
 }
 
-// Work-groups (unit, block of 256 coefficients), one thread per coefficient: coalesced rows of
-// the trajectory and of the slice-end sequence, loads issued four rows ahead of the sequential
-// (ascending-i) sum.
+// Full-history steps (MODE_FULL, and MODE_FINE with the previous trajectories): work-groups
+// (unit, block of 256 coefficients), one thread per coefficient, the prefix sum of the earlier
+// rows continued row by row (full_fine_history, full_serial_history).  The hybrid steps below
+// use k_history_split.
 __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double* hist) {
   const int u = blockIdx.x;
   const UnitView v = decode_unit(tb, a, u);
@@ -304,10 +305,100 @@ hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const
   return hipGetLastError();
 }
 
+// Hybrid fine steps and coarse steps: h = y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1}), and for
+// fine steps also - S^-a sum_{c=1}^{n} b_{n-c+r/S} (z_c - z_{c-1}) over the slice ends.  One
+// work-group per (unit, block of 128 coefficients); its four waves take the same coefficients
+// (two adjacent ones per lane, so every row read is a coalesced 1 KiB segment of 16-byte
+// loads) and split the rows of each sum into four contiguous chunks fixed by the row count
+// alone (never by the launch), each an ascending fma chain with eight rows in flight; the
+// chunk partials meet in LDS and are added as (0 + 1) + (2 + 3).  A serial solve and a
+// parareal sweep therefore sum in the same order, bit for bit.  (Measured on the config-2
+// fine sweep against one coefficient per lane: 3.8 -> 4.3 TB/s; eight or sixteen chunks, or
+// four coefficients per lane, were slower.)
+constexpr int HL = 64;       // lanes per wave, two coefficients each
+constexpr int HB = 2 * HL;   // coefficients per work-group
+constexpr int HW = 4;        // waves (row chunks) per work-group
+static_assert(HW == 4, "the chunk partials are added as (0 + 1) + (2 + 3)");
+
+typedef double h2 __attribute__((ext_vector_type(2)));
+
+// sum_{i=i0}^{i1} w(i) (x_i - x_{i-1}) for this lane's two coefficients, rows at x + i stride
+template <class WFn>
+__device__ inline h2 chunk_sum(const double* x, long stride, int i0, int i1, WFn w) {
+  h2 p = {0.0, 0.0};
+  if (i0 > i1) return p;
+  h2 prev = *reinterpret_cast<const h2*>(x + (long)(i0 - 1) * stride);
+  int i = i0;
+  for (; i + 7 <= i1; i += 8) {
+    h2 r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = *reinterpret_cast<const h2*>(x + (long)(i + q) * stride);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double wq = w(i + q);
+      p.x = fma(wq, r[q].x - prev.x, p.x);
+      p.y = fma(wq, r[q].y - prev.y, p.y);
+      prev = r[q];
+    }
+  }
+  for (; i <= i1; ++i) {
+    const h2 xi = *reinterpret_cast<const h2*>(x + (long)i * stride);
+    const double wq = w(i);
+    p.x = fma(wq, xi.x - prev.x, p.x);
+    p.y = fma(wq, xi.y - prev.y, p.y);
+    prev = xi;
+  }
+  return p;
+}
+
+__global__ __launch_bounds__(HL * HW) void k_history_split(Tables tb, StepArgs a, double* hist) {
+  __shared__ h2 red[2][HW][HL];
+  const int u = blockIdx.x, lane = threadIdx.x & (HL - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HL);
+  const UnitView v = decode_unit(tb, a, u);
+  // Mp is a multiple of 16, so a lane's pair is either wholly inside or wholly past it; lanes
+  // past it read coefficients 0 and 1 (in range) and store nothing
+  const int Mp = tb.Mp, k = blockIdx.y * HB + 2 * lane;
+  const bool in = k < Mp;
+  const int kk = in ? k : 0;
+  const double* bw = tb.bw + (long)v.b * tb.LB;
+  {  // trajectory (or slice-end) part: rows 1..L in HW chunks
+    const int L = v.L, len = (L + HW - 1) / HW;
+    const int i0 = 1 + wave * len, i1 = min(L, (wave + 1) * len);
+    red[0][wave][lane] = chunk_sum(v.y + kk, Mp, i0, i1, [&](int i) { return bw[L + 1 - i]; });
+  }
+  const bool fine = a.mode == MODE_FINE;
+  if (fine) {  // coarse-grid history of the hybrid fine step: slice ends 1..n in HW chunks
+    const int nz = v.nz, len = (nz + HW - 1) / HW;
+    const int c0 = 1 + wave * len, c1 = min(nz, (wave + 1) * len);
+    const double* bh = tb.bhyb + (long)v.b * tb.P * tb.S + (a.r - 1);
+    const long S = tb.S;
+    red[1][wave][lane] = chunk_sum(v.z + kk, Mp, c0, c1, [&](int c) { return bh[(long)(nz - c) * S]; });
+  }
+  __syncthreads();
+  if (wave != 0 || !in) return;
+  const h2 acc = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
+  h2 h = *reinterpret_cast<const h2*>(v.y + (long)v.L * Mp + k) - acc;
+  if (fine) {
+    const h2 acc2 = (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
+    const double sf = tb.inst[(long)v.b * NSCAL + IS_SFAC];
+    h.x = h.x - sf * acc2.x;
+    h.y = h.y - sf * acc2.y;
+  }
+  *reinterpret_cast<h2*>(hist + (long)u * Mp + k) = h;
+}
+
 hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
                           hipStream_t s) {
-  const int threads = tb.Mp < 256 ? roundup(tb.Mp, 64) : 256;
-  k_history1d<<<dim3(units, (tb.Mp + threads - 1) / threads), threads, 0, s>>>(tb, a, hist);
+  const bool full = a.mode == MODE_FULL || (a.mode == MODE_FINE && a.prev);
+  if (full) {
+    const int threads = tb.Mp < 256 ? roundup(tb.Mp, 64) : 256;
+    k_history1d<<<dim3(units, (tb.Mp + threads - 1) / threads), threads, 0, s>>>(tb, a, hist);
+  } else {
+    const int nblk = (tb.Mp + HB - 1) / HB;
+    if (nblk > 65535 || tb.Mp % 2 != 0) return hipErrorInvalidValue;
+    k_history_split<<<dim3(units, nblk), HL * HW, 0, s>>>(tb, a, hist);
+  }
   return hipGetLastError();
 }
 
