@@ -71,6 +71,8 @@ def lib():
         L.oracle_coarse_G.argtypes = [pp, ctypes.c_int32, dp, dp]
         L.oracle_fine_F.argtypes = [pp, ctypes.c_int32, dp, dp, dp]
         L.oracle_solve_serial.argtypes = [pp, dp, dp, dp]
+        L.oracle_soe_nodes.argtypes = [ctypes.c_double, ctypes.c_int32, dp, dp, ctypes.c_int32]
+        L.oracle_soe_nodes.restype = ctypes.c_int32
         L.oracle_solve_parareal.argtypes = [pp, dp, dp, ctypes.c_int32, ctypes.c_double, dp, dp,
                                             ctypes.POINTER(ctypes.c_int32)]
         _lib = L
@@ -105,6 +107,19 @@ def validate(p: Problem) -> bool:
 
 def bweight(x: float, alpha: float) -> float:
     return lib().oracle_bweight(float(x), float(alpha))
+
+
+SOE_J0 = 16  # ORACLE_SOE_J0 of oracle.h
+
+
+def soe_nodes(alpha: float, N: int):
+    """(lam, w) of the sum-of-exponentials L1 weights: b_j ~ sum_l w_l exp(-lam_l j) for
+    SOE_J0 <= j <= N (merged node lam = 0 first)."""
+    lam = np.zeros(512)
+    w = np.zeros(512)
+    n = lib().oracle_soe_nodes(float(alpha), int(N), _ptr(lam), _ptr(w), 512)
+    _check(0 if n > 0 else -1, "soe_nodes")
+    return lam[:n].copy(), w[:n].copy()
 
 
 def gauss_legendre01(Q: int):

@@ -46,7 +46,7 @@ int oracle_validate(const oracle_problem* p) {
   if (p->d_sel < -1 || p->d_sel > 4) return -1;
   if (p->d_sel == 0 && !(p->d_param > 0.0)) return -1;
   if (p->f_sel < 0 || p->f_sel > 5) return -1;
-  if (p->history != 0 && p->history != 1) return -1;
+  if (p->history < 0 || p->history > 2) return -1;
   if (p->source_time != 0 && p->source_time != 1) return -1;
   if (p->source_time == 1 && !f_is_u_independent(p->f_sel)) return -1;
   if (p->solver < 0 || p->solver > 2) return -1;
@@ -75,6 +75,30 @@ double oracle_bweight(double x, double alpha) {
   if (x == 0.0) return 1.0;
   double e = 1.0 - alpha;
   return pow(x, e) * expm1(e * log1p(1.0 / x));
+}
+
+/* Sum-of-exponentials weights (see oracle.h): the integral form of b_j, the trapezoid rule
+   in y = log(s) on the grid n h, the slow end merged, the fast end dropped. */
+int32_t oracle_soe_nodes(double alpha, int32_t N, double* lam, double* w, int32_t max_nodes) {
+  if (!(alpha > 0.0 && alpha < 1.0) || N < 1) return -1;
+  const double h = ORACLE_SOE_H, g = tgamma(alpha), c = h * (1.0 - alpha) / g;
+  /* dropped nodes: exp(-lam j0) <= e^-40 once lam >= 40 / j0 */
+  const int n_hi = (int)ceil(log(40.0 / ORACLE_SOE_J0) / h);
+  /* merged nodes n < n_lo: sum_n w_n (1 - exp(-lam_n j)) <= j c sum_n e^{(alpha+1) n h}
+     <= eps b_j for j <= N, with b_j >= (1-alpha) (j+1)^-alpha */
+  const double t = log(ORACLE_SOE_EPS * g * (1.0 - exp(-(alpha + 1.0) * h)) /
+                       (h * (double)N * pow((double)N + 1.0, alpha))) / (alpha + 1.0);
+  const int n_lo = (int)floor(t / h) + 1;
+  const int count = n_hi - n_lo + 2;
+  if (count > max_nodes) return -1;
+  lam[0] = 0.0;
+  w[0] = c * exp(alpha * (double)(n_lo - 1) * h) / (1.0 - exp(-alpha * h));
+  for (int n = n_lo; n <= n_hi; n++) {
+    const double y = (double)n * h, l = exp(y);
+    lam[n - n_lo + 1] = l;
+    w[n - n_lo + 1] = c * exp((alpha - 1.0) * y) * (-expm1(-l));
+  }
+  return count;
 }
 
 /* ---------------------------------------------------------------- quadrature */
@@ -465,7 +489,9 @@ int oracle_fine_F(const oracle_problem* p, int32_t n, const double* C, double* o
 
 /* Serial solve.  history = 0: C_{n+1} = F_n(C_0..C_n), the fine solution that is the
    fixed point of parareal (Section 2.2).  history = 1: the uniform L1 scheme over all
-   N fine steps with full fine history. */
+   N fine steps with full fine history.  history = 2: the same scheme with the history terms
+   at distances >= ORACLE_SOE_J0 from the sum-of-exponentials weights (an approximation,
+   Conclusions (i); at alpha = 1 the far weights vanish and it is history = 1). */
 int oracle_solve_serial(const oracle_problem* p, const double* u0, double* U, double* traj) {
   if (oracle_validate(p)) return -1;
   int Md = nmodes(p), P = p->slices, N = p->steps, S = N / P;
@@ -486,12 +512,43 @@ int oracle_solve_serial(const oracle_problem* p, const double* u0, double* U, do
   double* c = (double*)malloc(sizeof(double) * (size_t)(N + 1) * Md);
   double* hist = (double*)malloc(sizeof(double) * Md);
   memcpy(c, u0, sizeof(double) * Md);
+  /* history = 2: the weights at distances d >= j0 as a sum of exponentials (oracle.h); for
+     each mode the exponential sums V_l = sum_{i <= m+1-j0} exp(-lam_l (m+1-i)) (c_i - c_{i-1})
+     are carried from step to step, V_l <- exp(-lam_l) V_l + exp(-lam_l j0) (c_i - c_{i-1})
+     with i = m+1-j0 the row that has just reached distance j0 */
+  const int soe = p->history == 2 && p->alpha < 1.0;
+  enum { SOE_MAX = 512 };
+  double lam[SOE_MAX], wl[SOE_MAX];
+  int L = 0;
+  double* V = NULL;
+  if (soe) {
+    L = oracle_soe_nodes(p->alpha, N, lam, wl, SOE_MAX);
+    if (L < 0) rc = -1;
+    V = (double*)calloc((size_t)(L > 0 ? L : 1) * Md, sizeof(double));
+  }
+  const int j0 = ORACLE_SOE_J0;
   for (int m = 0; m < N && rc == 0; m++) {
     for (int k = 0; k < Md; k++) {
       double acc = 0.0;
-      for (int i = 1; i <= m; i++)
-        acc += oracle_bweight((double)(m + 1 - i), p->alpha) *
-               (c[(size_t)i * Md + k] - c[(size_t)(i - 1) * Md + k]);
+      if (!soe) {
+        for (int i = 1; i <= m; i++)
+          acc += oracle_bweight((double)(m + 1 - i), p->alpha) *
+                 (c[(size_t)i * Md + k] - c[(size_t)(i - 1) * Md + k]);
+      } else {
+        const int inew = m + 1 - j0;
+        if (inew >= 1) {
+          const double d = c[(size_t)inew * Md + k] - c[(size_t)(inew - 1) * Md + k];
+          for (int l = 0; l < L; l++)
+            V[(size_t)l * Md + k] = exp(-lam[l]) * V[(size_t)l * Md + k] + exp(-lam[l] * j0) * d;
+        }
+        double far = 0.0;
+        for (int l = 0; l < L; l++) far += wl[l] * V[(size_t)l * Md + k];
+        double near = 0.0;
+        for (int i = (inew + 1 > 1 ? inew + 1 : 1); i <= m; i++)
+          near += oracle_bweight((double)(m + 1 - i), p->alpha) *
+                  (c[(size_t)i * Md + k] - c[(size_t)(i - 1) * Md + k]);
+        acc = far + near;
+      }
       hist[k] = c[(size_t)m * Md + k] - acc;
     }
     double tD = t_fine(p, m);
@@ -503,7 +560,7 @@ int oracle_solve_serial(const oracle_problem* p, const double* u0, double* U, do
       memcpy(U + (size_t)n * Md, c + (size_t)n * S * Md, sizeof(double) * Md);
     if (traj) memcpy(traj, c, sizeof(double) * (size_t)(N + 1) * Md);
   }
-  free(c); free(hist);
+  free(c); free(hist); free(V);
   return rc;
 }
 
@@ -565,7 +622,7 @@ static int fine_F_full(const oracle_problem* p, int n, const double* C, const do
 int oracle_solve_parareal(const oracle_problem* p, const double* u0, double* U,
                           int32_t max_iter, double tol, double* U_iters, double* incr,
                           int32_t* iters) {
-  if (oracle_validate(p) || max_iter < 0) return -1;
+  if (oracle_validate(p) || max_iter < 0 || p->history == 2) return -1;
   int Md = nmodes(p), P = p->slices, S = p->steps / p->slices;
   int full = p->history == 1;
   size_t V = (size_t)(P + 1) * Md;

@@ -41,7 +41,9 @@ typedef struct {
   int32_t d_sel;        /* diffusion selector; -1 = D identically 0 (oracle-only test hook) */
   double  d_param;      /* constant D for d_sel == 0 */
   int32_t f_sel;        /* source selector */
-  int32_t history;      /* 0 hybrid (coarse history in F), 1 full uniform fine L1 */
+  int32_t history;      /* 0 hybrid (coarse history in F), 1 full uniform fine L1,
+                           2 uniform fine L1 with the history beyond ORACLE_SOE_J0 steps by a
+                           sum of exponentials (serial solve only) */
   int32_t source_time;  /* 0 lagged source (the paper), 1 source at the new time level */
   int32_t solver;       /* 0 (or 1): stiffness by Gauss quadrature, dense solve;
                            2: constant D only, stiffness integral taken exactly,
@@ -53,6 +55,22 @@ int    oracle_validate(const oracle_problem* p);
 
 /* L1 weight b_x = (x+1)^(1-alpha) - x^(1-alpha), with b_0 = 1 (L1 scheme, Section 2.1). */
 double oracle_bweight(double x, double alpha);
+
+/* Sum-of-exponentials form of the L1 weights at distances j >= ORACLE_SOE_J0 (the fast
+   history of the paper's outlook, Conclusions (i)): b_j ~ sum_l w_l exp(-lam_l j) for
+   ORACLE_SOE_J0 <= j <= N.  From b_j = (1-alpha) int_j^{j+1} s^-alpha ds and
+   s^-alpha = (1/Gamma(alpha)) int exp(alpha y - s e^y) dy over the real line, the trapezoid
+   rule in y with step ORACLE_SOE_H on the grid y = n h gives
+   w = h (1-alpha)/Gamma(alpha) e^{(alpha-1) y} (1 - exp(-e^y)), lam = e^y; the nodes below
+   n_lo (lam N negligible) are merged into one node lam = 0 whose weight is their geometric
+   sum, and the nodes above n_hi (exp(-lam j) < e^-40 for j >= j0) are dropped.  n_lo keeps
+   the merge error below ORACLE_SOE_EPS b_j for every j <= N.  Writes the merged node first,
+   then n_lo..n_hi ascending; returns the node count, or -1 if it exceeds max_nodes or alpha
+   is not in (0,1). */
+#define ORACLE_SOE_J0 16
+#define ORACLE_SOE_H 0.3
+#define ORACLE_SOE_EPS 1e-13
+int32_t oracle_soe_nodes(double alpha, int32_t N, double* lam, double* w, int32_t max_nodes);
 
 /* Gauss-Legendre nodes (ascending) and weights on (0,1); weights sum to 1. */
 void   oracle_gauss_legendre01(int32_t Q, double* x, double* w);

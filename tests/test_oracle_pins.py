@@ -765,3 +765,89 @@ def test_diagonal_solver_2d_smooth_mms_order(orc, alpha):
 def test_diagonal_solver_rejects_variable_d(orc):
     assert orc.lib().oracle_validate(orc.problem(d_sel=1, solver=2)) == -1
     assert orc.lib().oracle_validate(orc.problem(d_sel=0, solver=2)) == 0
+
+
+# ------------------------------------------------------ sum-of-exponentials history (f3)
+
+@pytest.mark.parametrize("alpha", [0.2, 0.3, 0.5, 0.7, 0.9, 0.99])
+@pytest.mark.parametrize("N", [256, 4096])
+def test_soe_weights_match_l1_weights(orc, alpha, N):
+    """The sum-of-exponentials weights (the fast history of the paper's outlook, Conclusions
+    (i)) reproduce the L1 weights b_j = (j+1)^(1-a) - j^(1-a) at every distance
+    SOE_J0 <= j <= N to 2e-13 relative, against a 40-digit evaluation of the closed form."""
+    lam, w = orc.soe_nodes(alpha, N)
+    assert lam[0] == 0.0 and np.all(np.diff(lam[1:]) > 0) and np.all(w > 0)
+    a = Decimal(repr(alpha))
+    js = sorted(set(list(range(orc.SOE_J0, orc.SOE_J0 + 40)) +
+                    list(np.unique(np.geomspace(orc.SOE_J0, N, 60).astype(int)))))
+    for j in js:
+        approx = float(np.sum(w * np.exp(-lam * j)))
+        ref = float(_b_decimal(Decimal(int(j)), a))
+        assert abs(approx - ref) <= 2e-13 * ref, (alpha, N, j, approx, ref)
+
+
+def test_soe_node_count_grows_slowly(orc):
+    """O(log N) nodes: about a hundred for N = 4096 at alpha = 0.3, a few more per factor 16."""
+    n1, n2 = len(orc.soe_nodes(0.3, 4096)[0]), len(orc.soe_nodes(0.3, 65536)[0])
+    assert 80 <= n1 <= 130 and n1 < n2 <= n1 + 15, (n1, n2)
+
+
+def _scalar_soe(alpha, lam_k, N, c0, lam, w, j0):
+    """One mode of the uniform L1 scheme with the weights at distances >= j0 replaced by
+    sum_l w_l exp(-lam_l d), summed directly over every earlier step (no recursion)."""
+    def b(d):
+        if d == 0:
+            return 1.0
+        if d >= j0:
+            return float(np.sum(w * np.exp(-lam * d)))
+        return (d + 1) ** (1 - alpha) - d ** (1 - alpha)
+    tau = (1.0 / N) ** alpha * math.gamma(2 - alpha)
+    c = [c0]
+    for m in range(N):
+        h = c[m] - sum(b(m + 1 - i) * (c[i] - c[i - 1]) for i in range(1, m + 1))
+        c.append(h / (1 + tau * lam_k))
+    return np.array(c)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.8])
+def test_soe_recursion_equals_direct_sum(orc, alpha):
+    """history = 2 carries the far history as exponential sums updated step by step; with
+    constant D and f = 0 each mode must equal the direct sum over all earlier steps with the
+    same approximate weights (catches an off-by-one in the row entering the far part)."""
+    M, N, D = 3, 80, 0.5
+    p = orc.problem(modes=M, quad=4 * M + 8, steps=N, slices=4, alpha=alpha, d_sel=0, d_param=D,
+                    history=2, solver=2)
+    lam, w = orc.soe_nodes(alpha, N)
+    u0 = np.array([0.8, -0.3, 0.2])
+    _, traj = orc.solve_serial(p, u0, want_traj=True)
+    for k in range(M):
+        ref = _scalar_soe(alpha, D * ((k + 1) * math.pi) ** 2, N, u0[k], lam, w, orc.SOE_J0)
+        assert np.allclose(traj[:, k], ref, rtol=1e-13, atol=1e-16), k
+
+
+def test_soe_short_runs_equal_full_history_bitwise(orc):
+    """With N <= SOE_J0 no step reaches the far part: history 2 is history 1 bit for bit."""
+    kw = dict(modes=6, quad=10, steps=16, slices=4, alpha=0.4, d_sel=2, f_sel=2)
+    u0 = np.linspace(0.5, -0.2, 6)
+    U1 = orc.solve_serial(orc.problem(history=1, **kw), u0)
+    U2 = orc.solve_serial(orc.problem(history=2, **kw), u0)
+    assert np.array_equal(U1, U2)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.7])
+def test_soe_history_error_budget_at_4096_steps(orc, alpha):
+    """Error budget of the approximation: at N = 4096 with the config-2 nonlinearity the
+    sum-of-exponentials solution stays within 1e-11 relative of the exact full-history
+    solution (weights within 2e-13; the scheme is stable, so the gap stays of that order)."""
+    kw = dict(modes=12, quad=18, steps=4096, slices=64, alpha=alpha, d_sel=2, f_sel=2)
+    u0 = (np.arange(1, 13) ** -1.5) * np.array([1, -1] * 6)
+    U1 = orc.solve_serial(orc.problem(history=1, **kw), u0)
+    U2 = orc.solve_serial(orc.problem(history=2, **kw), u0)
+    gap = np.linalg.norm(U2 - U1) / np.linalg.norm(U1)
+    assert 0 < gap <= 1e-11, gap
+
+
+def test_soe_rejected_by_parareal(orc):
+    p = orc.problem(modes=4, quad=8, steps=32, slices=4, alpha=0.5, history=2)
+    with pytest.raises(ValueError):
+        orc.solve_parareal(p, np.ones(4), 2)
