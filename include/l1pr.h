@@ -100,7 +100,16 @@ typedef struct {
   int32_t history;      /* 0: hybrid fine propagator (the paper's; parareal's fixed point)
                            1: full uniform L1 over all N steps (serial; parareal with the plain
                               coarse step, whose fine propagators then take the history of
-                              earlier slices from the previous iterate's fine trajectories) */
+                              earlier slices from the previous iterate's fine trajectories)
+                           2: the uniform L1 scheme of 1 with the history terms at distances
+                              d >= 16 from sum-of-exponentials weights b_d ~ sum_l w_l e^{-lam_l d}
+                              (the fast history of the conclusions' outlook): the trapezoid rule
+                              with step 0.3 in log s on b_d = (1-alpha) int_d^{d+1} s^-alpha ds,
+                              written as an integral of e^{-s t} t^{alpha-1}; weights within about
+                              1e-13 of b_d for 16 <= d <= N, O(log N) nodes (about 100 at
+                              N = 4096), carried as per-mode exponential sums, so each step costs
+                              O(nodes + 16) per coefficient instead of O(m); serial solve only;
+                              not for 1D beyond 256 modes unless solver = 2 */
   int32_t source_time;  /* 0: f lagged to the previous level (the paper)
                            1: f at the new time level (only for u-independent f) */
   int32_t assembly;     /* how the stiffness sum_q w_q D_q phi_k'(x_q) phi_l'(x_q) is formed:

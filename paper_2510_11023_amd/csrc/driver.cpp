@@ -47,6 +47,7 @@ struct Layout {
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
   size_t rhs0 = 0, xs = 0;  // 1D blocked solve: right-hand side and first solution (refinement)
+  size_t soe = 0, soeV = 0;  // history = 2: node tables [B][soeL][3], exponential sums [B][soeL][Mp]
   bool hasA = false;        // A [units][Mp][Mp] is part of the workspace
   size_t prev = 0, hp = 0;  // full-history parareal: previous trajectories, prefix sums
   size_t b12 = 0, s2 = 0;    // 2D: stacked basis tables of the separable stiffness products
@@ -79,7 +80,10 @@ bool valid(const l1pr_problem* p) {
   if (p->d_sel < L1PR_D_CONST || p->d_sel > L1PR_D_LINEAR) return false;
   if (p->d_sel == L1PR_D_CONST && !(p->d_param > 0.0)) return false;
   if (p->f_sel < L1PR_F_ZERO || p->f_sel > L1PR_F_MMS_SMOOTH) return false;
-  if (p->history != 0 && p->history != 1) return false;
+  if (p->history < 0 || p->history > 2) return false;
+  // the sum-of-exponentials history runs in the history kernel, which the 1D device-memory
+  // factorisation path (history inside its evaluation kernel) does not use
+  if (p->history == 2 && p->dim == 1 && p->solver != 2 && roundup(p->modes, 16) > 256) return false;
   if (p->source_time != 0 && p->source_time != 1) return false;
   if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
   if (p->assembly != 0 && p->assembly != 1) return false;
@@ -96,6 +100,43 @@ bool valid(const l1pr_problem* p) {
   return true;
 }
 
+// ---- sum-of-exponentials weights of the far L1 history (history = 2) ----------------------
+// From b_j = (1-a) int_j^{j+1} s^-a ds and s^-a = (1/Gamma(a)) int_R exp(a y - s e^y) dy, the
+// trapezoid rule in y on the grid y_n = n h gives b_j ~ sum_n w_n exp(-e^{y_n} j) with
+// w_n = h (1-a)/Gamma(a) e^{(a-1) y_n} (1 - exp(-e^{y_n})).  Nodes with e^{y_n} >= 40 / j0 are
+// dropped (their terms are below e^-40 at j >= j0); the nodes below n_lo, whose decay over N
+// steps is below the tolerance, are merged into one node of rate 0 with their geometric sum
+// as weight.  With h = 0.3 the weights match b_j to about 1e-13 for j0 <= j <= N.
+constexpr double kSoeH = 0.3, kSoeEps = 1e-13;
+
+int soe_n_hi() { return (int)std::ceil(std::log(40.0 / kSoeJ0) / kSoeH); }
+
+int soe_n_lo(double a, int N) {
+  const double num = kSoeEps * std::tgamma(a) * (1.0 - std::exp(-(a + 1.0) * kSoeH));
+  const double den = kSoeH * (double)N * std::pow((double)N + 1.0, a);
+  return (int)std::floor(std::log(num / den) / (a + 1.0) / kSoeH) + 1;
+}
+
+// nodes (rate, weight) for order a < 1, the merged rate-0 node first
+void soe_nodes(double a, int N, std::vector<double>& rate, std::vector<double>& w) {
+  const int lo = soe_n_lo(a, N), hi = soe_n_hi();
+  const double c = kSoeH * (1.0 - a) / std::tgamma(a);
+  rate.assign(1, 0.0);
+  w.assign(1, c * std::exp(a * (double)(lo - 1) * kSoeH) / (1.0 - std::exp(-a * kSoeH)));
+  for (int n = lo; n <= hi; ++n) {
+    const double y = (double)n * kSoeH, lam = std::exp(y);
+    rate.push_back(lam);
+    w.push_back(c * std::exp((a - 1.0) * y) * (-std::expm1(-lam)));
+  }
+}
+
+// nodes per instance for any order: the largest count over a fine grid of orders, plus two
+int soe_max_nodes(int N) {
+  int mx = 0;
+  for (int i = 1; i < 1000; ++i) mx = std::max(mx, soe_n_hi() - soe_n_lo(i / 1000.0, N) + 2);
+  return mx + 2;
+}
+
 void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.dim = p->dim;
   tb.M1 = p->modes;
@@ -110,7 +151,9 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   tb.B = B;
   // full history: b_0..b_N, plus entries read (never used) by the prefix kernel's last
   // block and step chunk
-  tb.LB = p->history == 1 ? p->steps + 1 + kSerialBlock + 64 : std::max(tb.S, tb.P) + 1;
+  tb.LB = p->history >= 1 ? p->steps + 1 + kSerialBlock + 64 : std::max(tb.S, tb.P) + 1;
+  tb.soe = nullptr;
+  tb.soeL = 0;
   tb.d_sel = p->d_sel;
   tb.f_sel = p->f_sel;
   tb.source_time = p->source_time;
@@ -148,8 +191,13 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
     }
   } else {
     units = B;
-    L.traj = take(cur, D * B * ((p->history == 1 ? N : S) + 1) * Mp);
+    L.traj = take(cur, D * B * ((p->history >= 1 ? N : S) + 1) * Mp);
     if (p->history == 1) L.hp = take(cur, D * B * kSerialBlock * Mp);
+    if (p->history == 2) {
+      tb.soeL = soe_max_nodes(p->steps);
+      L.soe = take(cur, D * B * tb.soeL * 3);
+      L.soeV = take(cur, D * B * tb.soeL * Mp);
+    }
   }
   const size_t nq = two ? Qp * Qp : Qp;  // quadrature points per unit
   L.d = take(cur, D * units * nq);
@@ -273,6 +321,27 @@ l1pr_status setup(const l1pr_problem* p, int B, int op, const double* alpha, voi
                          c.ptr(c.L.dphi), c.ptr(c.L.inst), c.ptr(c.L.bw), c.ptr(c.L.bhyb),
                          c.ptr(c.L.cosq), alpha_dev, un.modes, un.spp, c.s,
                          c.L.b12 ? c.ptr(c.L.b12) : nullptr, c.L.s2 ? c.ptr(c.L.s2) : nullptr));
+  if (c.L.soe) {
+    // per instance and node: (w, e^-lam, e^-lam j0); nodes past an instance's own count, and
+    // every node at order 1 (where the far weights vanish), are zero
+    const int Ls = tb.soeL;
+    std::vector<double> tab((size_t)B * Ls * 3, 0.0), rate, w;
+    for (int b = 0; b < B; ++b) {
+      if (!(al[b] < 1.0)) continue;
+      soe_nodes(al[b], p->steps, rate, w);
+      if ((int)rate.size() > Ls) return L1PR_EINVAL;
+      for (size_t l = 0; l < rate.size(); ++l) {
+        double* t = &tab[((size_t)b * Ls + l) * 3];
+        t[0] = w[l];
+        t[1] = std::exp(-rate[l]);
+        t[2] = std::exp(-rate[l] * kSoeJ0);
+      }
+    }
+    // pageable source: the copy is staged before hipMemcpyAsync returns
+    L1PR_TRY(hipMemcpyAsync(c.ptr(c.L.soe), tab.data(), sizeof(double) * tab.size(),
+                            hipMemcpyHostToDevice, c.s));
+    tb.soe = c.ptr(c.L.soe);
+  }
   return L1PR_OK;
 }
 
@@ -470,6 +539,7 @@ StepArgs base_args(const Ctx& c) {
   a.C2 = c.L.C2 ? c.ptr(c.L.C2) : nullptr;
   a.T2 = c.L.T2 ? c.ptr(c.L.T2) : nullptr;
   a.done = c.done;
+  a.soeV = c.L.soeV ? c.ptr(c.L.soeV) : nullptr;
   return a;
 }
 
@@ -516,8 +586,11 @@ l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_
   const int B = tb.B, P = tb.P, S = tb.S, N = tb.N, Mp = tb.Mp, M = tb.M;
   const long trajN = (long)(N + 1) * Mp;
   double* traj = c.ptr(c.L.traj);
-  double* hp = c.ptr(c.L.hp);
+  // history = 1: exact sums, by prefix blocks; history = 2: the far part by exponential sums
+  const bool soe = tb.soe != nullptr;
+  double* hp = soe ? nullptr : c.ptr(c.L.hp);
   L1PR_TRY(launch_pack(u0, M, B, M, traj, Mp, trajN, c.s));
+  if (soe) L1PR_TRY(launch_fill(c.ptr(c.L.soeV), (long)B * tb.soeL * Mp, 0.0, c.s));
   for (int m = 0; m < N; ++m) {
     StepArgs a = base_args(c);
     a.mode = MODE_FULL;
@@ -525,7 +598,7 @@ l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_
     a.traj = traj;
     a.hp = hp;
     a.hw = kSerialBlock;
-    if (m > 0 && m % kSerialBlock == 0) {
+    if (!soe && m > 0 && m % kSerialBlock == 0) {
       // block n = m / W: the sums over j < nW for its W steps
       PrefixArgs pa{};
       pa.x = traj;
@@ -799,7 +872,7 @@ l1pr_status solve_parareal_net(const l1pr_problem* p, int32_t batch, const doubl
                                int32_t coarse, const void* mlp_params, int32_t mnet, int32_t* iters,
                                double* incr, double* U_iters, int32_t* sweeps, void* ws,
                                size_t ws_bytes, void* stream) {
-  if (!u0 || !U || !p) return L1PR_EINVAL;
+  if (!u0 || !U || !p || p->history == 2) return L1PR_EINVAL;  // history 2: serial only
   if (max_iter < 0 || max_iter > p->slices || std::isnan(tol)) return L1PR_EINVAL;
   if (coarse != L1PR_COARSE_L1 && coarse != L1PR_COARSE_LEARNED) return L1PR_EINVAL;
   const bool learned = coarse == L1PR_COARSE_LEARNED;
@@ -843,7 +916,7 @@ l1pr_status l1pr_solve_serial(const l1pr_problem* p, int32_t batch, const double
     Ctx c;
     l1pr_status st = setup(p, batch, L1PR_OP_SERIAL, alpha, ws, ws_bytes, stream, c);
     if (st != L1PR_OK) return st;
-    return p->history == 1 ? serial_full(c, u0, U, traj) : serial_hybrid(c, u0, U, traj);
+    return p->history >= 1 ? serial_full(c, u0, U, traj) : serial_hybrid(c, u0, U, traj);
   } catch (...) {
     return L1PR_EHIP;
   }

@@ -388,8 +388,62 @@ __global__ __launch_bounds__(HL * HW) void k_history_split(Tables tb, StepArgs a
   *reinterpret_cast<h2*>(hist + (long)u * Mp + k) = h;
 }
 
+// Full uniform L1 step m with the far history as sums of exponentials (history = 2; the fast
+// history of the paper's conclusions): the L1 weights at distances d >= j0 are replaced by
+// sum_l w_l e^{-lam_l d}, so the far part of the sum is sum_l w_l V_l with
+// V_l = sum_{i <= m+1-j0} e^{-lam_l (m+1-i)} (y_i - y_{i-1}), carried from step to step:
+// V_l <- e^{-lam_l} V_l + e^{-lam_l j0} (y_i - y_{i-1}) for the row i = m+1-j0 that has just
+// reached distance j0.  The near part (d < j0) uses the exact weights.  One thread per
+// (instance, coefficient), the nodes in ascending order, eight nodes' states in flight; the
+// state goes to HBM between steps (B * soeL * Mp doubles).
+__global__ __launch_bounds__(64) void k_history_soe(Tables tb, StepArgs a, double* hist) {
+  const int u = blockIdx.x, k = blockIdx.y * 64 + threadIdx.x;
+  if (k >= tb.Mp) return;
+  const UnitView v = decode_unit(tb, a, u);
+  const int Mp = tb.Mp, m = a.m, L = tb.soeL;
+  const double* y = v.y + k;
+  const double* tab = tb.soe + (long)v.b * L * 3;
+  double* V = a.soeV + (long)v.b * L * Mp + k;
+  const int inew = m + 1 - kSoeJ0;
+  const double d = inew >= 1 ? y[(long)inew * Mp] - y[(long)(inew - 1) * Mp] : 0.0;
+  double far = 0.0;
+  int l = 0;
+  for (; l + 7 < L; l += 8) {
+    double s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] = V[(long)(l + q) * Mp];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double* t = tab + (l + q) * 3;
+      if (inew >= 1) {
+        s[q] = t[1] * s[q] + t[2] * d;
+        V[(long)(l + q) * Mp] = s[q];
+      }
+      far = fma(t[0], s[q], far);
+    }
+  }
+  for (; l < L; ++l) {
+    const double* t = tab + l * 3;
+    double sl = V[(long)l * Mp];
+    if (inew >= 1) {
+      sl = t[1] * sl + t[2] * d;
+      V[(long)l * Mp] = sl;
+    }
+    far = fma(t[0], sl, far);
+  }
+  const double* bw = tb.bw + (long)v.b * tb.LB;
+  double near = 0.0;
+  for (int i = inew + 1 > 1 ? inew + 1 : 1; i <= m; ++i)
+    near = fma(bw[m + 1 - i], y[(long)i * Mp] - y[(long)(i - 1) * Mp], near);
+  hist[(long)u * Mp + k] = y[(long)m * Mp] - (far + near);
+}
+
 hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
                           hipStream_t s) {
+  if (a.mode == MODE_FULL && tb.soe) {
+    k_history_soe<<<dim3(units, (tb.Mp + 63) / 64), 64, 0, s>>>(tb, a, hist);
+    return hipGetLastError();
+  }
   const bool full = a.mode == MODE_FULL || (a.mode == MODE_FINE && a.prev);
   if (full) {
     const int threads = tb.Mp < 256 ? roundup(tb.Mp, 64) : 256;

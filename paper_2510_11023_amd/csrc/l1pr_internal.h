@@ -60,6 +60,10 @@ struct Tables {
   const double* b12;   // 2D: [M1p][2 Qp] = [phi^T | dphi^T]
   const double* s2;    // 2D: [2 Qp][M1p] = [dphi; phi]
   int* flag;           // the call's device status word (FLAG_* bits, set with atomicOr)
+  // history = 2 (sum-of-exponentials far history): per instance and node, (w, e^-lam,
+  // e^-lam j0) [B][soeL][3]; nullptr otherwise
+  const double* soe;
+  int soeL;
   int spin;            // polls of a bounded device wait before it gives up (sets FLAG_WAIT)
 };
 
@@ -92,7 +96,12 @@ struct StepArgs {
   // parareal: instances that have met their stop test (nonzero) keep their slice ends; their
   // units skip the factorisation and store nothing (nullptr: no instance is finished)
   const int32_t* done;
+  // history = 2: the exponential sums V [B][soeL][Mp] carried from step to step
+  double* soeV;
 };
+
+// near window of the sum-of-exponentials history: distances below it use the exact weights
+constexpr int kSoeJ0 = 16;
 
 // instance of unit u in a step launch
 __host__ __device__ inline int unit_instance(const StepArgs& a, int u) {
