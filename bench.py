@@ -61,6 +61,7 @@ if ROOT not in sys.path:
 METRIC = "time-to-1e-8-rel solution: learned-G vs plain-G parareal; mode-steps/s"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
 TARGET = 1e-8
 
 # HBM traffic of the fine-sweep factor-and-solve kernel, per full launch (2048 units), from
@@ -148,6 +149,15 @@ def learned_vs_plain(l1, torch, W, dev):
     t_train = time.perf_counter() - t0
     del x, t, u0t
     log(f"learned G: data {t_data:.1f} s, training {t_train:.1f} s, loss {losses[0]:.3g} -> {losses[-1]:.3g}")
+    # training work on BF16 MFMA: forward 2 (in_p H + 2 H^2 + H out_p) per sample at the padded
+    # widths the kernels multiply, backward twice that (input and weight gradients)
+    i = model.info
+    fwd = 2 * (i.in_padded * i.hidden + 2 * i.hidden * i.hidden + i.hidden * i.out_padded)
+    train_flops = 3 * fwd * (nsamples // 1024) * 1024 * epochs
+    bf16 = {"bound": "mfma", "achieved": round(train_flops / t_train / 1e12, 3), "peak": PEAK_BF16_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(train_flops / t_train / 1e12 / PEAK_BF16_TFLOPS, 5),
+            "flops": train_flops, "note": "whole training loop over its wall time (BF16 MFMA "
+            "16x16x16, FP32 accumulation; launch-bound at batch 1024)"}
 
     ea = [float(a) for a in W.alphas_uniform(len(W.C4_EVAL_SEEDS), W.C4_EVAL_ALPHA_SEED)]
     u0 = torch.tensor(W.u0_batch_1d(M, W.C4_EVAL_SEEDS), device=dev)
@@ -159,7 +169,8 @@ def learned_vs_plain(l1, torch, W, dev):
                        f"trained on {ntrain} seeded serial trajectories and their first "
                        f"{W.C4_TRAIN_SWEEPS} plain parareal iterates ({nsamples} samples)",
            "train": {"data_s": round(t_data, 2), "train_s": round(t_train, 2), "epochs": epochs,
-                     "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1])}}
+                     "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+                     "bf16_roofline": bf16}}
     for name, extra in (("plain", {}), ("learned", {"coarse": l1.COARSE_LEARNED, "mlp_params": model.params})):
         ks, e = find_kstar(l1, p, u0, Us, ws, 30, alpha=ea, **extra)
         log(f"{name} G: k*={ks} errors " + " ".join(f"{v:.1e}" for v in e[: (ks or 30) + 1]))
@@ -184,9 +195,54 @@ def learned_vs_plain(l1, torch, W, dev):
     return out
 
 
-def uneven_batch(l1, torch, W, dev):
+def c5_network(l1, torch, W, dev, log_prefix="uneven learned G"):
+    """One residual network of 256 modes for the whole uneven workload: trained on plain-G
+    pairs of config-5-type problems (u0 = sin(pi x), D = 1 + sin^2(u)/2, manufactured f) at
+    M in {64, 128, 192, 256}, Q = 2M, S in {8, 24, 40, 64} (64 seeded orders each; serial
+    trajectories and the first three plain parareal iterates), the coefficients a problem
+    does not carry padded with zeros."""
+    import numpy as np
+
+    from paper_2510_11023_amd.learned import LearnedCoarse, training_data_padded
+
+    t0 = time.perf_counter()
+    model = LearnedCoarse(256, seed=0)
+    xs, ts = [], []
+    k = 0
+    for M in (64, 128, 192, 256):
+        for S in (8, 24, 40, 64):
+            p = l1.make_problem(**W.with_(W.C5, modes=M, quad=2 * M, steps=W.C5["slices"] * S))
+            u0 = torch.zeros((64, M), dtype=torch.float64, device=dev)
+            u0[:, 0] = 2.0 ** -0.5
+            al = W.alphas_uniform(64, seed=7000 + k)
+            x, t = training_data_padded(p, u0, al, model, sweeps=3)
+            xs.append(x)
+            ts.append(t)
+            k += 1
+    x, t = torch.cat(xs), torch.cat(ts)
+    del xs, ts
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    model.set_stats(x, t)
+    t0 = time.perf_counter()
+    losses = model.train(x, t, epochs=10, batch=1024, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n = x.shape[0]
+    del x, t
+    log(f"{log_prefix}: data {t_data:.1f} s, training {t_train:.1f} s ({n} samples), "
+        f"loss {losses[0]:.3g} -> {losses[-1]:.3g}")
+    return model, {"data_s": round(t_data, 2), "train_s": round(t_train, 2), "samples": int(n),
+                   "epochs": 10, "loss_first_epoch": float(losses[0]),
+                   "loss_last_epoch": float(losses[-1])}
+
+
+def uneven_batch(l1, torch, W, dev, learned_model=None):
     """Config 5: 256 instances with their own modes, steps per slice and order, grouped by
-    padded mode count; every group's parareal run is one branch of a single HIP graph."""
+    padded mode count; every group's parareal run is one branch of a single HIP graph; each
+    instance stops at its first sweep whose increment is <= 1e-8 (its units then return at
+    entry).  Plain coarse step, then (with a network) the learned one with the plain step as
+    fallback."""
     import numpy as np
 
     from paper_2510_11023_amd import solver
@@ -201,7 +257,7 @@ def uneven_batch(l1, torch, W, dev):
         B = len(idx)
         kw = W.with_(W.C5, modes=int(Mp), quad=2 * int(Mp), steps=P * int(spp[idx].max()))
         p = l1.make_problem(**kw)
-        ws = solver._workspace(p, B, 1, dev)[0]
+        ws = solver.uneven_workspace(p, B, dev, learned=learned_model is not None)
         p.tune = l1.autotune(p, B, workspace=ws)
         u0 = torch.zeros((B, int(Mp)), dtype=torch.float64, device=dev)
         u0[:, 0] = 2.0 ** -0.5
@@ -215,75 +271,96 @@ def uneven_batch(l1, torch, W, dev):
         torch.cuda.synchronize()
         t_ser += time.perf_counter() - t0
         groups.append(g)
-    # sweeps per group: until every instance's increment is <= 1e-8 (capped), found untimed
+    useful = float((modes.astype(np.int64) * P * spp).sum())
     cap, tol = 24, 1e-8
-    for g in groups:
-        U, conv, _ = l1.solve_parareal_uneven(g["p"], g["u0"], cap, g["modes"], g["spp"],
-                                              g["alpha"], conv_tol=tol, workspace=g["ws"])
-        c = conv.cpu().numpy()
-        g["sweeps"] = int(cap if (c < 0).any() else c.max())
-        g["out"] = torch.empty_like(U)
-        g["conv"] = torch.empty(g["B"], dtype=torch.int32, device=dev)
-        g["stamps"] = torch.zeros(g["sweeps"] + 1, dtype=torch.int64, device=dev)
-        g["stream"] = torch.cuda.Stream()
-    t_start = torch.zeros(1, dtype=torch.int64, device=dev)
 
-    def run_all():
-        solver.device_stamp(t_start)
-        main = torch.cuda.current_stream()
+    def graph_run(extra):
+        # sweeps per group: until every instance's increment is <= 1e-8 (capped), found untimed
         for g in groups:
-            g["stream"].wait_stream(main)
-            with torch.cuda.stream(g["stream"]):
-                l1.solve_parareal_uneven(g["p"], g["u0"], g["sweeps"], g["modes"], g["spp"],
-                                         g["alpha"], conv_tol=tol, workspace=g["ws"],
-                                         out=g["out"], conv=g["conv"], stamps=g["stamps"])
-        for g in groups:
-            main.wait_stream(g["stream"])
+            U, conv, _ = l1.solve_parareal_uneven(g["p"], g["u0"], cap, g["modes"], g["spp"],
+                                                  g["alpha"], conv_tol=tol, workspace=g["ws"], **extra)
+            c = conv.cpu().numpy()
+            g["sweeps"] = int(cap if (c < 0).any() else c.max())
+            g["out"] = torch.empty_like(U)
+            g["conv"] = torch.empty(g["B"], dtype=torch.int32, device=dev)
+            g["stamps"] = torch.zeros(g["sweeps"] + 1, dtype=torch.int64, device=dev)
+            g["stream"] = torch.cuda.Stream()
+        t_start = torch.zeros(1, dtype=torch.int64, device=dev)
 
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        run_all()  # warm-up outside capture
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        run_all()
-    graph.replay()
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(3):
-        t0 = time.perf_counter()
+        def run_all():
+            solver.device_stamp(t_start)
+            main = torch.cuda.current_stream()
+            for g in groups:
+                g["stream"].wait_stream(main)
+                with torch.cuda.stream(g["stream"]):
+                    l1.solve_parareal_uneven(g["p"], g["u0"], g["sweeps"], g["modes"], g["spp"],
+                                             g["alpha"], conv_tol=tol, workspace=g["ws"],
+                                             out=g["out"], conv=g["conv"], stamps=g["stamps"],
+                                             **extra)
+            for g in groups:
+                main.wait_stream(g["stream"])
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            run_all()  # warm-up outside capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            run_all()
         graph.replay()
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    t_graph = sorted(times)[1]
-    khz = solver.wall_clock_khz()
-    lat, err = [], 0.0
-    t0d = int(t_start.item())
-    for g in groups:
-        conv = g["conv"].cpu().numpy()
-        st = g["stamps"].cpu().numpy()
-        for b in range(g["B"]):
-            k = conv[b] if conv[b] > 0 else g["sweeps"]
-            lat.append((st[k] - t0d) / khz)  # ms
-        d = (g["out"] - g["Us"]).flatten(1).norm(dim=1) / g["Us"].flatten(1).norm(dim=1)
-        err = max(err, float(d.max()))
-    lat = np.array(lat)
-    useful = float((modes.astype(np.int64) * P * spp).sum())
-    log(f"uneven batch: {len(groups)} groups, graph {t_graph * 1e3:.1f} ms, serial {t_ser * 1e3:.1f} ms, "
-        f"max error vs serial {err:.2e}, latency p50/p90/p99 {np.percentile(lat, 50):.1f}/"
-        f"{np.percentile(lat, 90):.1f}/{np.percentile(lat, 99):.1f} ms")
-    return {"workload": "256 instances, P=64, M~U{64..256}, S~U{8..64} (N=64 S), alpha~U(0.2,1), "
-                        "D=1+sin^2(u)/2, manufactured f, u0=sin(pi x); grouped by roundup16(M) "
-                        "(Q = 2 roundup16(M)); one HIP graph with one branch per group",
-            "groups": [{"Mp": g["Mp"], "instances": g["B"], "sweeps": g["sweeps"], "tune": g["p"].tune}
-                       for g in groups],
-            "graph_ms": round(t_graph * 1e3, 2), "serial_ms": round(t_ser * 1e3, 2),
-            "useful_mode_steps_per_s": useful / t_graph,
-            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
-                           "p99": float(np.percentile(lat, 99))},
-            "max_rel_err_vs_serial": err, "convergence": "increment <= 1e-8 per instance"}
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            graph.replay()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t_graph = sorted(times)[1]
+        khz = solver.wall_clock_khz()
+        lat, err, sweeps_inst = [], 0.0, []
+        t0d = int(t_start.item())
+        for g in groups:
+            conv = g["conv"].cpu().numpy()
+            st = g["stamps"].cpu().numpy()
+            for b in range(g["B"]):
+                k = conv[b] if conv[b] > 0 else g["sweeps"]
+                sweeps_inst.append(int(k))
+                lat.append((st[k] - t0d) / khz)  # ms
+            d = (g["out"] - g["Us"]).flatten(1).norm(dim=1) / g["Us"].flatten(1).norm(dim=1)
+            err = max(err, float(d.max()))
+        lat = np.array(lat)
+        del graph
+        return {"graph_ms": round(t_graph * 1e3, 2), "useful_mode_steps_per_s": useful / t_graph,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                               "p99": float(np.percentile(lat, 99))},
+                "mean_sweeps_per_instance": float(np.mean(sweeps_inst)),
+                "groups": [{"Mp": g["Mp"], "instances": g["B"], "sweeps": g["sweeps"], "tune": g["p"].tune}
+                           for g in groups],
+                "max_rel_err_vs_serial": err}
+
+    plain = graph_run({})
+    log(f"uneven batch, plain G: {len(groups)} groups, graph {plain['graph_ms']:.1f} ms, serial "
+        f"{t_ser * 1e3:.1f} ms, error vs serial {plain['max_rel_err_vs_serial']:.2e}, mean sweeps "
+        f"{plain['mean_sweeps_per_instance']:.2f}")
+    out = {"workload": "256 instances, P=64, M~U{64..256}, S~U{8..64} (N=64 S), alpha~U(0.2,1), "
+                       "D=1+sin^2(u)/2, manufactured f, u0=sin(pi x); grouped by roundup16(M) "
+                       "(Q = 2 roundup16(M)); one HIP graph with one branch per group; each "
+                       "instance stops at its first sweep with increment <= 1e-8",
+           "serial_ms": round(t_ser * 1e3, 2), "plain": plain,
+           # the headline fields keep their former names (plain coarse step)
+           "graph_ms": plain["graph_ms"], "useful_mode_steps_per_s": plain["useful_mode_steps_per_s"],
+           "latency_ms": plain["latency_ms"], "max_rel_err_vs_serial": plain["max_rel_err_vs_serial"]}
+    if learned_model is not None:
+        model, train = learned_model
+        lr = graph_run({"coarse": l1.COARSE_LEARNED, "mlp_params": model.params, "mlp_modes": 256})
+        lr["train"] = train
+        out["learned"] = lr
+        out["speedup_learned_over_plain"] = round(plain["graph_ms"] / lr["graph_ms"], 3)
+        log(f"uneven batch, learned G: graph {lr['graph_ms']:.1f} ms, error vs serial "
+            f"{lr['max_rel_err_vs_serial']:.2e}, mean sweeps {lr['mean_sweeps_per_instance']:.2f}")
+    return out
 
 
 def config3_2d(l1, torch, W, dev, with_parareal=True):
@@ -418,6 +495,80 @@ def config3_cg(l1, torch, W, dev, Us_direct=None):
     out["parareal_plain"] = rec
     log(f"config 3 (CG): fine sweep {t_sweep * 1e3:.0f} ms, serial {t_ser * 1e3:.0f} ms, "
         f"parareal k*={ks} {rec.get('ms')} ms")
+    return out
+
+
+def median_time(torch, fn, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    out = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2], out
+
+
+def config1_latency(l1, torch, W, dev):
+    """Config 1 (one instance, M = 32, N = 256, P = 8): serial and parareal latency; parareal
+    stops at its first sweep whose increment is <= 1e-8 (the flowchart's test)."""
+    kw = dict(W.C1)
+    M, N, P = kw["modes"], kw["steps"], kw["slices"]
+    p = l1.make_problem(**kw)
+    u0 = torch.tensor(W.u0_sine_mode(M)[None, :], device=dev)
+    t_ser, (Us, _) = median_time(torch, lambda: l1.solve_serial(p, u0))
+    t_par, r = median_time(torch, lambda: l1.solve_parareal(p, u0, P, tol=1e-8))
+    err = rel_err_max(r.U, Us)
+    log(f"config 1: serial {t_ser * 1e3:.2f} ms, parareal {t_par * 1e3:.2f} ms ({r.iters} sweeps, "
+        f"error vs serial {err:.1e})")
+    return {"workload": f"1D, M={M}, Q={kw['quad']}, N={N}, P={P}, alpha={kw['alpha']}, "
+                        "D=1+sin^2(u)/2, manufactured f, u0=sin(pi x), one instance",
+            "serial_ms": round(t_ser * 1e3, 3), "parareal_ms": round(t_par * 1e3, 3),
+            "parareal_sweeps": r.iters, "parareal_rel_err_vs_serial": err,
+            "serial_mode_steps_per_s": M * N / t_ser, "parareal_mode_steps_per_s": M * N / t_par,
+            "stop": "per-instance increment <= 1e-8"}
+
+
+def soe_history(l1, torch, W, dev, alpha=0.3):
+    """The sum-of-exponentials far history (history = 2) against the exact full history
+    (history = 1) on the config-2 batch, serial solves at N = 4096 and 16384: wall time, the
+    history kernel's time per step, and the gap between the two solutions."""
+    from paper_2510_11023_amd import _lib
+
+    B, M = W.C2_BATCH, 256
+    u0 = torch.tensor(W.u0_batch_1d(M, range(B)), dtype=torch.float64, device=dev)
+    out = {"workload": f"1D, M={M}, Q=384, P=64, alpha={alpha}, {B} instances, config-2 D and f, "
+                       "serial solve with the full uniform L1 history: exact (history 1, prefix "
+                       "blocks of 64 steps) against the sum-of-exponentials far history (history 2)",
+           "runs": []}
+    for N in (4096, 16384):
+        rec = {"steps": N}
+        res = {}
+        for h in (1, 2):
+            p = l1.make_problem(**W.with_(W.C2, alpha=alpha, steps=N, history=h))
+            ws = torch.empty(l1.workspace_bytes(p, B, 0), dtype=torch.uint8, device=dev)
+            l1.solve_serial(p, u0, workspace=ws)
+            torch.cuda.synchronize()
+            _lib.profile_start(only=("history", "prefix"))
+            t0 = time.perf_counter()
+            U, _ = l1.solve_serial(p, u0, workspace=ws)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            st = _lib.profile_stop()
+            hist_ms = sum(v[1] for k, v in st.items())
+            res[h] = U
+            key = "exact" if h == 1 else "soe"
+            rec[key] = {"ms": round(t * 1e3, 1), "mode_steps_per_s": B * M * N / t,
+                        "history_us_per_step": round(hist_ms * 1e3 / N, 2),
+                        "workspace_mib": round(ws.numel() / 2**20, 1)}
+            del ws
+        if 2 in res:
+            rec["rel_gap_soe_vs_exact"] = rel_err_max(res[2], res[1])
+        out["runs"].append(rec)
+        log(f"soe history N={N}: exact {rec['exact']['ms']} ms ({rec['exact']['history_us_per_step']} us/step), "
+            f"soe {rec['soe']['ms']} ms ({rec['soe']['history_us_per_step']} us/step), gap {rec['rel_gap_soe_vs_exact']:.1e}")
     return out
 
 
@@ -699,7 +850,7 @@ def main():
     ap.add_argument("--no-paper-model", action="store_true")
     ap.add_argument("--no-constant-d", action="store_true")
     ap.add_argument("--mode", choices=["full", "kernels", "kernels2d", "kernelsfh", "fullhistory",
-                                       "cg2d", "constd"],
+                                       "cg2d", "constd", "uneven", "soe", "learned"],
                     default="full",
                     help="kernels: one parareal sweep of the alpha=0.3 batch and a 1 GiB plain "
                          "device copy (for hardware-counter runs); kernels2d: one fine sweep of "
@@ -708,7 +859,10 @@ def main():
                          "none of these prints a JSON line; fullhistory: only the full-history "
                          "parareal section (its JSON); cg2d: only the config-3 conjugate-gradient "
                          "section (its JSON); constd: only the constant-D diagonal-solve "
-                         "section (its JSON)")
+                         "section (its JSON); uneven: only the uneven-batch section with its "
+                         "learned coarse step (its JSON); soe: only the sum-of-exponentials "
+                         "history section (its JSON); learned: only the config-4 learned "
+                         "coarse step section (its JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this solver runs on one GPU; a run on several GPUs is not supported "
@@ -774,6 +928,19 @@ def main():
         print(json.dumps(full_history(l1, torch, W, dev)), flush=True)
         return
 
+    if args.mode == "uneven":
+        print(json.dumps(uneven_batch(l1, torch, W, dev, learned_model=c5_network(l1, torch, W, dev))),
+              flush=True)
+        return
+
+    if args.mode == "soe":
+        print(json.dumps(soe_history(l1, torch, W, dev)), flush=True)
+        return
+
+    if args.mode == "learned":
+        print(json.dumps(learned_vs_plain(l1, torch, W, dev)), flush=True)
+        return
+
     if args.mode == "kernels":
         # one coarse sweep + one fine sweep + one correction sweep, then a plain copy of
         # 2^27 doubles (1 GiB read + 1 GiB written) that calibrates the byte counters
@@ -785,16 +952,30 @@ def main():
         log("kernels mode done")
         return
 
-    # serial reference and its time
+    # serial reference and its time: one call over all 3 x 32 instances, each with its own
+    # alpha (the fair comparison: every instance's steps share the launches); the three groups
+    # one after another for context.  An instance's result does not depend on its batch, so
+    # both give the same solutions bit for bit.
+    u96 = torch.cat([u0] * len(alphas)).contiguous()
+    al96 = [a for a in alphas for _ in range(B)]
+    ws_ser96 = torch.empty(l1.workspace_bytes(p0, len(alphas) * B, 0), dtype=torch.uint8, device=dev)
+    l1.solve_serial(p0, u96, alpha=al96, workspace=ws_ser96)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U96, _ = l1.solve_serial(p0, u96, alpha=al96, workspace=ws_ser96)
+    torch.cuda.synchronize()
+    t_serial_all = time.perf_counter() - t0
+    del ws_ser96
+    log(f"serial, 96 instances in one call: {t_serial_all * 1e3:.1f} ms")
     Us, t_serial = {}, {}
-    for a in alphas:
-        l1.solve_serial(probs[a], u0, workspace=ws_ser)  # warm
+    for gi, a in enumerate(alphas):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         U, _ = l1.solve_serial(probs[a], u0, workspace=ws_ser)
         torch.cuda.synchronize()
         t_serial[a] = time.perf_counter() - t0
         Us[a] = U
+        assert torch.equal(U, U96[gi * B:(gi + 1) * B]), "batch independence"
         log(f"serial alpha={a}: {t_serial[a] * 1e3:.1f} ms")
 
     # k*(alpha): first sweep count whose iterate is within 1e-8 of the serial solution
@@ -809,10 +990,10 @@ def main():
     streams = [torch.cuda.Stream() for _ in alphas]
     ws_groups = [ws_par] + [torch.empty_like(ws_par) for _ in alphas[1:]]
 
-    def step(pr=probs):
+    def step(pr=probs, wsg=None):
         out = {}
         cur = torch.cuda.current_stream()
-        for a, s_, w in zip(alphas, streams, ws_groups):
+        for a, s_, w in zip(alphas, streams, wsg or ws_groups):
             s_.wait_stream(cur)
             with torch.cuda.stream(s_):
                 out[a] = l1.solve_parareal(pr[a], u0, kstar[a], tol=0.0, want_incr=False,
@@ -840,6 +1021,22 @@ def main():
 
     useful = len(alphas) * B * M * N
     value = useful / (ms_per_step / 1e3)
+
+    # the same 96 instances in one parareal call with the flowchart's stop rule applied per
+    # instance (increment <= 1e-8, one host synchronisation per sweep): no offline k*
+    ws96 = torch.empty(l1.workspace_bytes(p0, len(alphas) * B, 1), dtype=torch.uint8, device=dev)
+    run96 = lambda: l1.solve_parareal(p0, u96, P, tol=TARGET, alpha=al96, want_incr=False,
+                                      workspace=ws96)
+    t96, r96 = median_time(torch, run96, reps=3)
+    inst96 = r96.inst.cpu().numpy()
+    tol_stop = {"ms": round(t96 * 1e3, 1), "mode_steps_per_s": useful / t96,
+                "sweeps": r96.iters, "max_rel_err_vs_serial": rel_err_max(r96.U, U96),
+                "sweeps_per_alpha": {str(a): int(inst96[g * B:(g + 1) * B].max()) for g, a in enumerate(alphas)},
+                "note": "one call, 96 instances with their own alpha; each instance stops at its "
+                        "first sweep whose relative increment is <= 1e-8"}
+    del ws96
+    log(f"parareal, one call with per-instance stop: {t96 * 1e3:.1f} ms, {r96.iters} sweeps, "
+        f"error vs serial {tol_stop['max_rel_err_vs_serial']:.1e}")
     # sweep k launches only the slices n >= k (the earlier ones are converged)
     fine_units = [B * (P - min(k, P - 1)) for a in alphas for k in range(kstar[a])]
     executed = sum(u * S * M for u in fine_units)
@@ -941,12 +1138,15 @@ def main():
              "flops_per_unit_step": int(unit_step),
              "unit_steps": {"fine": fine_unit_steps, "coarse": coarse_unit_steps}}
 
-    # the same step with the quadrature-GEMM stiffness (assembly = 1)
-    step(probs_gemm)
+    # the same step with the quadrature-GEMM stiffness (assembly = 1), whose systems go through
+    # device memory: workspaces of their own
+    ws_gemm = [torch.empty(l1.workspace_bytes(probs_gemm[a], B, 1), dtype=torch.uint8, device=dev)
+               for a in alphas]
+    step(probs_gemm, ws_gemm)
     torch.cuda.synchronize()
     _lib.profile_start()
     t0 = time.perf_counter()
-    out_g = step(probs_gemm)
+    out_g = step(probs_gemm, ws_gemm)
     torch.cuda.synchronize()
     t_gemm = time.perf_counter() - t0
     stats_g = _lib.profile_stop()
@@ -963,14 +1163,23 @@ def main():
             "unit": "TFLOP/s", "frac": round(fl / avg_a / 1e12 / PEAK_FP64_TFLOPS, 4),
             "avg_launch_ms": round(avg_a * 1e3, 4), "flops_per_launch": fl}
     log(f"assembly=1 step: {t_gemm * 1e3:.1f} ms")
+    del ws_gemm
 
     learned = None
     if not args.no_learned:
         learned = learned_vs_plain(l1, torch, W, dev)
 
+    c1 = config1_latency(l1, torch, W, dev)
+
+    soe = None
+    if not args.no_full_history:
+        soe = soe_history(l1, torch, W, dev)
+
     uneven = None
     if not args.no_uneven:
-        uneven = uneven_batch(l1, torch, W, dev)
+        net5 = None if args.no_learned else c5_network(l1, torch, W, dev)
+        uneven = uneven_batch(l1, torch, W, dev, learned_model=net5)
+        del net5
 
     paper = None
     if not args.no_paper_model:
@@ -1016,8 +1225,15 @@ def main():
             "achieved_rel_err": {str(a): achieved_err[a] for a in alphas},
         },
         "time_to_1e8_ms": ms_per_step,
-        "serial_ms": serial_total * 1e3,
-        "serial_mode_steps_per_s": useful / serial_total,
+        "serial_ms": t_serial_all * 1e3,
+        "serial_mode_steps_per_s": useful / t_serial_all,
+        "serial_note": "one l1pr_solve_serial call over all 96 instances (per-instance alpha); "
+                       "the three alpha groups one after another take serial_ms_per_group_total",
+        "serial_ms_per_group_total": serial_total * 1e3,
+        "parareal_over_serial_time": round(ms_per_step / (t_serial_all * 1e3), 3),
+        "parareal_tol_stop": tol_stop,
+        "config1": c1,
+        "soe_history": soe,
         "executed_mode_steps_per_s": executed / (ms_per_step / 1e3),
         "profiled_kernel_time_per_wall_time": share,
         "schedule": "the three alpha groups on three streams, one workspace each",

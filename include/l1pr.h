@@ -235,8 +235,10 @@ enum { L1PR_COARSE_L1 = 0,       /* the coarse L1 step G of Section 2.1 */
  *              layout from l1pr_mlp_layout for M = p->modes, 1D, M <= 256, history 0,
  *              256-byte aligned).  The network is a deterministic function of its input, so
  *              parareal keeps its exactness (after k sweeps the first k+1 slice ends equal
- *              the serial solution).  A unit whose correction is not finite or larger than
- *              ||G_n|| + 1 uses the plain G_n (the plain coarse step is the fallback).
+ *              the serial solution).  The plain coarse step is the fallback: a unit whose
+ *              correction is not finite or larger than ||G_n|| + 1 uses the plain G_n, and an
+ *              instance whose increment grows from one sweep to the next (the learned
+ *              iteration is not contracting) uses the plain coarse step from then on.
  *              ws_bytes must then also cover l1pr_parareal_learned_extra_bytes(p, batch).
  *   iters    : device int32 [batch] or NULL: each instance's status after the call: the
  *              number of sweeps after which it was finished (tol > 0) or that it ran (tol <= 0,
@@ -277,8 +279,8 @@ l1pr_status l1pr_check(const void* ws, void* stream);
  *   mlp       : device blob of a network for mlp_modes modes (layout from l1pr_mlp_layout,
  *               256-byte aligned), p->modes <= mlp_modes <= 256: one network serves every
  *               instance; the coefficients an instance does not carry (k >= M_b) enter it as
- *               zeros and only its outputs for k < M_b are used.  A unit whose correction is
- *               not finite or larger than ||G_n|| + 1 keeps the plain G_n (the fallback).
+ *               zeros and only its outputs for k < M_b are used.  Fallback to the plain
+ *               coarse step as in l1pr_solve_parareal (per unit and per instance).
  *               ws_bytes must also cover l1pr_parareal_learned_extra_bytes(p, batch). */
 typedef struct {
   const int32_t* modes;
@@ -388,8 +390,10 @@ l1pr_status l1pr_mlp_sync(int32_t modes, const void* state, void* params, void* 
 /* zero the Adam moments in state */
 l1pr_status l1pr_mlp_reset_moments(int32_t modes, void* state, void* stream);
 /* normalisation into params: per-column mean and (population) standard deviation of the
- * inputs x [n][M+2] (a column with no spread gets 1); per-mode mean of the targets t [n][M]
- * and one common output scale, the root mean square of the per-mode standard deviations */
+ * inputs x [n][M+2] (a column with no spread gets 1; the M coefficient columns' scales are
+ * floored at 1e-4 of the largest of them, so that barely varying inputs are not magnified);
+ * per-mode mean of the targets t [n][M] and one common output scale, the root mean square of
+ * the per-mode standard deviations (a target column with no spread counts as 0) */
 l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_t n,
                            void* params, void* stream);
 /* training pairs from slice ends Z [B][P+1][M] and coarse values G [B][P][M] (device FP64):

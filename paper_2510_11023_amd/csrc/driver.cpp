@@ -44,6 +44,7 @@ struct Layout {
   size_t total = 0;
   size_t flags = 0;  // the call's device status word: offset 0 of every workspace (l1pr_check)
   size_t done = 0, conv = 0;  // parareal: per-instance finished flags and stop records [B]
+  size_t lgoff = 0, incrp = 0;  // parareal: learned step switched off [B], previous increment [B]
   size_t xq, wq, phi, phiT, dphi, cosq, inst, bw, bhyb, alpha, Z0, Z1, Gold, traj, d, rhs, A, incrk;
   size_t g, mom, F, C2, T2, q;
   size_t rhs0 = 0, xs = 0;  // 1D blocked solve: right-hand side and first solution (refinement)
@@ -239,6 +240,8 @@ void make_layout(const l1pr_problem* p, int B, int op, Layout& L, Tables& tb) {
   if (para) {
     L.done = take(cur, sizeof(int32_t) * B);
     L.conv = take(cur, sizeof(int32_t) * B);
+    L.lgoff = take(cur, sizeof(int32_t) * B);
+    L.incrp = take(cur, D * B);
   }
   L.total = cur;
 }
@@ -252,6 +255,7 @@ struct Ctx {
   bool pcg;      // 2D step systems by preconditioned conjugate gradients
   bool diag;     // constant D: the diagonal solve in the sine basis
   const int32_t* done = nullptr;  // parareal: finished instances (skip their units)
+  const int32_t* lg_off = nullptr;  // parareal, learned step: instances that went back to plain G
   char* ws;
   hipStream_t s;
   double* ptr(size_t off) const { return reinterpret_cast<double*>(ws + off); }
@@ -675,7 +679,7 @@ l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e, const
   if (st != L1PR_OK) return st;
   L1PR_TRY(timed("mlp", a, c.tb.B, c.s, [&] {
     return mlp_coarse_apply(lg->L, lg->params, lg->G, c.tb.Mp, c.tb.inst, c.tb.B, c.tb.M, c.tb.Mp,
-                            n, c.tb.P, e, lg->ws, c.s, c.done);
+                            n, c.tb.P, e, lg->ws, c.s, c.done, c.lg_off);
   }));
   return L1PR_OK;
 }
@@ -770,6 +774,13 @@ l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, d
 
   L1PR_TRY(launch_fill_int(done, B, 0, c.s));
   L1PR_TRY(launch_fill_int(conv, B, -1, c.s));
+  // learned coarse step: an instance whose increment grows from one sweep to the next goes
+  // back to the plain coarse step for good (the first k+1 slice ends after k sweeps stay the
+  // serial ones whatever the coarse step is; from the next sweep on its iteration is plain
+  // parareal)
+  int32_t* lgoff = lg ? reinterpret_cast<int32_t*>(c.ws + c.L.lgoff) : nullptr;
+  if (lgoff) L1PR_TRY(launch_fill_int(lgoff, B, 0, c.s));
+  c.lg_off = lgoff;
   // coarse initial sweep: U^0_{n+1} = G_n(U^0_0..U^0_n), G_old(n) = the same value
   L1PR_TRY(launch_pack(u0, M, B, M, Zk, Mp, vecP, c.s));
   for (int n = 0; n < P; ++n) {
@@ -825,7 +836,7 @@ l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, d
       if (st != L1PR_OK) return st;
     }
     L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, done, conv,
-                              exit_tol, tb.flag, c.s));
+                              exit_tol, tb.flag, c.s, lgoff, c.ptr(c.L.incrp)));
     if (tr.stamps) L1PR_TRY(launch_stamp(tr.stamps + k + 1, c.s));
     if (U_iters)
       L1PR_TRY(launch_unpack(Zk1, Mp, vecP, U_iters + (long)(k + 1) * iterStride, M,

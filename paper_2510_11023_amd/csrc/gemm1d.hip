@@ -393,55 +393,81 @@ __global__ __launch_bounds__(HL * HW) void k_history_split(Tables tb, StepArgs a
 // sum_l w_l e^{-lam_l d}, so the far part of the sum is sum_l w_l V_l with
 // V_l = sum_{i <= m+1-j0} e^{-lam_l (m+1-i)} (y_i - y_{i-1}), carried from step to step:
 // V_l <- e^{-lam_l} V_l + e^{-lam_l j0} (y_i - y_{i-1}) for the row i = m+1-j0 that has just
-// reached distance j0.  The near part (d < j0) uses the exact weights.  One thread per
-// (instance, coefficient), the nodes in ascending order, eight nodes' states in flight; the
+// reached distance j0.  The near part (d < j0) uses the exact weights.  One work-group per
+// (instance, 128 coefficients), two adjacent coefficients per lane (16-byte loads); its four
+// waves split the nodes into four contiguous ranges (fixed by the node count) and wave 0 also
+// forms the near part; the wave partials of the far sum are added as (0 + 1) + (2 + 3).  The
 // state goes to HBM between steps (B * soeL * Mp doubles).
-__global__ __launch_bounds__(64) void k_history_soe(Tables tb, StepArgs a, double* hist) {
-  const int u = blockIdx.x, k = blockIdx.y * 64 + threadIdx.x;
-  if (k >= tb.Mp) return;
+constexpr int SL = 64;  // lanes per wave, two coefficients each
+constexpr int SW = 4;   // waves (node ranges) per work-group
+static_assert(SW == 4, "the wave partials are added as (0 + 1) + (2 + 3)");
+
+__global__ __launch_bounds__(SL * SW) void k_history_soe(Tables tb, StepArgs a, double* hist) {
+  __shared__ h2 red[SW][SL];
+  const int u = blockIdx.x, lane = threadIdx.x & (SL - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / SL);
+  const int Mp = tb.Mp, k = blockIdx.y * (2 * SL) + 2 * lane;
+  const bool in = k < Mp;
+  const int kk = in ? k : 0;  // lanes past Mp work on coefficients 0, 1 and store nothing
   const UnitView v = decode_unit(tb, a, u);
-  const int Mp = tb.Mp, m = a.m, L = tb.soeL;
-  const double* y = v.y + k;
+  const int m = a.m, L = tb.soeL;
+  const double* y = v.y + kk;
   const double* tab = tb.soe + (long)v.b * L * 3;
-  double* V = a.soeV + (long)v.b * L * Mp + k;
+  double* V = a.soeV + (long)v.b * L * Mp + kk;
   const int inew = m + 1 - kSoeJ0;
-  const double d = inew >= 1 ? y[(long)inew * Mp] - y[(long)(inew - 1) * Mp] : 0.0;
-  double far = 0.0;
-  int l = 0;
-  for (; l + 7 < L; l += 8) {
-    double s[8];
+  h2 d = {0.0, 0.0};
+  if (inew >= 1)
+    d = *reinterpret_cast<const h2*>(y + (long)inew * Mp) - *reinterpret_cast<const h2*>(y + (long)(inew - 1) * Mp);
+  const int len = (L + SW - 1) / SW, l0 = wave * len, l1 = min(L, l0 + len);
+  h2 far = {0.0, 0.0};
+  int l = l0;
+  for (; l + 3 < l1; l += 4) {
+    h2 s[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s[q] = V[(long)(l + q) * Mp];
+    for (int q = 0; q < 4; ++q) s[q] = *reinterpret_cast<const h2*>(V + (long)(l + q) * Mp);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const double* t = tab + (l + q) * 3;
       if (inew >= 1) {
-        s[q] = t[1] * s[q] + t[2] * d;
-        V[(long)(l + q) * Mp] = s[q];
+        s[q].x = t[1] * s[q].x + t[2] * d.x;
+        s[q].y = t[1] * s[q].y + t[2] * d.y;
+        if (in) *reinterpret_cast<h2*>(V + (long)(l + q) * Mp) = s[q];
       }
-      far = fma(t[0], s[q], far);
+      far.x = fma(t[0], s[q].x, far.x);
+      far.y = fma(t[0], s[q].y, far.y);
     }
   }
-  for (; l < L; ++l) {
+  for (; l < l1; ++l) {
     const double* t = tab + l * 3;
-    double sl = V[(long)l * Mp];
+    h2 sl = *reinterpret_cast<const h2*>(V + (long)l * Mp);
     if (inew >= 1) {
-      sl = t[1] * sl + t[2] * d;
-      V[(long)l * Mp] = sl;
+      sl.x = t[1] * sl.x + t[2] * d.x;
+      sl.y = t[1] * sl.y + t[2] * d.y;
+      if (in) *reinterpret_cast<h2*>(V + (long)l * Mp) = sl;
     }
-    far = fma(t[0], sl, far);
+    far.x = fma(t[0], sl.x, far.x);
+    far.y = fma(t[0], sl.y, far.y);
   }
+  red[wave][lane] = far;
+  __syncthreads();
+  if (wave != 0 || !in) return;
+  const h2 farsum = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
   const double* bw = tb.bw + (long)v.b * tb.LB;
-  double near = 0.0;
-  for (int i = inew + 1 > 1 ? inew + 1 : 1; i <= m; ++i)
-    near = fma(bw[m + 1 - i], y[(long)i * Mp] - y[(long)(i - 1) * Mp], near);
-  hist[(long)u * Mp + k] = y[(long)m * Mp] - (far + near);
+  h2 near = {0.0, 0.0};
+  for (int i = inew + 1 > 1 ? inew + 1 : 1; i <= m; ++i) {
+    const h2 di = *reinterpret_cast<const h2*>(y + (long)i * Mp) - *reinterpret_cast<const h2*>(y + (long)(i - 1) * Mp);
+    near.x = fma(bw[m + 1 - i], di.x, near.x);
+    near.y = fma(bw[m + 1 - i], di.y, near.y);
+  }
+  const h2 ym = *reinterpret_cast<const h2*>(y + (long)m * Mp);
+  *reinterpret_cast<h2*>(hist + (long)u * Mp + k) = ym - (farsum + near);
 }
 
 hipError_t launch_history(const Tables& tb, const StepArgs& a, int units, double* hist,
                           hipStream_t s) {
   if (a.mode == MODE_FULL && tb.soe) {
-    k_history_soe<<<dim3(units, (tb.Mp + 63) / 64), 64, 0, s>>>(tb, a, hist);
+    if (tb.Mp % 2 != 0) return hipErrorInvalidValue;
+    k_history_soe<<<dim3(units, (tb.Mp + 2 * SL - 1) / (2 * SL)), SL * SW, 0, s>>>(tb, a, hist);
     return hipGetLastError();
   }
   const bool full = a.mode == MODE_FULL || (a.mode == MODE_FINE && a.prev);

@@ -392,7 +392,28 @@ __global__ void k_colstats(const float* x, int ld, int n, float* mean, float* sd
   if (threadIdx.x == 0) {
     const double var = r2[0] / n;
     mean[c] = (float)mu;
-    sd[c] = var > 0.0 ? (float)sqrt(var) : 1.0f;
+    sd[c] = var > 0.0 ? (float)sqrt(var) : 0.0f;  // 0: no spread (set by k_floor_scale)
+  }
+}
+
+// Input scales: a column with no spread gets 1; the coefficient columns (c < ncoef) are
+// floored at frac times the largest coefficient scale, so that inputs that barely vary (modes
+// the training states hardly excite) are not magnified into the network: their variation
+// between parareal iterates would otherwise move its output far more than the state moves.
+__global__ void k_floor_scale(float* sd, int ncoef, int ncols, float frac) {
+  __shared__ float red[256];
+  float mx = 0.f;
+  for (int c = threadIdx.x; c < ncoef; c += 256) mx = fmaxf(mx, sd[c]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const float lo = frac * red[0];
+  for (int c = threadIdx.x; c < ncols; c += 256) {
+    const float v = sd[c];
+    sd[c] = v == 0.f ? 1.f : (c < ncoef ? fmaxf(v, lo) : v);
   }
 }
 
@@ -462,7 +483,8 @@ __global__ void k_norm_f64(const double* x, int ldx, int ncols, int n, const flo
 __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstride, const double* O,
                                                      int outp, int M, int Mp, const float* om,
                                                      const float* osd, Epilogue ep,
-                                                     const int32_t* done, const double* inst) {
+                                                     const int32_t* done, const double* inst,
+                                                     const int32_t* lg_off) {
   const int u = blockIdx.x;
   if (done && done[u]) return;  // a finished parareal instance keeps its slice ends
   {
@@ -491,7 +513,8 @@ __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstri
     }
     __syncthreads();
   }
-  const bool use = (bad == 0) && isfinite(rc[0]) && sqrt(rc[0]) <= sqrt(rg[0]) + 1.0;
+  const bool use = (bad == 0) && isfinite(rc[0]) && sqrt(rc[0]) <= sqrt(rg[0]) + 1.0 &&
+                   !(lg_off && lg_off[u]);
   for (int k = threadIdx.x; k < Mp; k += blockDim.x) {
     double x = G[u * gstride + k];
     if (use && k < M) x = x + (O[(long)u * outp + k] * (double)osd[k] + (double)om[k]);
@@ -636,7 +659,8 @@ hipError_t mlp_forward_ws(const MlpLayout& L, const char* params, int n, MlpWs& 
 // learned correction and epilogue for B units whose plain coarse values are in G
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,
-                            const Epilogue& ep, void* ws, hipStream_t s, const int32_t* done) {
+                            const Epilogue& ep, void* ws, hipStream_t s, const int32_t* done,
+                            const int32_t* lg_off) {
   if (M > L.out) return hipErrorInvalidValue;  // the network covers at least the batch's modes
   const char* pp = (const char*)params;
   const InferWs W = carve_infer(L, B, ws);
@@ -646,7 +670,7 @@ hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double
   hipError_t r = mlp_forward_f64(L, pp, B, W.X, W.Ha, W.Hb, W.O, s);
   if (r != hipSuccess) return r;
   k_infer_apply<<<B, 256, 0, s>>>(G, gstride, W.O, L.outp, M, Mp, (const float*)(pp + L.out_mean),
-                                  (const float*)(pp + L.out_std), ep, done, inst);
+                                  (const float*)(pp + L.out_std), ep, done, inst, lg_off);
   return hipGetLastError();
 }
 
@@ -716,6 +740,7 @@ l1pr_status l1pr_mlp_stats(int32_t modes, const float* x, const float* t, int64_
   char* p = (char*)params;
   hipStream_t s = (hipStream_t)stream;
   k_colstats<<<L.in, 256, 0, s>>>(x, L.in, (int)n, (float*)(p + L.in_mean), (float*)(p + L.in_std));
+  k_floor_scale<<<1, 256, 0, s>>>((float*)(p + L.in_std), modes, L.in, 1e-4f);
   k_colstats<<<L.out, 256, 0, s>>>(t, L.out, (int)n, (float*)(p + L.out_mean), (float*)(p + L.out_std));
   // one output scale for every mode: the root mean square of the per-mode deviations, so the
   // loss weighs each mode by its absolute contribution to the error of the state

@@ -256,7 +256,8 @@ hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* 
 __global__ __launch_bounds__(256) void k_increment(const double* Znew, const double* Zold, int rows,
                                                    int Mp, double* incr_out, int incr_stride, int k,
                                                    double* incr_k, int32_t* done, int32_t* conv,
-                                                   double exit_tol, int* flag) {
+                                                   double exit_tol, int* flag, int32_t* lg_off,
+                                                   double* incr_prev) {
   __shared__ double sd[256], su[256];
   const int b = blockIdx.x, tid = threadIdx.x;
   const long per = (long)rows * Mp;
@@ -293,6 +294,11 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
         if (done) done[b] = 1;
         if (conv) conv[b] = k + 1;
       }
+      // learned coarse step: off for good after a sweep that did not contract
+      if (lg_off) {
+        if (k >= 1 && rel > incr_prev[b]) lg_off[b] = 1;
+        incr_prev[b] = rel;
+      }
     }
   }
 }
@@ -300,9 +306,9 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
                             int32_t* done, int32_t* conv, double exit_tol, int* flag,
-                            hipStream_t s) {
+                            hipStream_t s, int32_t* lg_off, double* incr_prev) {
   k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k, done,
-                                conv, exit_tol, flag);
+                                conv, exit_tol, flag, lg_off, incr_prev);
   return hipGetLastError();
 }
 

@@ -191,3 +191,41 @@ def training_data(p, u0: torch.Tensor, alphas, model: LearnedCoarse, chunk: int 
                 del U, G, F, Zf
             del its
     return torch.cat(xs), torch.cat(ts)
+
+
+def _pad_modes(X: torch.Tensor, modes: int) -> torch.Tensor:
+    """[..., M] -> [..., modes] with zero coefficients appended (the modes a problem does not
+    carry; its coarse and fine values are exactly zero there)."""
+    M = X.shape[-1]
+    if M == modes:
+        return X.contiguous()
+    out = torch.zeros(X.shape[:-1] + (modes,), dtype=X.dtype, device=X.device)
+    out[..., :M] = X
+    return out
+
+
+def training_data_padded(p, u0: torch.Tensor, alphas, model: LearnedCoarse, sweeps: int = 0):
+    """training_data for a problem with fewer modes than the network: the slice ends, coarse
+    and fine values of the problem are padded with zero coefficients up to model.modes before
+    the features are formed, so one network can serve batches of several mode counts
+    (uneven batches).  Same row order as training_data."""
+    xs, ts = [], []
+    al = [float(a) for a in alphas]
+    ad = torch.tensor(al, dtype=torch.float64, device=u0.device)
+    Z, _ = solve_serial(p, u0, alpha=al)
+    G = coarse_apply(p, Z, alpha=al)
+    x, t = model.features(p, _pad_modes(Z, model.modes), _pad_modes(G, model.modes), ad)
+    xs.append(x)
+    ts.append(t)
+    if sweeps > 0:
+        its = solve_parareal(p, u0, sweeps, tol=0.0, alpha=al, want_iterates=True,
+                             want_incr=False).iterates
+        for k in range(min(sweeps, its.shape[0])):
+            U = its[k].contiguous()
+            G = coarse_apply(p, U, alpha=al)
+            F = fine_apply(p, U, alpha=al)
+            Zf = torch.cat([U[:, :1], F], dim=1)
+            x, t = model.features(p, _pad_modes(Zf, model.modes), _pad_modes(G, model.modes), ad)
+            xs.append(x)
+            ts.append(t)
+    return torch.cat(xs), torch.cat(ts)
