@@ -46,26 +46,36 @@ __device__ inline double rowbc(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Tile ownership: wave w owns the whole tile-rows w and nt-1-w of the lower triangle
-// (w + 1 + nt - w = nt + 1 <= 17 tiles), so slot s maps to (I, K) with scalar arithmetic.
+// Tile ownership: wave w owns the whole tile-rows ra = w and rb = nt-1-w of the lower
+// triangle (w + 1 + nt - w = nt + 1 <= 17 tiles).  Its diagonal tiles come first, in slots 0
+// (ra, ra) and 1 (rb, rb), so the code that picks a wave's diagonal tile chooses between two
+// slots; then row ra's tiles (ra, K) in slots nd + K and row rb's (rb, K) in slots nd + ra + K
+// (nd = number of diagonal slots), all with scalar arithmetic.
 __device__ inline void slot_tile(int s, int wave, int nt, int& I, int& K) {
   const int ra = wave, rb = nt - 1 - wave;
   I = -1;
   K = -1;
   if (ra > rb) return;
-  if (s <= ra) {
+  const int nd = (ra < rb) ? 2 : 1;
+  if (s == 0) {
     I = ra;
-    K = s;
-  } else if (ra < rb && s <= ra + 1 + rb) {
+    K = ra;
+  } else if (s < nd) {
     I = rb;
-    K = s - ra - 1;
+    K = rb;
+  } else if (s < nd + ra) {
+    I = ra;
+    K = s - nd;
+  } else if (ra < rb && s < nd + ra + rb) {
+    I = rb;
+    K = s - nd - ra;
   }
 }
 
-// owner wave and slot of the diagonal tile (j, j)
+// owner wave and slot (0 or 1) of the diagonal tile (j, j)
 __device__ inline void diag_owner(int j, int nt, int& w, int& s) {
   w = j < nt - 1 - j ? j : nt - 1 - j;
-  s = (w == j) ? j : w + 1 + j;
+  s = (w == j) ? 0 : 1;
 }
 
 #define SLOT_FENCE() __builtin_amdgcn_sched_barrier(0)
@@ -168,9 +178,12 @@ __device__ inline double lane_uniform(double v, int src) {
 // caller's 16-lane row (DPP broadcast).
 // Work that is zero by structure is skipped: at step p the pivot column of the A half is only
 // needed in rows >= p (rows above feed nothing that is read again), and the pivot column of
-// the I half is zero below row p.
+// the I half is zero below row p.  The A half goes first, alone: its steps are the pivot chain,
+// and leaving the I half out of them halves the instructions each step issues.  The I half
+// then replays the 16 column operations with the kept multipliers; the pivots (the column
+// scales) are read off the eliminated A half at the end.
 struct DiagFactor {
-  double a[4], w[4], sc;  // sc: the pivot of this lane's column, then 1/sqrt of it
+  double a[4], w[4], mm[16], sc;  // mm: multipliers of each step; sc: the pivot of this lane's column
 
   __device__ __attribute__((always_inline)) void init(const d4& t, int lane) {
     const int lr = lane >> 4, lc = lane & 15;
@@ -182,18 +195,33 @@ struct DiagFactor {
     sc = 1.0;
   }
 
+  // step P on the A half only (the pivot chain); the multipliers are kept for the I half
   template <int P>
   __device__ __attribute__((always_inline)) void step(int lane) {
     const int lc = lane & 15;
     const double piv = lane_uniform(a[P / 4], (P % 4) * 16 + P);
     const double rowp = lane_read(a[P / 4], (P % 4) * 16 + lc);
-    // the next pivot waits on m only; the column scale 1/sqrt(a_pp) is formed at the end
     const double m = (lc > P) ? rowp * rcp_nr(piv) : 0.0;
-    sc = (lc == P) ? piv : sc;
+    mm[P] = m;
 #pragma unroll
     for (int v = P / 4; v < 4; ++v) a[v] = fma(-rowbc<P>(a[v]), m, a[v]);
+  }
+  // step P on the I half: the same column operation with the kept multipliers (it reads only
+  // the I half, so it can follow all of the A steps; each entry sees the same operations in
+  // the same order)
+  template <int P>
+  __device__ __attribute__((always_inline)) void stepw() {
 #pragma unroll
-    for (int v = 0; v <= P / 4; ++v) w[v] = fma(-rowbc<P>(w[v]), m, w[v]);
+    for (int v = 0; v <= P / 4; ++v) w[v] = fma(-rowbc<P>(w[v]), mm[P], w[v]);
+  }
+  // the pivot of this lane's column c: entry (c, c), which no step after c changes
+  __device__ __attribute__((always_inline)) void pivots(int lane) {
+    const int lc = lane & 15;
+    const int src = (lc & 3) * 16 + lc;
+    const double p0 = lane_read(a[0], src), p1 = lane_read(a[1], src);
+    const double p2 = lane_read(a[2], src), p3 = lane_read(a[3], src);
+    const int q = lc >> 2;
+    sc = q == 0 ? p0 : (q == 1 ? p1 : (q == 2 ? p2 : p3));
   }
 
   // W in the accumulator layout; also published in A-operand order,
@@ -217,7 +245,11 @@ struct DiagFactor {
   DF.step<6>(lane); BETWEEN(6) DF.step<7>(lane); BETWEEN(7) DF.step<8>(lane); BETWEEN(8)    \
   DF.step<9>(lane); BETWEEN(9) DF.step<10>(lane); BETWEEN(10) DF.step<11>(lane);           \
   BETWEEN(11) DF.step<12>(lane); BETWEEN(12) DF.step<13>(lane); BETWEEN(13)                \
-  DF.step<14>(lane); BETWEEN(14) DF.step<15>(lane); BETWEEN(15)
+  DF.step<14>(lane); BETWEEN(14) DF.step<15>(lane); BETWEEN(15)                            \
+  DF.pivots(lane);                                                                         \
+  DF.stepw<0>(); DF.stepw<1>(); DF.stepw<2>(); DF.stepw<3>(); DF.stepw<4>(); DF.stepw<5>();  \
+  DF.stepw<6>(); DF.stepw<7>(); DF.stepw<8>(); DF.stepw<9>(); DF.stepw<10>(); DF.stepw<11>(); \
+  DF.stepw<12>(); DF.stepw<13>(); DF.stepw<14>(); DF.stepw<15>();
 
 // Right-looking Cholesky of the nt x nt tile lower triangle that the waves hold in `acc`
 // (transposed tiles, slot ownership as in slot_tile), with the forward substitution of the
@@ -232,7 +264,7 @@ __device__ __attribute__((always_inline)) inline void factor_tiles(d4 (&acc)[RNS
   {
     int wd, sdg;
     diag_owner(0, nt, wd, sdg);
-    if (wave == wd) {  // the owner of tile-row 0 keeps (0, 0) in slot 0
+    if (wave == wd) {  // wave 0 keeps (0, 0) in slot 0
       DiagFactor df;
       df.init(acc[0], lane);
 #define L1PR_NOTHING(P)
@@ -281,10 +313,7 @@ __device__ __attribute__((always_inline)) inline void factor_tiles(d4 (&acc)[RNS
     int wd1 = -1, sd1 = -1;
     if (j1 < nt) diag_owner(j1, nt, wd1, sd1);
     if (wave == wd1) {
-      d4 t = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < RNS; ++s)
-        if (s == sd1) t = acc[s];
+      d4 t = (sd1 == 0) ? acc[0] : acc[1];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double px = sP[(j1 * 4 + v) * 64 + lane];
@@ -296,9 +325,10 @@ __device__ __attribute__((always_inline)) inline void factor_tiles(d4 (&acc)[RNS
       L1PR_DIAG_STEPS(df, L1PR_NOTHING)
 #undef L1PR_NOTHING
       t = df.finish(lane, sWA);
-#pragma unroll
-      for (int s = 0; s < RNS; ++s)
-        if (s == sd1) acc[s] = t;
+      if (sd1 == 0)
+        acc[0] = t;
+      else
+        acc[1] = t;
     } else {
       // right-hand side below the block: b_i -= L_ij y_j
       const int nthr = (wd1 >= 0) ? RT - 64 : RT;
@@ -469,10 +499,7 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       double z[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) z[v] = sb[j0 + lr + 4 * v];
-      d4 X = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < RNS; ++s)
-        if (s == sdg) X = acc[s];
+      const d4 X = (sdg == 0) ? acc[0] : acc[1];
       double pr = 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) pr += X[v] * z[v];
@@ -483,9 +510,10 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
       double xv[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) xv[v] = sb[j0 + lr + 4 * v];
-      // nearest block first.  Slots of row ra are s = K, of row rb (when rb > ra)
-      // s = ra + 1 + K, so the slot range of row j is known without decoding every slot.
-      const int s_lo = (pass == 0 && ra < rb) ? ra + 1 : 0;  // slot of (j, 0)
+      // nearest block first.  Slots of row ra are s = nd + K, of row rb (when rb > ra)
+      // s = nd + ra + K, so the slot range of row j is known without decoding every slot.
+      const int nd = (ra < rb) ? 2 : 1;
+      const int s_lo = (pass == 0 && ra < rb) ? nd + ra : nd;  // slot of (j, 0)
 #pragma unroll
       for (int s = RNS - 1; s >= 0; --s) {
         if (s >= s_lo && s < s_lo + j) {
