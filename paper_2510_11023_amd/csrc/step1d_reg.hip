@@ -427,11 +427,23 @@ __global__ __launch_bounds__(RT) void k_chol_reg(Tables tb, StepArgs a, Epilogue
     if (tid + RT < Jm) sm[tid + RT] = m1;
     __syncthreads();
     const double pi2 = kPi * kPi;
+    const double tpi2 = tau * pi2;
 #pragma unroll
     for (int s = 0; s < RNS; ++s) {
       int tI, tK;
       slot_tile(s, wave, nt, tI, tK);
       if (tI < 0) continue;
+      if (tI > tK && 16 * tI + 16 <= Mb) {
+        // strictly below the diagonal with every row inside the instance's modes: k > l, so
+        // the entries e read m_{k-l} at k - l0 - 4e and m_{k+l+2} at k + l0 + 2 + 4e
+        const int k = tI * 16 + lc, l0 = tK * 16 + lr;
+        const double ck = tpi2 * (double)(k + 1);
+        const double* pd = sm + (k - l0 - 12);
+        const double* ps = sm + (k + l0 + 2);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[s][e] = ck * (double)(l0 + 1 + 4 * e) * (pd[12 - 4 * e] + ps[4 * e]);
+        continue;
+      }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = tI * 16 + lc, l = tK * 16 + lr + 4 * e;
