@@ -236,9 +236,13 @@ enum { L1PR_COARSE_L1 = 0,       /* the coarse L1 step G of Section 2.1 */
  *              256-byte aligned).  The network is a deterministic function of its input, so
  *              parareal keeps its exactness (after k sweeps the first k+1 slice ends equal
  *              the serial solution).  The plain coarse step is the fallback: a unit whose
- *              correction is not finite or larger than ||G_n|| + 1 uses the plain G_n, and an
- *              instance whose increment grows from one sweep to the next (the learned
- *              iteration is not contracting) uses the plain coarse step from then on.
+ *              correction is not finite or larger than ||G_n|| + 1 uses the plain G_n.  The
+ *              plain step also judges the learned one per instance: after the first fine
+ *              sweep an instance whose learned coarse values are not closer to the fine
+ *              results F_n than the plain ones, and later an instance whose increment
+ *              shrinks by less than half from one sweep to the next, goes back to the plain
+ *              coarse step for good, its stored coarse values replaced by the plain ones (its
+ *              iteration is then exactly plain parareal).
  *              ws_bytes must then also cover l1pr_parareal_learned_extra_bytes(p, batch).
  *   iters    : device int32 [batch] or NULL: each instance's status after the call: the
  *              number of sweeps after which it was finished (tol > 0) or that it ran (tol <= 0,

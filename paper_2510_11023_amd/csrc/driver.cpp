@@ -637,15 +637,19 @@ l1pr_status serial_full(const Ctx& c, const double* u0, double* U, double* traj_
 struct Learned {
   const void* params = nullptr;
   MlpLayout L{};
-  double* G = nullptr;  // [B][Mp]
+  double* G = nullptr;   // [B][Mp]: the plain coarse values of the current step
+  double* Gp = nullptr;  // [B][P][Mp]: the plain coarse value behind each stored G_old(n)
   void* ws = nullptr;
 };
 
-// Scratch of the learned coarse step: the plain G values and the inference activations of a
-// network of up to kMlpMaxModes modes (a network may cover more modes than the batch).
+// Scratch of the learned coarse step: the plain G values of the current step and of every
+// stored G_old(n), and the inference activations of a network of up to kMlpMaxModes modes (a
+// network may cover more modes than the batch).
 size_t learned_extra_bytes(const Tables& tb) {
   const MlpLayout L = mlp_layout(kMlpMaxModes);
-  return (sizeof(double) * (size_t)tb.B * tb.Mp + 255) / 256 * 256 + mlp_infer_ws_bytes(L, tb.B);
+  return (sizeof(double) * (size_t)tb.B * tb.Mp + 255) / 256 * 256 +
+         (sizeof(double) * (size_t)tb.B * tb.P * tb.Mp + 255) / 256 * 256 +
+         mlp_infer_ws_bytes(L, tb.B);
 }
 
 // The learned coarse step of a parareal call: network `params` for `mnet` >= M modes (1D,
@@ -657,8 +661,12 @@ l1pr_status make_learned(const Ctx& c, const void* params, int mnet, size_t ws_b
   if (ws_bytes < c.L.total + learned_extra_bytes(c.tb)) return L1PR_ENOMEM;
   lg.params = params;
   lg.L = mlp_layout(mnet);
-  lg.G = c.ptr(c.L.total);
-  lg.ws = c.ws + c.L.total + (sizeof(double) * (size_t)c.tb.B * c.tb.Mp + 255) / 256 * 256;
+  size_t off = c.L.total;
+  lg.G = c.ptr(off);
+  off += (sizeof(double) * (size_t)c.tb.B * c.tb.Mp + 255) / 256 * 256;
+  lg.Gp = c.ptr(off);
+  off += (sizeof(double) * (size_t)c.tb.B * c.tb.P * c.tb.Mp + 255) / 256 * 256;
+  lg.ws = c.ws + off;
   return L1PR_OK;
 }
 
@@ -677,9 +685,14 @@ l1pr_status coarse_step(const Ctx& c, double* Z, int n, const Epilogue& e, const
   tmp.out_stride = c.tb.Mp;
   l1pr_status st = run_step(c, a, tmp, c.tb.B);
   if (st != L1PR_OK) return st;
+  // where G_old(n) is stored, its plain value goes to Gp(n): the fallback to the plain coarse
+  // step can then restore a plain G_old exactly
+  const bool keeps_gold = e.kind == EPI_STORE2 || e.kind == EPI_CORRECT;
+  double* gp = (keeps_gold && lg->Gp) ? lg->Gp + (long)n * c.tb.Mp : nullptr;
   L1PR_TRY(timed("mlp", a, c.tb.B, c.s, [&] {
     return mlp_coarse_apply(lg->L, lg->params, lg->G, c.tb.Mp, c.tb.inst, c.tb.B, c.tb.M, c.tb.Mp,
-                            n, c.tb.P, e, lg->ws, c.s, c.done, c.lg_off);
+                            n, c.tb.P, e, lg->ws, c.s, c.done, c.lg_off, gp,
+                            (long)c.tb.P * c.tb.Mp);
   }));
   return L1PR_OK;
 }
@@ -774,10 +787,12 @@ l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, d
 
   L1PR_TRY(launch_fill_int(done, B, 0, c.s));
   L1PR_TRY(launch_fill_int(conv, B, -1, c.s));
-  // learned coarse step: an instance whose increment grows from one sweep to the next goes
-  // back to the plain coarse step for good (the first k+1 slice ends after k sweeps stay the
-  // serial ones whatever the coarse step is; from the next sweep on its iteration is plain
-  // parareal)
+  // learned coarse step: an instance goes back to the plain coarse step for good when, after
+  // the first fine sweep, its learned coarse values are not closer to the fine results than the
+  // plain ones, or when a later sweep shrinks its increment by less than half; its stored
+  // G_old then become the plain values, so from the next sweep on its iteration is exactly
+  // plain parareal (the first k+1 slice ends after k sweeps stay the serial ones whatever the
+  // coarse step is)
   int32_t* lgoff = lg ? reinterpret_cast<int32_t*>(c.ws + c.L.lgoff) : nullptr;
   if (lgoff) L1PR_TRY(launch_fill_int(lgoff, B, 0, c.s));
   c.lg_off = lgoff;
@@ -813,6 +828,10 @@ l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, d
     const int n_lo = prev ? 0 : std::min(k, P - 1);
     l1pr_status stf = fine_sweep(c, Zk, traj, prev, n_lo);
     if (stf != L1PR_OK) return stf;
+    // learned coarse step, first sweep: the plain step judges it against the fine results
+    if (lg && k == 0)
+      L1PR_TRY(launch_learned_judge(traj + (long)S * Mp, slotS, Gold, lg->Gp, B, P, Mp, done,
+                                    lgoff, c.s));
     // sequential sweep: U^{k+1}_{n+1} = F_old(n) + (G_n(U^{k+1}_0..U^{k+1}_n) - G_old(n)).
     // For n <= k the inputs of G_n are the converged slice ends, the same as when G_old(n) was
     // formed, so the bracket is exactly zero: those rows are F_old(n), copied, and G_old(n)
@@ -836,7 +855,8 @@ l1pr_status parareal(const Ctx& c0, const double* u0, double* U, int max_iter, d
       if (st != L1PR_OK) return st;
     }
     L1PR_TRY(launch_increment(Zk1, Zk, B, P + 1, Mp, incr, max_iter, k, incrk, done, conv,
-                              exit_tol, tb.flag, c.s, lgoff, c.ptr(c.L.incrp)));
+                              exit_tol, tb.flag, c.s, lgoff, c.ptr(c.L.incrp), Gold,
+                              lg ? lg->Gp : nullptr, (long)P * Mp));
     if (tr.stamps) L1PR_TRY(launch_stamp(tr.stamps + k + 1, c.s));
     if (U_iters)
       L1PR_TRY(launch_unpack(Zk1, Mp, vecP, U_iters + (long)(k + 1) * iterStride, M,

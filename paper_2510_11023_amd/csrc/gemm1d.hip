@@ -7,8 +7,9 @@
 //   k_history1d      hist = y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1})
 //                           [- S^-a sum_{i=1}^{n} b_{n-i+r/S} (C_i - C_{i-1})   (fine steps)].
 // The GEMMs tile 64 units x 64 columns per work-group (four waves, 2x2 MFMA 16x16x4 tiles
-// each) and stream the shared table through LDS in chunks of 16 rows, so each table is read
-// once per 64 units instead of once per unit.  An output element is a fixed-order sum over
+// each) and stream the shared table through LDS in chunks of 32 rows (the next chunk loaded
+// into registers while the current one is multiplied), so each table is read once per 64
+// units instead of once per unit.  An output element is a fixed-order sum over
 // its own row only, so a unit's values do not depend on the other units of the launch.
 #include "l1pr_internal.h"
 
@@ -17,7 +18,7 @@ namespace l1pr {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;   // units and columns per work-group tile
-constexpr int GK = 16;   // reduction chunk
+constexpr int GK = 32;   // reduction chunk
 
 // Row pointer of the lagged state of unit u.
 __device__ inline const double* lag_row(const Tables& tb, const StepArgs& a, int u) {
@@ -26,7 +27,10 @@ __device__ inline const double* lag_row(const Tables& tb, const StepArgs& a, int
 }
 
 // C[u][n] = sum_k Arow(u)[k] * B[k][n] for a 64 x 64 tile; returns the accumulators.
-// A rows come from `rowp(u)` (nullptr rows read as zero), B is [K][ldb] row-major.
+// A rows come from `rowp(u)` (nullptr rows read as zero), B is [K][ldb] row-major.  The
+// reduction runs in chunks of GK rows through LDS; each thread holds its share of the next
+// chunk in registers, loaded from global memory while the current chunk's MFMAs run.  Entries
+// past K are zeros.  The k-steps of 4 are accumulated in ascending order whatever GK is.
 template <class RowFn>
 __device__ inline void tile_gemm(RowFn rowp, int units, int u0, int n0, int K, const double* B,
                                  int ldb, int ncols, d4 (&acc)[2][2], double (*sA)[GK + 1],
@@ -37,22 +41,34 @@ __device__ inline void tile_gemm(RowFn rowp, int units, int u0, int n0, int K, c
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // this thread's entries of a chunk: A rows ar + 8i at column ak, B rows bk + 4i at column bc
+  constexpr int NA = GT * GK / 256, NB = GK * GT / 256;
+  const int ar = tid / GK, ak = tid % GK, bk = tid / GT, bc = tid % GT;
+  const double* arow[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int u = u0 + ar + (256 / GK) * i;
+    arow[i] = (u < units) ? rowp(u) : nullptr;
+  }
+  const bool bok = n0 + bc < ncols;
+  double ra[NA], rb[NB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) ra[i] = (arow[i] && k0 + ak < K) ? arow[i][k0 + ak] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int kk = k0 + bk + (256 / GT) * i;
+      rb[i] = (bok && kk < K) ? B[(long)kk * ldb + n0 + bc] : 0.0;
+    }
+  };
+  load(0);
   for (int k0 = 0; k0 < K; k0 += GK) {
-    for (int e = tid; e < GT * GK; e += 256) {
-      const int r = e / GK, kk = e % GK;
-      const int u = u0 + r;
-      double v = 0.0;
-      if (u < units) {
-        const double* row = rowp(u);
-        v = row[k0 + kk];
-      }
-      sA[r][kk] = v;
-    }
-    for (int e = tid; e < GK * GT; e += 256) {
-      const int kk = e / GT, c = e % GT;
-      sB[kk][c] = (n0 + c < ncols) ? B[(long)(k0 + kk) * ldb + n0 + c] : 0.0;
-    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) sA[ar + (256 / GK) * i][ak] = ra[i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sB[bk + (256 / GT) * i][bc] = rb[i];
     __syncthreads();
+    if (k0 + GK < K) load(k0 + GK);
 #pragma unroll
     for (int ks = 0; ks < GK / 4; ++ks) {
       const int kq = ks * 4 + (lane >> 4);

@@ -410,13 +410,23 @@ hipError_t launch_unpack_pad(const double* src, int M, long src_stride, double* 
 // the per-instance stop test: an unfinished instance whose increment is <= exit_tol is marked
 // done (done[b] = 1, conv[b] = k + 1); a non-finite increment marks it done with
 // conv[b] = L1PR_ENONFINITE and sets FLAG_NONFINITE.  Finished instances keep their record.
-// With lg_off set (learned coarse step), an unfinished instance whose increment exceeds its
-// previous sweep's (incr_prev) gets lg_off[b] = 1: the learned correction is off for it from
-// then on.
+// With lg_off set (learned coarse step), an unfinished instance whose increment exceeds
+// kLearnedMinContraction times its previous sweep's (incr_prev) gets lg_off[b] = 1: the learned
+// correction is off for it from then on, and its G_old rows (gold, gper doubles per instance)
+// are replaced by the plain coarse values stored in gplain.
+constexpr double kLearnedMinContraction = 0.5;
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
                             int32_t* done, int32_t* conv, double exit_tol, int* flag,
-                            hipStream_t s, int32_t* lg_off = nullptr, double* incr_prev = nullptr);
+                            hipStream_t s, int32_t* lg_off = nullptr, double* incr_prev = nullptr,
+                            double* gold = nullptr, const double* gplain = nullptr, long gper = 0);
+// After the first fine sweep of a learned parareal run: each unfinished instance on the learned
+// coarse step whose learned G_old(n) are not closer to the fine results F_old(n) (row
+// (b P + n) of fold, fold_stride apart) than the plain values gplain goes back to the plain
+// step (lg_off) with G_old replaced by the plain values.
+hipError_t launch_learned_judge(const double* fold, long fold_stride, double* gold,
+                                const double* gplain, int B, int P, int Mp, const int32_t* done,
+                                int32_t* lg_off, hipStream_t s);
 // Zdst[b] = Zsrc[b] (rows x Mp) for the finished instances
 hipError_t launch_copy_done(const double* Zsrc, double* Zdst, const int32_t* done, int B, long per,
                             hipStream_t s);

@@ -32,6 +32,7 @@ struct Epilogue;
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,
                             const Epilogue& ep, void* ws, hipStream_t s,
-                            const int32_t* done = nullptr, const int32_t* lg_off = nullptr);
+                            const int32_t* done = nullptr, const int32_t* lg_off = nullptr,
+                            double* gp = nullptr, long gpstride = 0);
 
 }  // namespace l1pr

@@ -478,13 +478,15 @@ __global__ void k_norm_f64(const double* x, int ldx, int ncols, int n, const flo
 
 // G_L = G_L1 + (O * out_std + out_mean) on the unit's own modes (k < M_b, the instance's
 // count; the network's outputs for other modes are not used); falls back to G_L1 for a unit
-// whose correction is not finite or larger than ||G_L1|| + 1.  Then the step epilogue.  One
-// work-group per unit.
+// whose correction is not finite or larger than ||G_L1|| + 1, or whose instance is marked in
+// lg_off.  Then the step epilogue; with gp set, the plain value G_L1 is also stored there.
+// One work-group per unit.
 __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstride, const double* O,
                                                      int outp, int M, int Mp, const float* om,
                                                      const float* osd, Epilogue ep,
                                                      const int32_t* done, const double* inst,
-                                                     const int32_t* lg_off) {
+                                                     const int32_t* lg_off, double* gp,
+                                                     long gpstride) {
   const int u = blockIdx.x;
   if (done && done[u]) return;  // a finished parareal instance keeps its slice ends
   {
@@ -517,6 +519,7 @@ __global__ __launch_bounds__(256) void k_infer_apply(const double* G, long gstri
                    !(lg_off && lg_off[u]);
   for (int k = threadIdx.x; k < Mp; k += blockDim.x) {
     double x = G[u * gstride + k];
+    if (gp) gp[(long)u * gpstride + k] = x;
     if (use && k < M) x = x + (O[(long)u * outp + k] * (double)osd[k] + (double)om[k]);
     if (ep.kind == EPI_CORRECT) {
       const double go = ep.gold[(long)u * ep.gold_stride + k];
@@ -660,7 +663,7 @@ hipError_t mlp_forward_ws(const MlpLayout& L, const char* params, int n, MlpWs& 
 hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double* G, long gstride,
                             const double* inst, int B, int M, int Mp, int n, int P,
                             const Epilogue& ep, void* ws, hipStream_t s, const int32_t* done,
-                            const int32_t* lg_off) {
+                            const int32_t* lg_off, double* gp, long gpstride) {
   if (M > L.out) return hipErrorInvalidValue;  // the network covers at least the batch's modes
   const char* pp = (const char*)params;
   const InferWs W = carve_infer(L, B, ws);
@@ -670,7 +673,8 @@ hipError_t mlp_coarse_apply(const MlpLayout& L, const void* params, const double
   hipError_t r = mlp_forward_f64(L, pp, B, W.X, W.Ha, W.Hb, W.O, s);
   if (r != hipSuccess) return r;
   k_infer_apply<<<B, 256, 0, s>>>(G, gstride, W.O, L.outp, M, Mp, (const float*)(pp + L.out_mean),
-                                  (const float*)(pp + L.out_std), ep, done, inst, lg_off);
+                                  (const float*)(pp + L.out_std), ep, done, inst, lg_off, gp,
+                                  gpstride);
   return hipGetLastError();
 }
 

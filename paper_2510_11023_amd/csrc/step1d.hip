@@ -257,8 +257,10 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
                                                    int Mp, double* incr_out, int incr_stride, int k,
                                                    double* incr_k, int32_t* done, int32_t* conv,
                                                    double exit_tol, int* flag, int32_t* lg_off,
-                                                   double* incr_prev) {
+                                                   double* incr_prev, double* gold,
+                                                   const double* gplain, long gper) {
   __shared__ double sd[256], su[256];
+  __shared__ int flip;
   const int b = blockIdx.x, tid = threadIdx.x;
   const long per = (long)rows * Mp;
   const double* a = Znew + b * per;
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
   }
   sd[tid] = dn;
   su[tid] = un;
+  if (tid == 0) flip = 0;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) {
@@ -294,21 +297,80 @@ __global__ __launch_bounds__(256) void k_increment(const double* Znew, const dou
         if (done) done[b] = 1;
         if (conv) conv[b] = k + 1;
       }
-      // learned coarse step: off for good after a sweep that did not contract
+      // learned coarse step: off for good after a sweep that contracted the increment by less
+      // than kLearnedMinContraction (the plain coarse step contracts by 0.1-0.3 per sweep on
+      // these problems, so a learned step that does worse is not helping)
       if (lg_off) {
-        if (k >= 1 && rel > incr_prev[b]) lg_off[b] = 1;
+        if (k >= 1 && !lg_off[b] && rel > kLearnedMinContraction * incr_prev[b]) {
+          lg_off[b] = 1;
+          flip = 1;
+        }
         incr_prev[b] = rel;
       }
     }
   }
+  // an instance back on the plain coarse step gets plain G_old values, so the next correction
+  // G_new - G_old compares like with like
+  __syncthreads();
+  if (flip && gold && gplain)
+    for (long e = tid; e < gper; e += 256) gold[b * gper + e] = gplain[b * gper + e];
+}
+
+// The learned step's judgement after the first fine sweep: for each unfinished instance still
+// on the learned step, the squared distances of the fine results F_old(n) from the learned
+// coarse values G_old(n) and from the plain ones Gp(n), summed over its slices in a fixed
+// order.  If the learned values are not closer, the instance goes back to the plain coarse
+// step for good (lg_off) with G_old replaced by the plain values.  One work-group per instance.
+__global__ __launch_bounds__(256) void k_learned_judge(const double* fold, long fold_stride,
+                                                       double* gold, const double* gplain, int P,
+                                                       int Mp, const int32_t* done,
+                                                       int32_t* lg_off) {
+  __shared__ double sl[256], sp[256];
+  __shared__ int off;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if ((done && done[b]) || lg_off[b]) return;  // uniform over the work-group
+  const long gper = (long)P * Mp;
+  double dl = 0.0, dp = 0.0;
+  for (long e = tid; e < gper; e += 256) {
+    const int n = (int)(e / Mp), k = (int)(e % Mp);
+    const double f = fold[(long)(b * P + n) * fold_stride + k];
+    const double a = f - gold[b * gper + e], c = f - gplain[b * gper + e];
+    dl += a * a;
+    dp += c * c;
+  }
+  sl[tid] = dl;
+  sp[tid] = dp;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      sl[tid] += sl[tid + w];
+      sp[tid] += sp[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    off = !(sl[0] < sp[0]);
+    if (off) lg_off[b] = 1;
+  }
+  __syncthreads();
+  if (off)
+    for (long e = tid; e < gper; e += 256) gold[b * gper + e] = gplain[b * gper + e];
+}
+
+hipError_t launch_learned_judge(const double* fold, long fold_stride, double* gold,
+                                const double* gplain, int B, int P, int Mp, const int32_t* done,
+                                int32_t* lg_off, hipStream_t s) {
+  k_learned_judge<<<B, 256, 0, s>>>(fold, fold_stride, gold, gplain, P, Mp, done, lg_off);
+  return hipGetLastError();
 }
 
 hipError_t launch_increment(const double* Znew, const double* Zold, int B, int rows, int Mp,
                             double* incr_out, int incr_stride, int k, double* incr_k,
                             int32_t* done, int32_t* conv, double exit_tol, int* flag,
-                            hipStream_t s, int32_t* lg_off, double* incr_prev) {
+                            hipStream_t s, int32_t* lg_off, double* incr_prev, double* gold,
+                            const double* gplain, long gper) {
   k_increment<<<B, 256, 0, s>>>(Znew, Zold, rows, Mp, incr_out, incr_stride, k, incr_k, done,
-                                conv, exit_tol, flag, lg_off, incr_prev);
+                                conv, exit_tol, flag, lg_off, incr_prev, gold, gplain, gper);
   return hipGetLastError();
 }
 

@@ -314,3 +314,75 @@ def test_learned_parareal_exact_with_diagonal_solve(gpu):
         assert torch.equal(res.iterates[k][:, : k + 1], Us[:, : k + 1]), k
     plain = gpu.solve_parareal(pg, u0, 0, want_iterates=True).iterates[0]
     assert not torch.equal(res.iterates[0], plain)   # the network's correction is applied
+
+
+def _constant_network(gpu, kw, sign, seeds):
+    """A network whose correction is the constant sign * (mean defect F - G of the instances
+    `seeds` at the problem's order): the last layer's weights are zero and its bias gives
+    r = sign * out_mean."""
+    from paper_2510_11023_amd.learned import LearnedCoarse, training_data
+
+    pg = gpu.make_problem(**kw)
+    model = LearnedCoarse(kw["modes"], seed=4)
+    u0 = dev(W.u0_batch_1d(kw["modes"], seeds))
+    x, t = training_data(pg, u0, [kw["alpha"]] * len(seeds), model, sweeps=1)
+    model.set_stats(x, t)
+    _, _, om, osd = model.norms()
+    flat = model.masters().copy()
+    i = model.info
+    flat[i.flat_w[3]: i.flat_w[3] + i.out_padded * i.hidden] = 0.0
+    b3 = np.zeros(i.out_padded, dtype=np.float32)
+    b3[: i.out] = (sign - 1.0) * om / osd   # O * osd + om = sign * om
+    flat[i.flat_b[3]: i.flat_b[3] + i.out_padded] = b3
+    model.set_masters(flat)
+    return model
+
+
+def _plain_sweeps_from(gpu, pg, U0, sweeps):
+    """Plain parareal sweeps from the initial iterate U0 [B][P+1][M], through the library's own
+    propagators: U_{n+1} <- F_n(U^k) + (G_n(U^{k+1}) - G_n(U^k))."""
+    its = [U0]
+    P = pg.slices
+    for _ in range(sweeps):
+        Uk = its[-1]
+        F = gpu.fine_apply(pg, Uk)
+        Gold = gpu.coarse_apply(pg, Uk)
+        Un = Uk.clone()
+        for n in range(P):
+            Gn = gpu.coarse_apply(pg, Un)[:, n]
+            Un[:, n + 1] = F[:, n] + (Gn - Gold[:, n])
+        its.append(Un)
+    return its
+
+
+def test_judge_returns_a_worse_network_to_exact_plain_parareal(gpu):
+    """After the first fine sweep the plain coarse step judges the learned one: a correction
+    that moves the coarse values away from the fine results (r = -mean defect) is dropped, the
+    stored coarse values become the plain ones, and every later sweep is exactly plain parareal
+    from the learned initial iterate (bit for bit against the library's own propagators)."""
+    kw = SMALL
+    pg = gpu.make_problem(**kw)
+    u0 = dev(W.u0_batch_1d(kw["modes"], [40, 41]))
+    worse = _constant_network(gpu, kw, -1.0, [40, 41])
+    res = gpu.solve_parareal(pg, u0, 4, want_iterates=True, coarse=gpu.COARSE_LEARNED,
+                             mlp_params=worse.params)
+    torch.cuda.synchronize()
+    plain0 = gpu.solve_parareal(pg, u0, 0, want_iterates=True).iterates[0]
+    assert not torch.equal(res.iterates[0], plain0)   # the correction was applied in sweep 0
+    ref = _plain_sweeps_from(gpu, pg, res.iterates[0].contiguous(), 4)
+    for k in range(1, 5):
+        assert torch.equal(res.iterates[k], ref[k]), k
+
+
+def test_judge_keeps_a_better_network(gpu):
+    """A correction towards the fine results (r = +mean defect) passes the judgement: the
+    sweeps after the first are not those of plain parareal from the same initial iterate."""
+    kw = SMALL
+    pg = gpu.make_problem(**kw)
+    u0 = dev(W.u0_batch_1d(kw["modes"], [40, 41]))
+    better = _constant_network(gpu, kw, 1.0, [40, 41])
+    res = gpu.solve_parareal(pg, u0, 2, want_iterates=True, coarse=gpu.COARSE_LEARNED,
+                             mlp_params=better.params)
+    torch.cuda.synchronize()
+    ref = _plain_sweeps_from(gpu, pg, res.iterates[0].contiguous(), 2)
+    assert not torch.equal(res.iterates[2], ref[2])
