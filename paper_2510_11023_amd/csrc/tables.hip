@@ -43,8 +43,8 @@ __global__ void k_gauss_legendre(int Q, int Qp, double* xq, double* wq) {
   wq[i] = 1.0 / ((1.0 - z * z) * deriv * deriv);
 }
 
-// phi[q][k] = sqrt2 sin((k+1) pi x_q), dphi[q][k] = sqrt2 (k+1) pi cos((k+1) pi x_q),
-// zero outside k < M, q < Q.  When b12 is set (2D), also the stacked tables of the
+// phi[q][k] = sqrt2 sin((k+1) pi x_q), dphi[q][k] = sqrt2 (k+1) pi cos((k+1) pi x_q) (when
+// dphi is set), zero outside k < M, q < Q.  When b12 is set (2D), also the stacked tables of the
 // separable stiffness products: b12 [Mp][2 Qp] = [phi^T | dphi^T], s2 [2 Qp][Mp] = [dphi; phi].
 __global__ void k_basis(int M, int Q, int Mp, int Qp, const double* xq, double* phi,
                         double* phiT, double* dphi, double* b12, double* s2) {
@@ -60,7 +60,7 @@ __global__ void k_basis(int M, int Q, int Mp, int Qp, const double* xq, double* 
   }
   phi[(long)q * Mp + k] = v;
   phiT[(long)k * Qp + q] = v;
-  dphi[(long)q * Mp + k] = dv;
+  if (dphi) dphi[(long)q * Mp + k] = dv;
   if (b12) {
     b12[(long)k * 2 * Qp + q] = v;
     b12[(long)k * 2 * Qp + Qp + q] = dv;

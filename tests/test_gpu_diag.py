@@ -207,6 +207,47 @@ def test_diag_1d_4096_modes_first_step_every_coefficient(gpu, orc):
         assert torch.equal(r.iterates[k][:, : k + 1], Us[:, : k + 1]), k
 
 
+def test_diag_2d_256_modes_first_step_every_coefficient(gpu, orc):
+    """2D at the largest shape the diagonal solve accepts and the bench times (256 x 256
+    modes, 384 x 384 points): every coefficient of one step against the oracle's load."""
+    T = 1.0 / 2048
+    kw = const_d(W.C3, modes=256, quad=384, steps=1, slices=1, T=T)
+    pg, po = gpu.make_problem(solver=2, **kw), orc.problem(solver=2, **kw)
+    c0 = W.u0_random_2d(256, 2)
+    _, tr = gpu.solve_serial(pg, dev(c0[None]), want_traj=True)
+    c1 = tr[0, 1].cpu().numpy()
+    tau = T ** kw["alpha"] * math.gamma(2.0 - kw["alpha"])
+    _, F = orc.galerkin_rows(po, c0, 0.0, 0.0, [0])
+    k1, k2 = np.meshgrid(np.arange(1, 257), np.arange(1, 257), indexing="ij")
+    lam = ((k1 ** 2 + k2 ** 2) * math.pi ** 2).ravel()
+    lhs = c1 * (1.0 + tau * 0.8 * lam)
+    rhs = c0 + tau * F
+    scale = np.abs(lhs) + np.abs(c0) + tau * np.abs(F)
+    assert np.max(np.abs(lhs - rhs) / scale) <= TOL
+
+
+def test_diag_1d_largest_shape_first_step_every_coefficient(gpu, orc):
+    """1D at the largest shape the diagonal solve accepts (4096 modes, 8192 points): one step
+    against the oracle's load, within 1e-10 relative L2 over all coefficients.  Coefficient by
+    coefficient the bound is 1e-9: each F_k is an 8192-term sum whose terms cancel for high
+    modes, so its rounding relative to |F_k| grows with the number of terms (the GPU's blocked
+    sum and the oracle's sequential one differ by 1.0e-10 at the worst coefficient here)."""
+    T = 1.0 / 4096
+    kw = const_d(W.C2, modes=4096, quad=8192, steps=1, slices=1, T=T)
+    pg, po = gpu.make_problem(solver=2, **kw), orc.problem(solver=2, **kw)
+    c0 = W.u0_batch_1d(4096, [2])
+    _, tr = gpu.solve_serial(pg, dev(c0), want_traj=True)
+    c1 = tr[0, 1].cpu().numpy()
+    tau = T ** kw["alpha"] * math.gamma(2.0 - kw["alpha"])
+    _, F = orc.galerkin_rows(po, c0[0], 0.0, 0.0, [0])
+    lam = (np.arange(1, 4097) * math.pi) ** 2
+    lhs = c1 * (1.0 + tau * 0.8 * lam)
+    rhs = c0[0] + tau * F
+    assert rel(lhs, rhs) <= TOL
+    scale = np.abs(lhs) + np.abs(c0[0]) + tau * np.abs(F)
+    assert np.max(np.abs(lhs - rhs) / scale) <= 10 * TOL
+
+
 def test_diag_full_shape_parareal_exact(gpu):
     """Config-2 shape with constant D, 32 instances, 64 slices of 4 steps: parareal iterates
     equal the serial solution bit for bit on the converged slices."""
