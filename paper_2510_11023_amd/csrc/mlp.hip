@@ -39,6 +39,8 @@ __device__ inline float silu_grad(float z) {
 // C[M][N] = sum_k A(i,k) B(k,j):  A(i,k) = AT ? A[k*lda+i] : A[i*lda+k],
 //                                   B(k,j) = BT ? B[j*ldb+k] : B[k*ldb+j].
 // 64x64 tile per 256-thread work-group (2x2 waves of 2x2 MFMA tiles), K in chunks of 32.
+// The operands' leading dimensions and their 16-byte vectors are aligned by the layout
+// (multiples of 32 elements, 256-byte aligned arrays).
 enum { GE_STORE = 0, GE_BIAS_ACT = 1, GE_BIAS = 2, GE_DACT = 3 };
 
 struct GemmEpi {
@@ -54,51 +56,84 @@ struct GemmEpi {
 
 constexpr int MB = 64, MK = 32;
 
+// With a split reduction (gridDim.z > 1) work-group z sums k in [z kz, (z+1) kz) and stores its
+// partial tile (GE_STORE) at ep.c32 + z M ldc; k_sum_partials adds the parts in z order.
+// Staging: per 32-wide k chunk each thread moves one 16-byte vector of A and one of B (8
+// values along the operand's contiguous dimension) into LDS, A as [i][k] and B as [j][k], so
+// each MFMA operand (4 consecutive k) is one 8-byte LDS read; the next chunk's vectors are
+// loaded into registers while the current chunk is multiplied.
+union V8 {
+  uint4 v;
+  bf16 h[8];
+};
+
 template <bool AT, bool BT>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const bf16* A, int lda, const bf16* B, int ldb,
-                                                   int M, int N, int K, GemmEpi ep) {
-  __shared__ bf16 sA[MB][MK + 4];
-  __shared__ bf16 sB[MK][MB + 4];
+                                                   int M, int N, int K, int kz, GemmEpi ep) {
+  __shared__ __align__(16) bf16 sA[MB][MK + 8];
+  __shared__ __align__(16) bf16 sB[MB][MK + 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   const int i0 = blockIdx.y * MB, j0 = blockIdx.x * MB;
+  const int kb0 = blockIdx.z * kz, kb1 = min(K, kb0 + kz);
+  if (gridDim.z > 1) ep.c32 += (long)blockIdx.z * M * ep.ldc;
+  // this thread's vectors: along k (row ar / column bc) or along i / j (k row ak / bk)
+  const int ar = AT ? (tid & 7) * 8 : tid >> 2, ak = AT ? tid >> 3 : (tid & 3) * 8;
+  const int bc = BT ? tid >> 2 : (tid & 7) * 8, bk = BT ? (tid & 3) * 8 : tid >> 3;
+  V8 va, vb;
+  auto load = [&](int k0) {
+    if (!AT) {
+      const int i = i0 + ar, k = k0 + ak;
+      if (i < M && k + 8 <= kb1) va.v = *(const uint4*)(A + (long)i * lda + k);
+      else
+        for (int e = 0; e < 8; ++e) va.h[e] = (i < M && k + e < kb1) ? A[(long)i * lda + k + e] : (bf16)0;
+    } else {
+      const int i = i0 + ar, k = k0 + ak;
+      if (k < kb1 && i + 8 <= M) va.v = *(const uint4*)(A + (long)k * lda + i);
+      else
+        for (int e = 0; e < 8; ++e) va.h[e] = (k < kb1 && i + e < M) ? A[(long)k * lda + i + e] : (bf16)0;
+    }
+    if (BT) {
+      const int j = j0 + bc, k = k0 + bk;
+      if (j < N && k + 8 <= kb1) vb.v = *(const uint4*)(B + (long)j * ldb + k);
+      else
+        for (int e = 0; e < 8; ++e) vb.h[e] = (j < N && k + e < kb1) ? B[(long)j * ldb + k + e] : (bf16)0;
+    } else {
+      const int j = j0 + bc, k = k0 + bk;
+      if (k < kb1 && j + 8 <= N) vb.v = *(const uint4*)(B + (long)k * ldb + j);
+      else
+        for (int e = 0; e < 8; ++e) vb.h[e] = (k < kb1 && j + e < N) ? B[(long)k * ldb + j + e] : (bf16)0;
+    }
+  };
   f4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += MK) {
-    for (int e = tid; e < MB * MK; e += 256) {
-      int r, kk;
-      if (AT) { kk = e / MB; r = e % MB; } else { r = e / MK; kk = e % MK; }
-      const int i = i0 + r, k = k0 + kk;
-      bf16 v = 0;
-      if (i < M && k < K) v = AT ? A[(long)k * lda + i] : A[(long)i * lda + k];
-      sA[r][kk] = v;
+  if (kb0 < kb1) load(kb0);
+  for (int k0 = kb0; k0 < kb1; k0 += MK) {
+    if (!AT) {
+      *(uint4*)&sA[ar][ak] = va.v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sA[ar + e][ak] = va.h[e];
     }
-    for (int e = tid; e < MB * MK; e += 256) {
-      int c, kk;
-      if (BT) { c = e / MK; kk = e % MK; } else { kk = e / MB; c = e % MB; }
-      const int j = j0 + c, k = k0 + kk;
-      bf16 v = 0;
-      if (j < N && k < K) v = BT ? B[(long)j * ldb + k] : B[(long)k * ldb + j];
-      sB[kk][c] = v;
+    if (BT) {
+      *(uint4*)&sB[bc][bk] = vb.v;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sB[bc + e][bk] = vb.h[e];
     }
     __syncthreads();
+    if (k0 + MK < kb1) load(k0 + MK);
 #pragma unroll
     for (int ks = 0; ks < MK / 16; ++ks) {
       const int kb = ks * 16 + 4 * (lane >> 4);
       s4 af[2], bfr[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const bf16* p = &sA[wi * 32 + a * 16 + (lane & 15)][kb];
-        af[a] = s4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-      }
+      for (int a = 0; a < 2; ++a) af[a] = *(const s4*)&sA[wi * 32 + a * 16 + (lane & 15)][kb];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int c = wj * 32 + b * 16 + (lane & 15);
-        bfr[b] = s4{(short)sB[kb][c], (short)sB[kb + 1][c], (short)sB[kb + 2][c], (short)sB[kb + 3][c]};
-      }
+      for (int b = 0; b < 2; ++b) bfr[b] = *(const s4*)&sB[wj * 32 + b * 16 + (lane & 15)][kb];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -134,12 +169,38 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const bf16* A, int lda, const
 }
 
 hipError_t gemm_bf16(bool at, bool bt, const bf16* A, int lda, const bf16* B, int ldb, int M, int N,
-                     int K, const GemmEpi& ep, hipStream_t s) {
-  dim3 grid((N + MB - 1) / MB, (M + MB - 1) / MB);
-  if (!at && !bt) k_gemm_bf16<false, false><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, ep);
-  else if (!at && bt) k_gemm_bf16<false, true><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, ep);
-  else if (at && !bt) k_gemm_bf16<true, false><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, ep);
-  else k_gemm_bf16<true, true><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, ep);
+                     int K, const GemmEpi& ep, hipStream_t s, int splits = 1) {
+  const int kz = ((K + splits - 1) / splits + MK - 1) / MK * MK;
+  dim3 grid((N + MB - 1) / MB, (M + MB - 1) / MB, splits);
+  if (!at && !bt) k_gemm_bf16<false, false><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, kz, ep);
+  else if (!at && bt) k_gemm_bf16<false, true><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, kz, ep);
+  else if (at && !bt) k_gemm_bf16<true, false><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, kz, ep);
+  else k_gemm_bf16<true, true><<<grid, 256, 0, s>>>(A, lda, B, ldb, M, N, K, kz, ep);
+  return hipGetLastError();
+}
+
+// C[i][j] = sum_z P[z][i][j] in z order (the parts of a split reduction)
+__global__ void k_sum_partials(const float* P, int parts, long mn, float* C) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  float t = 0.f;
+  for (int z = 0; z < parts; ++z) t += P[z * mn + e];
+  C[e] = t;
+}
+
+// weight gradient dW[M][N] = A^T B over the batch (K = n rows), split KSPLIT ways over the
+// batch so that a few 64 x 64 output tiles still fill the machine
+constexpr int KSPLIT = 8;
+hipError_t gemm_wgrad(const bf16* A, int lda, const bf16* B, int ldb, int M, int N, int K, float* dW,
+                      float* part, hipStream_t s) {
+  GemmEpi e{};
+  e.kind = GE_STORE;
+  e.c32 = part;
+  e.ldc = N;
+  hipError_t r = gemm_bf16(true, false, A, lda, B, ldb, M, N, K, e, s, KSPLIT);
+  if (r != hipSuccess) return r;
+  const long mn = (long)M * N;
+  k_sum_partials<<<(unsigned)((mn + 255) / 256), 256, 0, s>>>(part, KSPLIT, mn, dW);
   return hipGetLastError();
 }
 
@@ -312,13 +373,25 @@ __global__ void k_out_grad(const float* O, const float* Tn, int n, int outp, int
   if (threadIdx.x == 0) rowloss[i] = red[0];
 }
 
-// out[c] = sum_i g[i][c] (bias gradients; fixed order)
-__global__ void k_colsum_bf16(const bf16* g, int n, int ld, int ncols, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
+// out[c] = sum_i g[i][c] (bias gradients).  A work-group takes 16 columns; its 16 row groups
+// sum the rows i = r, r + 16, ... of each column, and the 16 partials are added in row-group
+// order (a fixed order).
+__global__ __launch_bounds__(256) void k_colsum_bf16(const bf16* g, int n, int ld, int ncols,
+                                                     float* out) {
+  __shared__ float red[16][17];
+  const int r = threadIdx.x >> 4, cl = threadIdx.x & 15;
+  const int c = blockIdx.x * 16 + cl;
   float s = 0.f;
-  for (int i = 0; i < n; ++i) s += from_bf16(g[(long)i * ld + c]);
-  out[c] = s;
+  if (c < ncols)
+    for (int i = r; i < n; i += 16) s += from_bf16(g[(long)i * ld + c]);
+  red[r][cl] = s;
+  __syncthreads();
+  if (r == 0 && c < ncols) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q][cl];
+    out[c] = t;
+  }
 }
 
 // loss = sum rowloss / (n * out)
@@ -548,6 +621,7 @@ size_t mlp_ws_bytes(const MlpLayout& L, int n, bool train) {
     add(2 * (size_t)n * L.hidden);                  // dZ (pong)
     add(4 * L.nflat);                               // gradients
     add(4 * (size_t)n);                             // row losses
+    add(4 * (size_t)KSPLIT * L.hidden * (L.hidden > L.inp ? L.hidden : L.inp));  // wgrad parts
   }
   return b;
 }
@@ -563,6 +637,7 @@ struct MlpWs {
   bf16* dZb;
   float* grad;
   float* rowloss;
+  float* part;
 };
 
 MlpWs carve(const MlpLayout& L, int n, bool train, void* ws) {
@@ -587,6 +662,7 @@ MlpWs carve(const MlpLayout& L, int n, bool train, void* ws) {
     W.dZb = (bf16*)take(2 * (size_t)n * L.hidden);
     W.grad = (float*)take(4 * L.nflat);
     W.rowloss = (float*)take(4 * (size_t)n);
+    W.part = (float*)take(4 * (size_t)KSPLIT * L.hidden * (L.hidden > L.inp ? L.hidden : L.inp));
   }
   return W;
 }
@@ -821,13 +897,10 @@ l1pr_status l1pr_mlp_train_step(int32_t modes, void* params, void* state, const 
   if (loss) k_loss<<<1, 256, 0, s>>>(W.rowloss, n, L.out, loss);
   // layer 4: dW4 = dO^T H3, db4 = colsum dO, dZ3 = (dO W4) * silu'(Z3)
   {
-    GemmEpi e{};
-    e.kind = GE_STORE;
-    e.c32 = W.grad + L.fw[3];
-    e.ldc = L.hidden;
-    if (gemm_bf16(true, false, W.dO, L.outp, W.H[2], L.hidden, L.outp, L.hidden, n, e, s) != hipSuccess)
+    if (gemm_wgrad(W.dO, L.outp, W.H[2], L.hidden, L.outp, L.hidden, n, W.grad + L.fw[3], W.part,
+                   s) != hipSuccess)
       return L1PR_EHIP;
-    k_colsum_bf16<<<nblk(L.outp), 256, 0, s>>>(W.dO, n, L.outp, L.outp, W.grad + L.fb[3]);
+    k_colsum_bf16<<<(L.outp + 15) / 16, 256, 0, s>>>(W.dO, n, L.outp, L.outp, W.grad + L.fb[3]);
     GemmEpi d{};
     d.kind = GE_DACT;
     d.h = W.dZa;
@@ -844,13 +917,10 @@ l1pr_status l1pr_mlp_train_step(int32_t modes, void* params, void* state, const 
   for (int l = 2; l >= 0; --l) {
     const bf16* hin = (l == 0) ? W.X0 : W.H[l - 1];
     const int kin = (l == 0) ? L.inp : L.hidden;
-    GemmEpi e{};
-    e.kind = GE_STORE;
-    e.c32 = W.grad + L.fw[l];
-    e.ldc = kin;
-    if (gemm_bf16(true, false, dz, L.hidden, hin, kin, L.hidden, kin, n, e, s) != hipSuccess)
+    if (gemm_wgrad(dz, L.hidden, hin, kin, L.hidden, kin, n, W.grad + L.fw[l], W.part, s) !=
+        hipSuccess)
       return L1PR_EHIP;
-    k_colsum_bf16<<<nblk(L.hidden), 256, 0, s>>>(dz, n, L.hidden, L.hidden, W.grad + L.fb[l]);
+    k_colsum_bf16<<<(L.hidden + 15) / 16, 256, 0, s>>>(dz, n, L.hidden, L.hidden, W.grad + L.fb[l]);
     if (l > 0) {
       GemmEpi d{};
       d.kind = GE_DACT;
