@@ -356,8 +356,10 @@ l1pr_status l1pr_device_stamp(int64_t* t, void* stream);
 
 /* Measures the variants of a fine step of `batch` instances x P slices (the parareal fine
  * sweep) and writes the fastest as tune bits: the GEMM tiles for systems of at most 256
- * coefficients (bits 0, 1), the block width and trailing-update tiles of the blocked
- * factorisation beyond (bits 2, 3); 0 for problems without a choice.
+ * coefficients (bits 0, 1; timed on the fine step and on a step of `batch` units, the serial
+ * solve's, the variant with the smaller sum chosen, since serial and parareal must use the
+ * same bits), the block width and trailing-update tiles of the blocked factorisation beyond
+ * (bits 2, 3); 0 for problems without a choice.
  * Needs a parareal workspace (ws_bytes >= l1pr_workspace_bytes(p, batch, L1PR_OP_PARAREAL));
  * synchronises the stream. */
 l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t ws_bytes,
