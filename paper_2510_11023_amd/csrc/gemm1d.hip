@@ -369,7 +369,12 @@ __device__ inline h2 chunk_sum(const double* x, long stride, int i0, int i1, WFn
 
 __global__ __launch_bounds__(HL * HW) void k_history_split(Tables tb, StepArgs a, double* hist) {
   __shared__ h2 red[2][HW][HL];
-  const int u = blockIdx.x, lane = threadIdx.x & (HL - 1);
+  // work-groups reach the 8 XCDs round robin by linear id (x fastest): with the unit count a
+  // multiple of 8, XCD x % 8 takes the contiguous eighth x % 8 of the units, so the units of an
+  // instance, which share its slice ends, read them into one XCD's L2
+  const int nu = gridDim.x;
+  const int u = (nu & 7) ? blockIdx.x : (blockIdx.x & 7) * (nu >> 3) + (blockIdx.x >> 3);
+  const int lane = threadIdx.x & (HL - 1);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / HL);
   const UnitView v = decode_unit(tb, a, u);
   // Mp is a multiple of 16, so a lane's pair is either wholly inside or wholly past it; lanes
