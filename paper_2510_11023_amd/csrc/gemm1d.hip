@@ -415,13 +415,15 @@ __global__ __launch_bounds__(HL * HW) void k_history_split(Tables tb, StepArgs a
 // V_l = sum_{i <= m+1-j0} e^{-lam_l (m+1-i)} (y_i - y_{i-1}), carried from step to step:
 // V_l <- e^{-lam_l} V_l + e^{-lam_l j0} (y_i - y_{i-1}) for the row i = m+1-j0 that has just
 // reached distance j0.  The near part (d < j0) uses the exact weights.  One work-group per
-// (instance, 128 coefficients), two adjacent coefficients per lane (16-byte loads); its four
-// waves split the nodes into four contiguous ranges (fixed by the node count) and wave 0 also
-// forms the near part; the wave partials of the far sum are added as (0 + 1) + (2 + 3).  The
-// state goes to HBM between steps (B * soeL * Mp doubles).
+// (instance, 128 coefficients), two adjacent coefficients per lane (16-byte loads); its 16
+// waves split the nodes into 16 contiguous ranges (fixed by the node count; with few nodes
+// the last ranges are empty) and wave 0 also forms the near part; the wave partials of the
+// far sum are added pairwise in a fixed tree.  Only B * Mp / 128 work-groups exist (64 at 32
+// instances of 256 modes), so the node split across 16 waves is what keeps enough loads in
+// flight.  The state goes to HBM between steps (B * soeL * Mp doubles).
 constexpr int SL = 64;  // lanes per wave, two coefficients each
-constexpr int SW = 4;   // waves (node ranges) per work-group
-static_assert(SW == 4, "the wave partials are added as (0 + 1) + (2 + 3)");
+constexpr int SW = 16;  // waves (node ranges) per work-group
+static_assert(SW == 16, "the wave partials are added pairwise in a fixed tree");
 
 __global__ __launch_bounds__(SL * SW) void k_history_soe(Tables tb, StepArgs a, double* hist) {
   __shared__ h2 red[SW][SL];
@@ -442,12 +444,12 @@ __global__ __launch_bounds__(SL * SW) void k_history_soe(Tables tb, StepArgs a, 
   const int len = (L + SW - 1) / SW, l0 = wave * len, l1 = min(L, l0 + len);
   h2 far = {0.0, 0.0};
   int l = l0;
-  for (; l + 3 < l1; l += 4) {
-    h2 s[4];
+  for (; l + 7 < l1; l += 8) {
+    h2 s[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] = *reinterpret_cast<const h2*>(V + (long)(l + q) * Mp);
+    for (int q = 0; q < 8; ++q) s[q] = *reinterpret_cast<const h2*>(V + (long)(l + q) * Mp);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const double* t = tab + (l + q) * 3;
       if (inew >= 1) {
         s[q].x = t[1] * s[q].x + t[2] * d.x;
@@ -472,7 +474,10 @@ __global__ __launch_bounds__(SL * SW) void k_history_soe(Tables tb, StepArgs a, 
   red[wave][lane] = far;
   __syncthreads();
   if (wave != 0 || !in) return;
-  const h2 farsum = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  h2 p8[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) p8[q] = red[2 * q][lane] + red[2 * q + 1][lane];
+  const h2 farsum = ((p8[0] + p8[1]) + (p8[2] + p8[3])) + ((p8[4] + p8[5]) + (p8[6] + p8[7]));
   const double* bw = tb.bw + (long)v.b * tb.LB;
   h2 near = {0.0, 0.0};
   for (int i = inew + 1 > 1 ? inew + 1 : 1; i <= m; ++i) {
