@@ -118,9 +118,9 @@ typedef struct {
                               sine basis; the same quadrature sum, 2M+1 moments instead of
                               M^2 dot products), M <= 256; larger M uses 1
                            1: quadrature GEMM dphi^T diag(w D) dphi on FP64 MFMA */
-  int32_t tune;         /* variants of the fine and full-history steps (bit 0: 64 x 64 tiles
-                           for the lagged-state product instead of 16 x 16 split-K tiles;
-                           bit 1: 16 x 16 split-K tiles for the projections instead of 64 x 64;
+  int32_t tune;         /* variants of the fine and full-history steps (bit 0: 16 x 16
+                           split-K tiles for the lagged-state product instead of 32 x 32;
+                           bit 1: 16 x 16 split-K tiles for the projections instead of 32 x 32;
                            bit 2: 128-column blocks instead of 256 in the device-memory
                            factorisation of systems with more than 256 coefficients;
                            bit 3: 64 x 64 instead of 128 x 128 tiles in its trailing

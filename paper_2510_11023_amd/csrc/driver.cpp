@@ -88,7 +88,7 @@ bool valid(const l1pr_problem* p) {
   if (p->source_time != 0 && p->source_time != 1) return false;
   if (p->source_time == 1 && (p->f_sel == L1PR_F_LOGISTIC || p->f_sel == L1PR_F_SIN)) return false;
   if (p->assembly != 0 && p->assembly != 1) return false;
-  if (p->tune < 0 || p->tune > (TUNE_LAG_TILED | TUNE_PROJ_SKINNY | TUNE_NB128 | TUNE_TRAIL64))
+  if (p->tune < 0 || p->tune > (TUNE_LAG_SKINNY | TUNE_PROJ_SKINNY | TUNE_NB128 | TUNE_TRAIL64))
     return false;
   if (p->solver < 0 || p->solver > 2) return false;
   if (p->solver == 1 && p->dim != 2) return false;  // the iterative solve is the 2D one
@@ -418,7 +418,7 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
       }));
     } else {
       const bool coarse = a.mode == MODE_COARSE;
-      const bool sk_lag = coarse || !(c.tb.tune & TUNE_LAG_TILED);
+      const bool sk_lag = coarse || (c.tb.tune & TUNE_LAG_SKINNY);
       const bool sk_proj = coarse || (c.tb.tune & TUNE_PROJ_SKINNY);
       L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, sk_lag, c.s); }));
       L1PR_TRY(timed("proj", a, units, c.s, [&] {
@@ -500,10 +500,10 @@ l1pr_status run_step(const Ctx& c, const StepArgs& a, const Epilogue& e, int uni
   if (c.reg) {
     // GEMM variants.  Coarse steps (one unit per instance) take the skinny tiles for both
     // products.  Fine and full-history steps take the variants in the problem's tuning bits
-    // (default: skinny lagged-state product, 64 x 64 projections), never a choice made from
+    // (default: 32 x 32 tiles for both products), never a choice made from
     // the unit count, so a serial solve and a parareal fine sweep do the same arithmetic.
     const bool coarse = a.mode == MODE_COARSE;
-    const bool sk_lag = coarse || !(c.tb.tune & TUNE_LAG_TILED);
+    const bool sk_lag = coarse || (c.tb.tune & TUNE_LAG_SKINNY);
     const bool sk_proj = coarse || (c.tb.tune & TUNE_PROJ_SKINNY);
     L1PR_TRY(timed("lag", a, units, c.s, [&] { return launch_lag_gemm(c.tb, a, units, a.d, a.g, sk_lag, c.s); }));
     L1PR_TRY(timed("proj", a, units, c.s, [&] {
@@ -1099,7 +1099,7 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
     L1PR_TRY(hipEventCreate(&e1));
     float best = 1e30f;
     int32_t best_t = 0;
-    for (int32_t t = 0; t <= (TUNE_LAG_TILED | TUNE_PROJ_SKINNY); ++t) {
+    for (int32_t t = 0; t <= (TUNE_LAG_SKINNY | TUNE_PROJ_SKINNY); ++t) {
       c.tb.tune = t;
       StepArgs a = base_args(c);
       a.mode = MODE_FINE;
@@ -1116,7 +1116,7 @@ l1pr_status l1pr_autotune(const l1pr_problem* p, int32_t batch, void* ws, size_t
       // over a few launches after one warm-up, on a fine step (B P units, parareal) and on a
       // step of B units (the serial solve, which the same bits govern), and take the variant
       // with the smaller sum of the two
-      const bool sk_lag = !(t & TUNE_LAG_TILED), sk_proj = (t & TUNE_PROJ_SKINNY) != 0;
+      const bool sk_lag = (t & TUNE_LAG_SKINNY) != 0, sk_proj = (t & TUNE_PROJ_SKINNY) != 0;
       float sum = 0.f;
       for (int units : {tb.B * tb.P, tb.B}) {
         float ms = 0.f;

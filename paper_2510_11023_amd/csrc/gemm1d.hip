@@ -6,10 +6,14 @@
 //                    F = g Phi (load vector F_k = sum_q w_q f_q phi_k(x_q)).
 //   k_history1d      hist = y_L - sum_{i=1}^{L} b_{L+1-i} (y_i - y_{i-1})
 //                           [- S^-a sum_{i=1}^{n} b_{n-i+r/S} (C_i - C_{i-1})   (fine steps)].
-// The GEMMs tile 64 units x 64 columns per work-group (four waves, 2x2 MFMA 16x16x4 tiles
-// each) and stream the shared table through LDS in chunks of 32 rows (the next chunk loaded
-// into registers while the current one is multiplied), so each table is read once per 64
-// units instead of once per unit.  An output element is a fixed-order sum over
+// The GEMMs tile 32 units x 32 columns per work-group (four waves, one MFMA 16x16x4 tile
+// each; tile_gemm takes any multiple of 32 in either direction) and stream the shared table
+// through LDS in chunks of 32 rows (the next chunk loaded into registers while the current one
+// is multiplied), so each table is read once per 32 units instead of once per unit.  (Measured
+// at 2048 units of 256 modes and 384 nodes: 64 x 64 tiles leave most CUs with one or two
+// waves per SIMD; 32 x 32 tiles take the projections from 55.8 to 38.9 us and the
+// lagged-state product from 42 to 23 us, the same sums bit for bit; 32 x 64, 64 x 32 and
+// 64-row chunks were slower.)  An output element is a fixed-order sum over
 // its own row only, so a unit's values do not depend on the other units of the launch.
 #include "l1pr_internal.h"
 
@@ -17,7 +21,7 @@ namespace l1pr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int GT = 64;   // units and columns per work-group tile
+constexpr int GT = 32;   // units and columns per work-group tile
 constexpr int GK = 32;   // reduction chunk
 
 // Row pointer of the lagged state of unit u.
@@ -26,24 +30,25 @@ __device__ inline const double* lag_row(const Tables& tb, const StepArgs& a, int
   return v.y + (long)v.L * tb.Mp;
 }
 
-// C[u][n] = sum_k Arow(u)[k] * B[k][n] for a 64 x 64 tile; returns the accumulators.
+// C[u][n] = sum_k Arow(u)[k] * B[k][n] for a TU x TN tile; returns the accumulators.
 // A rows come from `rowp(u)` (nullptr rows read as zero), B is [K][ldb] row-major.  The
 // reduction runs in chunks of GK rows through LDS; each thread holds its share of the next
 // chunk in registers, loaded from global memory while the current chunk's MFMAs run.  Entries
 // past K are zeros.  The k-steps of 4 are accumulated in ascending order whatever GK is.
-template <class RowFn>
+template <int TU, int TN, class RowFn>
 __device__ inline void tile_gemm(RowFn rowp, int units, int u0, int n0, int K, const double* B,
-                                 int ldb, int ncols, d4 (&acc)[2][2], double (*sA)[GK + 1],
-                                 double (*sB)[GT + 1]) {
+                                 int ldb, int ncols, d4 (&acc)[TU / 32][TN / 32],
+                                 double (*sA)[GK + 1], double (*sB)[TN + 1]) {
+  constexpr int FA = TU / 32, FB = TN / 32;  // MFMA tiles per wave in each direction
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  // this thread's entries of a chunk: A rows ar + 8i at column ak, B rows bk + 4i at column bc
-  constexpr int NA = GT * GK / 256, NB = GK * GT / 256;
-  const int ar = tid / GK, ak = tid % GK, bk = tid / GT, bc = tid % GT;
+    for (int b = 0; b < FB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  // this thread's entries of a chunk: A rows ar + (256/GK) i at column ak, B rows bk + (256/TN) i at column bc
+  constexpr int NA = TU * GK / 256, NB = GK * TN / 256;
+  const int ar = tid / GK, ak = tid % GK, bk = tid / TN, bc = tid % TN;
   const double* arow[NA];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
@@ -57,7 +62,7 @@ __device__ inline void tile_gemm(RowFn rowp, int units, int u0, int n0, int K, c
     for (int i = 0; i < NA; ++i) ra[i] = (arow[i] && k0 + ak < K) ? arow[i][k0 + ak] : 0.0;
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int kk = k0 + bk + (256 / GT) * i;
+      const int kk = k0 + bk + (256 / TN) * i;
       rb[i] = (bok && kk < K) ? B[(long)kk * ldb + n0 + bc] : 0.0;
     }
   };
@@ -66,51 +71,52 @@ __device__ inline void tile_gemm(RowFn rowp, int units, int u0, int n0, int K, c
 #pragma unroll
     for (int i = 0; i < NA; ++i) sA[ar + (256 / GK) * i][ak] = ra[i];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) sB[bk + (256 / GT) * i][bc] = rb[i];
+    for (int i = 0; i < NB; ++i) sB[bk + (256 / TN) * i][bc] = rb[i];
     __syncthreads();
     if (k0 + GK < K) load(k0 + GK);
 #pragma unroll
     for (int ks = 0; ks < GK / 4; ++ks) {
       const int kq = ks * 4 + (lane >> 4);
-      double af[2], bf[2];
+      double af[FA], bf[FB];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = sA[wi * 32 + a * 16 + (lane & 15)][kq];
+      for (int a = 0; a < FA; ++a) af[a] = sA[wi * (TU / 2) + a * 16 + (lane & 15)][kq];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = sB[kq][wj * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < FB; ++b) bf[b] = sB[kq][wj * (TN / 2) + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
 }
 
-// grid: (ceil(Qp / 64), ceil(units / 64))
+// grid: (ceil(Qp / TN), ceil(units / TU))
+template <int TU, int TN>
 __global__ __launch_bounds__(256) void k_lag_gemm1d(Tables tb, StepArgs a, int units, double* dq,
                                                     double* gq) {
-  __shared__ double sA[GT][GK + 1];
-  __shared__ double sB[GK][GT + 1];
-  const int n0 = blockIdx.x * GT, u0 = blockIdx.y * GT;
-  d4 acc[2][2];
-  tile_gemm([&](int u) { return lag_row(tb, a, u); }, units, u0, n0, tb.Mp, tb.phiT, tb.Qp,
+  __shared__ double sA[TU][GK + 1];
+  __shared__ double sB[GK][TN + 1];
+  const int n0 = blockIdx.x * TN, u0 = blockIdx.y * TU;
+  d4 acc[TU / 32][TN / 32];
+  tile_gemm<TU, TN>([&](int u) { return lag_row(tb, a, u); }, units, u0, n0, tb.Mp, tb.phiT, tb.Qp,
             tb.Qp, acc, sA, sB);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
 #pragma unroll
-  for (int ai = 0; ai < 2; ++ai)
+  for (int ai = 0; ai < TU / 32; ++ai)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int u = u0 + wi * 32 + ai * 16 + (lane >> 4) + 4 * e;
+      const int u = u0 + wi * (TU / 2) + ai * 16 + (lane >> 4) + 4 * e;
       if (u >= units) continue;
       const UnitView v = decode_unit(tb, a, u);
       const double* ins = tb.inst + (long)v.b * NSCAL;
       const double tD = t_level(tb, v.m_prev, v.Nb);
       const double tf = tb.source_time ? t_level(tb, v.m_src, v.Nb) : tD;
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        const int q = n0 + wj * 32 + bj * 16 + (lane & 15);
+      for (int bj = 0; bj < TN / 32; ++bj) {
+        const int q = n0 + wj * (TN / 2) + bj * 16 + (lane & 15);
         if (q >= tb.Qp) continue;
         const double uq = acc[ai][bj][e];
         const double w = tb.wq[q];
@@ -120,15 +126,16 @@ __global__ __launch_bounds__(256) void k_lag_gemm1d(Tables tb, StepArgs a, int u
     }
 }
 
-// grid: (ceil(max(Jm, Mp) / 64), ceil(units / 64), 2); z = 0: moments (skipped when m is
+// grid: (ceil(max(Jm, Mp) / TN), ceil(units / TU), 2); z = 0: moments (skipped when m is
 // nullptr), z = 1: load vector.
+template <int TU, int TN>
 __global__ __launch_bounds__(256) void k_proj_gemm1d(Tables tb, int units, const double* dq,
                                                      const double* gq, double* m, int Jm,
                                                      double* F) {
-  __shared__ double sA[GT][GK + 1];
-  __shared__ double sB[GK][GT + 1];
+  __shared__ double sA[TU][GK + 1];
+  __shared__ double sB[GK][TN + 1];
   const int which = blockIdx.z;
-  const int n0 = blockIdx.x * GT, u0 = blockIdx.y * GT;
+  const int n0 = blockIdx.x * TN, u0 = blockIdx.y * TU;
   const int ncols = which == 0 ? Jm : tb.Mp;
   if (which == 0 && m == nullptr) return;
   if (n0 >= ncols) return;
@@ -136,20 +143,20 @@ __global__ __launch_bounds__(256) void k_proj_gemm1d(Tables tb, int units, const
   const double* B = which == 0 ? tb.cosq : tb.phi;
   const int ldb = which == 0 ? Jm : tb.Mp;
   double* out = which == 0 ? m : F;
-  d4 acc[2][2];
-  tile_gemm([&](int u) { return Ain + (long)u * tb.Qp; }, units, u0, n0, tb.Qp, B, ldb, ncols,
-            acc, sA, sB);
+  d4 acc[TU / 32][TN / 32];
+  tile_gemm<TU, TN>([&](int u) { return Ain + (long)u * tb.Qp; }, units, u0, n0, tb.Qp, B, ldb,
+                    ncols, acc, sA, sB);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = wave >> 1, wj = wave & 1;
 #pragma unroll
-  for (int ai = 0; ai < 2; ++ai)
+  for (int ai = 0; ai < TU / 32; ++ai)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int u = u0 + wi * 32 + ai * 16 + (lane >> 4) + 4 * e;
+      const int u = u0 + wi * (TU / 2) + ai * 16 + (lane >> 4) + 4 * e;
       if (u >= units) continue;
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        const int c = n0 + wj * 32 + bj * 16 + (lane & 15);
+      for (int bj = 0; bj < TN / 32; ++bj) {
+        const int c = n0 + wj * (TN / 2) + bj * 16 + (lane & 15);
         if (c < ncols) out[(long)u * ncols + c] = acc[ai][bj][e];
       }
     }
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(256) void k_history1d(Tables tb, StepArgs a, double
 }
 
 // ------------------------------------------------------------------ skinny variants
-// For launches with few units (the coarse steps: one unit per instance) the 64 x 64 tiles
+// For launches with few units (the coarse steps: one unit per instance) the 32 x 32 tiles
 // leave most of the chip idle and expose every load's latency.  These variants give each
 // work-group one 16 x 16 output tile and cut the reduction into 32-wide chunks: lane group q
 // of wave w owns chunk 4 (w + 4 i) + q, loads all of it before its first MFMA, and the four
@@ -302,7 +309,7 @@ hipError_t launch_lag_gemm(const Tables& tb, const StepArgs& a, int units, doubl
     k_lag_skinny1d<<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
   } else {
     dim3 grid((tb.Qp + GT - 1) / GT, (units + GT - 1) / GT);
-    k_lag_gemm1d<<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
+    k_lag_gemm1d<GT, GT><<<grid, 256, 0, s>>>(tb, a, units, dq, gq);
   }
   return hipGetLastError();
 }
@@ -316,7 +323,7 @@ hipError_t launch_proj_gemm(const Tables& tb, int units, const double* dq, const
     k_proj_skinny1d<<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
   } else {
     dim3 grid((nc + GT - 1) / GT, (units + GT - 1) / GT, 2);
-    k_proj_gemm1d<<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
+    k_proj_gemm1d<GT, GT><<<grid, 256, 0, s>>>(tb, units, dq, gq, m, Jm, F);
   }
   return hipGetLastError();
 }

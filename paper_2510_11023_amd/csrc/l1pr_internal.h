@@ -28,7 +28,7 @@ enum { IS_ALPHA = 0, IS_TAU, IS_TAUC, IS_SFAC, IS_G1A, IS_G3A, IS_MB, IS_SB, NSC
 
 // tuning bits (l1pr_problem.tune): GEMM variant of the lagged-state product and of the
 // projections in fine and full-history steps
-enum { TUNE_LAG_TILED = 1, TUNE_PROJ_SKINNY = 2, TUNE_NB128 = 4, TUNE_TRAIL64 = 8 };
+enum { TUNE_LAG_SKINNY = 1, TUNE_PROJ_SKINNY = 2, TUNE_NB128 = 4, TUNE_TRAIL64 = 8 };
 
 // kinds of step
 enum { MODE_FINE = 0, MODE_COARSE = 1, MODE_FULL = 2 };
@@ -383,7 +383,7 @@ hipError_t launch_blk_diag(const Tables& tb, const StepArgs& a, int units, doubl
 hipError_t launch_blk_refine1d(const Tables& tb, const StepArgs& a, const Epilogue& e, int units,
                                double* q, const double* rhs0, double* xs, hipStream_t s);
 bool reg_path_ok(int Mp, int Qp);
-// skinny: 16 x 16 tiles with a split reduction (few units) instead of 64 x 64 tiles.  Both
+// skinny: 16 x 16 tiles with a split reduction (few units) instead of 32 x 32 tiles.  Both
 // give every output as a fixed-order sum over its own row, but the two orders differ, so
 // every step whose result must match another run bit for bit (the fine steps of a serial
 // solve and of a parareal sweep) has to use the same variant.
