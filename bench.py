@@ -69,7 +69,7 @@ TARGET = 1e-8
 # the counters' reading for a plain copy of known size (fetch and write factors below).
 # Valid only for the kernel sources with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "1b8503eea024e276a1b139696f022de3cb736993b568d21419d358e1f8016fcf",
+TRAFFIC_RECORD = {"sha256": "4aa1a04b5ff014a8140b675f4557e8a2f4efa7c4938eab6a18a5e63e9e0235d0",
                   "fetch_kib": 8710.5, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": int((2 * 8710.5 + 4096) * 1024)}
 
