@@ -206,6 +206,27 @@ def test_deterministic_and_batch_independent(gpu):
     assert torch.equal(Ra[1], Rb[0])
 
 
+@pytest.mark.parametrize("tune", [0, 1, 2, 3])
+def test_batch_independent_across_gemm_tiles(gpu, tune):
+    """The batched GEMMs tile 32 units x 32 columns (or 16 x 16 split-K tiles, tune bits 0 and
+    1): 37 instances make 37 serial units and 222 fine units per sweep, several unit tiles with
+    a partial last one, and Mp = 48, Qp = 80 and 97 moments leave partial column tiles and
+    reduction chunks.
+    Every instance's result must equal its own single-instance run bit for bit, in the serial
+    solve and in a parareal sweep."""
+    kw = W.with_(W.C2, modes=40, quad=66, steps=36, slices=6, alpha=0.45)
+    print(f"[parity] gemm tiles tune={tune}", flush=True)
+    pg = gpu.make_problem(tune=tune, **kw)
+    u0 = W.u0_batch_1d(40, range(70, 107))
+    Ua, _ = gpu.solve_serial(pg, dev(u0))
+    Ra = gpu.solve_parareal(pg, dev(u0), 2, tol=0.0).U
+    for b in (0, 17, 31, 32, 36):
+        U1, _ = gpu.solve_serial(pg, dev(u0[b:b + 1]))
+        assert torch.equal(U1[0], Ua[b]), b
+        R1 = gpu.solve_parareal(pg, dev(u0[b:b + 1]), 2, tol=0.0).U
+        assert torch.equal(R1[0], Ra[b]), b
+
+
 def test_invalid_arguments_rejected(gpu):
     from paper_2510_11023_amd import _lib
 
