@@ -67,11 +67,12 @@ TARGET = 1e-8
 # HBM traffic of the fine-sweep factor-and-solve kernel, per full launch (2048 units), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE on `python bench.py --mode kernels`, divided by
 # the counters' reading for a plain copy of known size (fetch and write factors below).
-# Valid only for the kernel sources with this hash.
-TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h")
-TRAFFIC_RECORD = {"sha256": "4aa1a04b5ff014a8140b675f4557e8a2f4efa7c4938eab6a18a5e63e9e0235d0",
-                  "fetch_kib": 8710.5, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
-                  "bytes_per_launch": int((2 * 8710.5 + 4096) * 1024)}
+# Valid only for the kernel sources and build flags with this hash.
+TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h",
+                   "paper_2510_11023_amd/build.py")
+TRAFFIC_RECORD = {"sha256": "483ffea63ef65febecb3681c00724c517cc49632a97ac5b40e5e6536177d5db0",
+                  "fetch_kib": 8721.5, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
+                  "bytes_per_launch": int((2 * 8721.5 + 4096) * 1024)}
 
 
 def log(msg):
