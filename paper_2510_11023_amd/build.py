@@ -27,14 +27,19 @@ FLAGS = [
 ]
 
 
-# Per-file additions.  The register-resident factor kernel is bound by its per-unit dependency
-# chain, and the scheduler's iterative ILP strategy orders it better: 666 -> 646 us per
-# 2048-unit launch at M = 256, the same results bit for bit (the default, max-ILP,
-# memory-clause, min-register and max-occupancy strategies were measured too).  Only this
-# file: the compiler fails on the blocked-factorisation source with it, and the other kernels
-# were not measured with it.
+# Per-file scheduling strategies, each the fastest of the default, max-ILP, memory-clause and
+# the iterative ILP, min-register and max-occupancy strategies on its own workload, with the
+# same results bit for bit:
+# - the register-resident factor kernel, bound by its per-unit dependency chain: iterative ILP,
+#   666 -> 646 us per 2048-unit launch at M = 256;
+# - the blocked factorisation through device memory: iterative max-occupancy, 1384 -> 1328 ms
+#   for the 2D fine sweep of 128 systems of 4096 coefficients (the compiler fails on this file
+#   with the iterative ILP strategy).
+# The other sources keep the default (measured on the GEMMs and the 2D conjugate gradients:
+# within 2%).
 FILE_FLAGS = {
     "step1d_reg.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "chol_blk.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"],
 }
 
 
