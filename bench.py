@@ -70,7 +70,7 @@ TARGET = 1e-8
 # Valid only for the kernel sources and build flags with this hash.
 TRAFFIC_SOURCES = ("paper_2510_11023_amd/csrc/step1d_reg.hip", "paper_2510_11023_amd/csrc/l1pr_internal.h",
                    "paper_2510_11023_amd/build.py")
-TRAFFIC_RECORD = {"sha256": "e3f16b01005daa4e38a344d9d4a739361777537ad28f1fb1dd40de33747d95bb",
+TRAFFIC_RECORD = {"sha256": "b2229fb70e4db912dd049b76d91d20f06c8d8463067e94761883de4c68135b6e",
                   "fetch_kib": 8721.5, "write_kib": 4096, "fetch_factor": 2.0, "write_factor": 1.0,
                   "bytes_per_launch": int((2 * 8721.5 + 4096) * 1024)}
 

@@ -35,8 +35,8 @@ FLAGS = [
 # - the blocked factorisation through device memory: iterative max-occupancy, 1384 -> 1328 ms
 #   for the 2D fine sweep of 128 systems of 4096 coefficients (the compiler fails on this file
 #   with the iterative ILP strategy).
-# The other sources keep the default (measured on the GEMMs and the 2D conjugate gradients:
-# within 2%).
+# The other sources keep the default (measured on the 1D GEMMs and history sums, the 2D
+# conjugate gradients, the full-history prefix sums and the MLP: within 2%).
 FILE_FLAGS = {
     "step1d_reg.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
     "chol_blk.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-maxocc"],
